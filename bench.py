@@ -1,0 +1,171 @@
+"""Benchmark: MLUPS of the fused reactive-mixture LBM step on one MI355X.
+
+A "step" is one time step of the whole hot path (advection, boundaries,
+moments, gradients, Stefan-Maxwell, reaction sub-steps, collision of all M+1
+stored lattices) over the whole lattice.  Default workload: the 3D channel
+512x64x64 with the 9-species / 21-reaction synthetic mechanism, TMS walls on
+the four side faces, flux inlet and LODI outlet, FP32 deviation storage with
+FP64 arithmetic; the same workload in FP64 storage is measured beside it.
+
+Prints one JSON line.  Inputs are resident in HBM before the timed region.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_traffic.json")
+
+
+def _kernel_hash():
+    h = hashlib.sha256()
+    for f in ("physics.hpp", "kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2108_07605_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(storage):
+    """HBM bytes per collide launch from committed rocprofv3 counter runs, or
+    None when absent or taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != _kernel_hash():
+        return None
+    rec = t.get(storage)
+    return None if rec is None else rec.get("bytes_per_launch")
+
+
+def _time_storage(case, storage, steps, warmup):
+    import torch
+    from paper_2108_07605_amd import rlbm
+    lat = rlbm.Lattice(case, storage=storage)
+    lat.set_state()
+    stream = lat.stream
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    # per-kernel durations: HIP events around every launch on the lattice stream
+    lat.set_timing(True)
+    lat.step(steps)
+    kt = lat.kernel_times()
+    lat.set_timing(False)
+    inv = lat.invariants()
+    ok = inv[-1] == 0.0
+    del lat
+    torch.cuda.empty_cache()
+    return {"ms_total": ms, "wall_s": wall, "kernels": kt, "finite": bool(ok)}
+
+
+def _cpu_baseline(budget_s=20.0):
+    """The oracle, as it stands, on a bounded sample of the same workload: a
+    64x16x16 channel with the same mechanism and boundaries, stepped until
+    about budget_s of CPU time."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from oracle import Oracle
+    from paper_2108_07605_amd import workloads as wl
+    case = wl.make_case("channel3d", nx=64, ny=16, nz=16)
+    o = Oracle(case)
+    o.step(1)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < budget_s:
+        o.step(1)
+        n += 1
+    dt = time.perf_counter() - t0
+    N = case["nx"] * case["ny"] * case["nz"]
+    return {"value": N * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"channel3d 64x16x16 (16384 nodes), same mechanism and boundaries, "
+                      f"{n} steps in {dt:.1f} s, FP64 NumPy, 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--nx", type=int, default=512)
+    ap.add_argument("--ny", type=int, default=64)
+    ap.add_argument("--nz", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--storage", default="both", choices=["both", "f32dev", "f64"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding note in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2108_07605_amd import workloads as wl
+    torch.cuda.set_device(0)
+    case = wl.make_case("channel3d", nx=args.nx, ny=args.ny, nz=args.nz)
+    N = case["nx"] * case["ny"] * case["nz"]
+    M = case["mech"]["M"]
+    L = M + 1
+    res = {}
+    storages = ["f32dev", "f64"] if args.storage == "both" else [args.storage]
+    for st in storages:
+        r = _time_storage(case, st, args.steps, args.warmup)
+        s = 4 if st == "f32dev" else 8
+        bytes_node = 2 * L * 27 * s                      # populations read + written once
+        ms_step = r["ms_total"] / args.steps
+        mlups = N / (ms_step * 1e-3) / 1e6
+        coll_ms, coll_n = r["kernels"]["collide"]
+        coll_avg = coll_ms / max(coll_n, 1)
+        achieved = bytes_node * N / (coll_avg * 1e-3) / 1e9
+        traffic = _traffic(st)
+        res[st] = {
+            "mlups": mlups, "ms_per_step": ms_step, "finite": r["finite"],
+            "kernels_ms_avg": {k: v[0] / max(v[1], 1) for k, v in r["kernels"].items()},
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": traffic,
+                         "kernel": "k_collide", "alg_bytes_per_node": bytes_node},
+            "step_frac_of_hbm_roofline": mlups * 1e6 * bytes_node / (HBM_PEAK_GBS * 1e9),
+        }
+    main_st = storages[0]
+    m = res[main_st]
+    out = {
+        "metric": "MLUPS (all M+2 LBEs) + % HBM roofline, FP32-store vs FP64; p50/p99 solve latency",
+        "value": m["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"channel3d {case['nx']}x{case['ny']}x{case['nz']}, 9 species / "
+                               f"{len(case['mech']['lnA'])} reversible reactions, TMS walls on y/z, "
+                               f"flux inlet, LODI outlet, {main_st} storage",
+                   "nodes": N, "storage": main_st, "species": M, "substeps": case["substeps"]},
+        "roofline": m["roofline"],
+        "storages": res,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline(args.cpu_budget)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * rlbm.h -- C ABI of the reactive-mixture lattice Boltzmann library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library advances the M+2 coupled lattice Boltzmann equations of
+ * Sawant, Dorschner & Karlin, "Consistent lattice Boltzmann model for reactive
+ * mixtures" (arXiv 2108.07605) on the D3Q27 lattice: M species equations with
+ * Stefan-Maxwell diffusion and mass-action reaction sources (section 2), the
+ * mixture momentum lattice f with the extended equilibrium and the energy
+ * lattice g whose energy includes the energy of formation (section 3), with
+ * the M-th (slaved) species implied by f - sum_a f_a (section 3.6, eq.
+ * strongest), and the wall, inlet and outlet constructions of section 4.
+ *
+ * Conventions
+ *  - Lattice units: dt = dx = 1; temperatures in kelvin.
+ *  - Nodes are numbered n = (z * ny + y) * nx + x (x fastest).  Fields are
+ *    structure-of-arrays: u is [3][N], Y is [M][N].
+ *  - Discrete velocities: i = 9 (c_z + 1) + 3 (c_y + 1) + (c_x + 1); the rest
+ *    velocity is i = 13 and the opposite of i is 26 - i.
+ *  - Population buffers exchanged through this ABI are FP64, ordered
+ *    [L][27][N] with L = M + 1 stored lattices: the M - 1 unslaved species in
+ *    ascending species index, then f, then g.
+ *  - Every call returns 0 on success or a negative RLBM_E* code; the message
+ *    of the last failure on the calling thread is rlbm_last_error().  No call
+ *    aborts or throws.
+ *  - Pointers flagged on_device refer to device memory of the lattice's GPU;
+ *    otherwise to host memory.  The library never frees caller memory.
+ *  - Calls on one lattice must not overlap from several threads.
+ */
+#ifndef RLBM_H
+#define RLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RLBM_OK 0
+#define RLBM_EINVAL (-1)      /* invalid argument (dims, faces, species, state) */
+#define RLBM_ENOSPC (-2)      /* caller buffer smaller than rlbm_lattice_bytes */
+#define RLBM_EHIP (-3)        /* a HIP runtime call failed */
+#define RLBM_EUNSUP (-4)      /* valid but unsupported configuration */
+#define RLBM_ENONFINITE (-5)  /* state contains NaN/Inf or non-positive density */
+
+#define RLBM_MAX_SPECIES 12
+#define RLBM_MAX_REACTIONS 64
+#define RLBM_MAX_ELEMENTS 8
+
+/* Mechanism: species thermochemistry, reactions and transport, all in
+ * lattice units (section 3.6: the paper obtains these from a kinetics
+ * package; here they are inputs).
+ *
+ * Thermo (one NASA-7 range per species, T in kelvin, R_a = R_univ/m_a):
+ *   C_{a,p}/R_a = a0 + a1 T + a2 T^2 + a3 T^3 + a4 T^4
+ *   H_a/(R_a T) = a0 + a1 T/2 + a2 T^2/3 + a3 T^3/4 + a4 T^4/5 + a5/T
+ *   S_a/R_a     = a0 ln T + a1 T + a2 T^2/2 + a3 T^3/3 + a4 T^4/4 + a6
+ *   U_a = H_a - R_a T  (eqs. specUa, specHa with the Mayer relation)
+ * Reactions (mass action, production rates of section 2.3):
+ *   c_b = max(rho_b, 0)/m_b,  k_f = exp(lnA) T^beta exp(-Ta/T),
+ *   K_c = exp(-sum_a dnu_a g_a/(R_univ T)) (exp(ln_cstd)/T)^(sum_a dnu_a),
+ *   q = k_f prod c^nu_f - reversible * k_f/K_c prod c^nu_r,
+ *   rho_dot_a = m_a sum_r (nu_r - nu_f)_ar q_r.
+ * Transport (synthetic laws standing in for mixture-averaged transport):
+ *   mu = mu_ref (T/T_ref)^mu_exp, lambda = mu C_p / Pr,
+ *   D_ab = D_ref[a][b] (T/T_ref)^D_exp (P_ref/P),
+ *   1/tau_ab = m R_univ T / (D_ab m_a m_b)    (section 2.3, eqs. betaa, taua)
+ * The library copies everything; the caller may free the descriptor after
+ * rlbm_mech_create returns. */
+typedef struct rlbm_mech_desc {
+    int32_t M;                    /* species, 2..RLBM_MAX_SPECIES */
+    int32_t R;                    /* reactions, 0..RLBM_MAX_REACTIONS */
+    int32_t E;                    /* elements, 0..RLBM_MAX_ELEMENTS */
+    const double* molar_mass;     /* [M] > 0 */
+    const double* nasa;           /* [M][7] */
+    const int32_t* composition;   /* [M][E] atoms per molecule (invariants); NULL if E = 0 */
+    double R_univ;                /* universal gas constant > 0 */
+    double ln_cstd;               /* standard concentration c_std(T) = exp(ln_cstd)/T */
+    const int32_t* nu_f;          /* [R][M] reactant coefficients, 0..3 */
+    const int32_t* nu_r;          /* [R][M] product coefficients, 0..3 */
+    const double* lnA;            /* [R] */
+    const double* beta;           /* [R] */
+    const double* Ta;             /* [R] activation temperatures Ea/R (K) */
+    const int32_t* reversible;    /* [R] 0 or 1 */
+    double T_ref, P_ref;          /* transport reference state */
+    double mu_ref, mu_exp, Pr;    /* viscosity law and Prandtl number */
+    double D_exp;                 /* exponent of the diffusivity law */
+    const double* D_ref;          /* [M][M] symmetric, > 0 off the diagonal */
+} rlbm_mech_desc;
+
+typedef struct rlbm_mech rlbm_mech;
+typedef struct rlbm_lattice rlbm_lattice;
+
+#define RLBM_FACE_PERIODIC 0
+#define RLBM_FACE_WALL 1      /* Tamm-Mott-Smith isothermal no-slip wall (section 4.2.2) */
+#define RLBM_FACE_INLET 2     /* flux inlet (section 4.3); x- face only */
+#define RLBM_FACE_OUTLET 3    /* LODI + convective outlet (section 4.4); x+ face only */
+
+/* One face of the box.  Faces are ordered x-, x+, y-, y+, z-, z+.  An axis is
+ * periodic on both faces or on neither.  A node on several non-periodic faces
+ * takes the union of their incoming links; wall faces take precedence over
+ * the inlet and the outlet at such nodes. */
+typedef struct rlbm_face {
+    int32_t type;
+    /* WALL: target temperature at node x,
+     *   T_w(x) = T_lo + (T_hi - T_lo) (1 + tanh((x - x0)/width)) / 2,
+     * target velocity 0 (impermeable, stationary). */
+    double T_lo, T_hi, x0, width;
+    /* INLET: imposed density, normal velocity (+x), temperature and mass
+     * fractions of the incoming mixture (its mass flux is rho_in * u_in). */
+    double rho_in, u_in, T_in;
+    const double* Y_in;           /* [M], copied at rlbm_lattice_create */
+    /* OUTLET: far-field pressure and relaxation factor of the partially
+     * non-reflecting LODI condition, L1 = sigma (1 - Ma^2) c / nx (P - P_inf). */
+    double P_inf, sigma;
+} rlbm_face;
+
+#define RLBM_STORAGE_F64 0        /* populations stored in FP64 */
+#define RLBM_STORAGE_F32_DEV 1    /* FP32 deviations from a per-(lattice, velocity) reference */
+
+typedef struct rlbm_lattice_desc {
+    int32_t nx, ny, nz;           /* >= 1 each; >= 2 along an axis with an inlet/outlet */
+    rlbm_face faces[6];
+    int32_t storage;              /* RLBM_STORAGE_* */
+    int32_t substeps;             /* reaction sub-steps l >= 1 (eq. R3) */
+    int32_t slaved;               /* slaved species index, or -1: chosen at rlbm_set_state as
+                                     the largest domain-mean mass fraction (lowest index on ties) */
+} rlbm_lattice_desc;
+
+/* Create / destroy a mechanism (host object; uploaded per lattice). */
+int rlbm_mech_create(const rlbm_mech_desc* desc, rlbm_mech** out);
+void rlbm_mech_destroy(rlbm_mech* mech);
+
+/* Exact number of device bytes a lattice needs: two population buffers,
+ * per-node auxiliary fields, interface-node tables and scratch. */
+int rlbm_lattice_bytes(const rlbm_lattice_desc* desc, const rlbm_mech* mech, size_t* bytes);
+
+/* Create a lattice in caller-owned device memory `dev_mem` of `bytes` bytes
+ * (256-byte aligned), which must stay valid until rlbm_lattice_destroy.
+ * `stream` is a hipStream_t (NULL = default stream) on which all work of
+ * this lattice is enqueued; it is borrowed, not owned.  The device is the
+ * current device at creation.  Synchronous (uploads tables). */
+int rlbm_lattice_create(const rlbm_lattice_desc* desc, const rlbm_mech* mech, void* dev_mem,
+                        size_t bytes, void* stream, rlbm_lattice** out);
+void rlbm_lattice_destroy(rlbm_lattice* lat);
+
+/* Set the state to the equilibria at the given fields (rho > 0, T > 0,
+ * sum_a Y_a = 1): species f_a^eq, mixture f^eq and energy g^eq (sections 2.2,
+ * 3.2, 3.3).  rho [N], u [3][N], T [N], Y [M][N].  Resets the outlet state
+ * and, in FP32 storage, fixes the reference populations at the domain-mean
+ * state.  Host inputs are copied synchronously; device inputs are read on the
+ * lattice stream. */
+int rlbm_set_state(rlbm_lattice* lat, const double* rho, const double* u, const double* T,
+                   const double* Y, int on_device);
+
+/* Enqueue n time steps (stream, boundaries, moments, gradients, collision)
+ * on the lattice stream and return; n = 0 is a no-op. */
+int rlbm_step(rlbm_lattice* lat, int64_t n);
+
+/* Macroscopic fields of the current (post-collision) populations: rho [N],
+ * u [3][N], T [N], Y [M][N], P [N]; any pointer may be NULL.  With on_device =
+ * 0 the call synchronises the stream and copies to host. */
+int rlbm_read_fields(rlbm_lattice* lat, double* rho, double* u, double* T, double* Y, double* P,
+                     int on_device);
+
+/* FP64 copies of all stored populations, [L][27][N] (checkpoint/resume and
+ * parity).  Writing re-encodes into the lattice's storage format. */
+int rlbm_read_populations(rlbm_lattice* lat, double* buf, int on_device);
+int rlbm_write_populations(rlbm_lattice* lat, const double* buf, int on_device);
+
+/* Global invariants of the current populations into host array out[n_out]:
+ * [0] sum rho, [1..3] sum rho u, [4] sum rho E, [5..5+E) element totals
+ * (moles), [5+E] 1 if any population is non-finite else 0.  Needs
+ * n_out >= 6 + E.  Synchronises the stream. */
+int rlbm_invariants(rlbm_lattice* lat, double* out, int n_out);
+
+/* Number of stored lattices L, nodes N and interface nodes. */
+int rlbm_lattice_shape(const rlbm_lattice* lat, int32_t* L, int64_t* N, int64_t* n_interface,
+                       int32_t* slaved);
+
+/* Per-kernel timing with HIP events recorded on the lattice stream around
+ * every launch while enabled.  rlbm_kernel_times synchronises and returns,
+ * for kernel k in {0: boundary, 1: moments, 2: collide}, the accumulated
+ * milliseconds ms[k] and launch counts counts[k] since the last reset. */
+int rlbm_set_timing(rlbm_lattice* lat, int enable);
+int rlbm_kernel_times(rlbm_lattice* lat, double* ms, int64_t* counts, int n);
+
+/* Batches of independent lattices advanced together.  Each kernel phase of a
+ * step is one launch over the flattened (lattice, node-block) work list, so
+ * small and uneven instances share the GPU.  All lattices of a batch must be
+ * on the same device, use the same species count and storage format, and are
+ * advanced on the stream of the first one.  A batch step is equivalent, bit
+ * for bit, to rlbm_step on each lattice.  The batch keeps its tables in the
+ * caller-owned device memory dev_mem of rlbm_batch_bytes(k) bytes. */
+typedef struct rlbm_batch rlbm_batch;
+int rlbm_batch_bytes(int32_t k, size_t* bytes);
+int rlbm_batch_create(rlbm_lattice* const* lats, int32_t k, void* dev_mem, size_t bytes,
+                      rlbm_batch** out);
+/* Advance lattice j by steps[j] >= 0 steps (all lattices share the launches;
+ * a lattice drops out once its steps are done).  Asynchronous. */
+int rlbm_batch_step(rlbm_batch* batch, const int64_t* steps);
+void rlbm_batch_destroy(rlbm_batch* batch);
+
+const char* rlbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RLBM_H */

@@ -1,0 +1,36 @@
+// Kernel launchers shared by the host library (kernels.hip implements them).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "physics.hpp"
+
+namespace rlbm {
+
+// One launch of a step phase over a work list of n_lat lattices.
+struct StepLaunch {
+    const LatDev* lats;   // device table [n_lat]
+    const int* blk;       // device prefix of blocks per lattice [n_lat + 1]
+    int n_lat;
+    int blocks;           // total blocks (blk[n_lat])
+    long long t;          // step counter of this launch series
+    int* flag;            // device failure flag (temperature iteration)
+    hipStream_t stream;
+};
+
+// phase 0: boundary (64-thread blocks over interface nodes),
+// phase 1: moments, phase 2: collide (256-thread blocks over nodes).
+hipError_t launch_phase(int phase, int M, int storage, const StepLaunch& a);
+hipError_t launch_init(int M, int storage, const LatDev* lat, long long N, const double* rho, const double* u,
+                       const double* T, const double* Y, hipStream_t st);
+hipError_t launch_refs(int M, const LatDev* lat, double* ref, double rho, double T, const double* Y,
+                       hipStream_t st);
+hipError_t launch_fields(int M, int storage, const LatDev* lat, long long N, long long t, double* rho, double* u,
+                         double* T, double* Y, double* P, int* flag, hipStream_t st);
+hipError_t launch_pops(int storage, const LatDev* lat, long long N, int nl, long long t, double* buf, int write,
+                       hipStream_t st);
+hipError_t launch_invariants(int M, int storage, const LatDev* lat, long long N, long long t, double* partial,
+                             int nv, double* out, hipStream_t st);
+bool species_supported(int M);
+
+}  // namespace rlbm

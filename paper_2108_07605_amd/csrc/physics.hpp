@@ -1,0 +1,302 @@
+// Device-side physics of the reactive-mixture lattice Boltzmann step
+// (Sawant, Dorschner & Karlin, arXiv 2108.07605).  FP64 throughout; the
+// population storage format is decided in the kernels only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rlbm.h"
+
+namespace rlbm {
+
+constexpr int Q = 27;
+constexpr int MAXM = RLBM_MAX_SPECIES;
+constexpr int MAXR = RLBM_MAX_REACTIONS;
+constexpr int MAXE = RLBM_MAX_ELEMENTS;
+
+// D3Q27 velocity i = 9 (cz + 1) + 3 (cy + 1) + (cx + 1) (section 2.2, eq. d3q27vel).
+__host__ __device__ constexpr int cx_of(int i) { return i % 3 - 1; }
+__host__ __device__ constexpr int cy_of(int i) { return (i / 3) % 3 - 1; }
+__host__ __device__ constexpr int cz_of(int i) { return i / 9 - 1; }
+__host__ __device__ constexpr int c2_of(int i) {
+    return cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_of(i) * cz_of(i);
+}
+
+// Mechanism in the layout the kernels read (uniform addresses: scalar loads).
+struct MechDev {
+    int M, R, E, pad_;
+    double m[MAXM];             // molar masses
+    double inv_m[MAXM];
+    double Ra[MAXM];            // R_univ / m_a
+    double uc[MAXM][6];         // U_a(T) = sum_k uc[a][k] T^k
+    double cvc[MAXM][5];        // C_{a,v}(T) = sum_k cvc[a][k] T^k  (= dU_a/dT)
+    double nasa[MAXM][7];       // raw NASA-7 coefficients (Gibbs functions)
+    double R_univ, ln_cstd;
+    // reactions
+    double lnA[MAXR], beta[MAXR], Ta[MAXR], dnu_sum[MAXR];
+    int rev[MAXR];
+    int8_t nu_f[MAXR][MAXM], nu_r[MAXR][MAXM];
+    double dnu[MAXR][MAXM];
+    // transport
+    double T_ref, inv_T_ref, P_ref, inv_P_ref, mu_ref, mu_exp, inv_Pr, D_exp;
+    double Kab[MAXM][MAXM];     // 1 / (D_ref[a][b] m_a m_b)
+    double comp[MAXM][MAXE];    // element atoms per molecule (invariants)
+};
+
+// Per-lattice parameters (device resident, one entry per lattice of a batch).
+struct LatDev {
+    int nx, ny, nz, pad0;
+    int per[3];                 // periodic flags per axis
+    int slaved, substeps, storage;
+    long long N;
+    int n_if, n_out;
+    const MechDev* mech;
+    void* pop[2];               // ping-pong population buffers [L][27][N]
+    double* aux;                // [8 + M][N]: rho, ux, uy, uz, T, Phi_x,y,z, Y_0..Y_{M-1}
+    const int* if_index;        // [N]: interface slot or -1 (NULL if n_if == 0)
+    const int* if_node;         // [n_if]
+    const unsigned* if_mask;    // [n_if] incoming set D as a 27-bit mask
+    const int* if_type;         // [n_if] RLBM_FACE_WALL / INLET / OUTLET
+    const double* if_T;         // [n_if] wall target temperature
+    const int* if_out;          // [n_if] outlet slot or -1
+    double* bcbuf;              // [L * 27][n_if] post-boundary populations (FP64)
+    double* out_state;          // [5 + M][n_out]: rho, ux, uy, uz, T, Y
+    const double* ref;          // [L * 27] reference populations (FP32 storage)
+    double rho_in, u_in, T_in, P_inf, sigma;
+    double Y_in[MAXM];
+    int parity0;                // buffer holding the current populations at t = 0
+    int pad1;
+    long long t_end;            // batch: lattice active while t < t_end
+};
+
+constexpr int AUX_RHO = 0, AUX_U = 1, AUX_T = 4, AUX_PHI = 5, AUX_Y = 8;
+
+// ---------------------------------------------------------------------------
+// product form (section 2.2, eqs. phi0, phiPlus, phis, prod)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double psi(int c, double xi, double P) {
+    return c == 0 ? 1.0 - P : 0.5 * (c > 0 ? (xi + P) : (P - xi));
+}
+
+// Energy equilibrium of one velocity (section 3.3, eq. geq_i).  With
+// W_a = Psi_{c_a}(u_a, theta + u_a^2) the operator product form applied to
+// E = U + u^2/2 reduces, since O_b acts as multiplication by u_b on
+// functions independent of u_b, to
+//   g_i = rho [U Wx Wy Wz + kx Wy Wz + Wx ky Wz + Wx Wy kz],
+//   k_0(u) = u^2/2 - O^2[u^2/2],  k_{+-1}(u) = (+-O[u^2/2] + O^2[u^2/2]) / 2,
+//   O[u^2/2] = theta u + u^3/2,  O^2[u^2/2] = theta^2 + 5/2 theta u^2 + u^4/2.
+struct GeqAxis {
+    double W[3];   // c = -1, 0, +1
+    double k[3];
+};
+
+__device__ __forceinline__ void geq_axis(double u, double th, GeqAxis& a) {
+    const double u2 = u * u;
+    const double P = th + u2;
+    a.W[0] = 0.5 * (P - u);
+    a.W[1] = 1.0 - P;
+    a.W[2] = 0.5 * (P + u);
+    const double o1 = th * u + 0.5 * u2 * u;
+    const double o2 = th * th + 2.5 * th * u2 + 0.5 * u2 * u2;
+    a.k[0] = 0.5 * (o2 - o1);
+    a.k[1] = 0.5 * u2 - o2;
+    a.k[2] = 0.5 * (o2 + o1);
+}
+
+__device__ __forceinline__ double geq_i(int i, double rho, double U, const GeqAxis& X,
+                                        const GeqAxis& Yy, const GeqAxis& Z) {
+    const int a = cx_of(i) + 1, b = cy_of(i) + 1, c = cz_of(i) + 1;
+    const double wyz = Yy.W[b] * Z.W[c];
+    return rho * (U * X.W[a] * wyz + X.k[a] * wyz + X.W[a] * (Yy.k[b] * Z.W[c] + Yy.W[b] * Z.k[c]));
+}
+
+// ---------------------------------------------------------------------------
+// thermochemistry (section 3.1, eqs. specUa, U, temperature)
+// ---------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ double mix_inv_m(const MechDev& mc, const double* Y) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) s += Y[a] * mc.inv_m[a];
+    return s;
+}
+
+// Collapse sum_a Y_a U_a(T) into one quintic and solve for T by Newton.
+template <int M>
+__device__ __forceinline__ double solve_T(const MechDev& mc, const double* Y, double U,
+                                          double T, int* fail) {
+    double c[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) s += Y[a] * mc.uc[a][k];
+        c[k] = s;
+    }
+    c[0] -= U;
+    for (int it = 0; it < 100; ++it) {
+        const double F = c[0] + T * (c[1] + T * (c[2] + T * (c[3] + T * (c[4] + T * c[5]))));
+        const double dF = c[1] + T * (2.0 * c[2] + T * (3.0 * c[3] + T * (4.0 * c[4] + T * 5.0 * c[5])));
+        const double dT = F / dF;
+        T -= dT;
+        if (fabs(dT) <= 1e-12 * fabs(T)) return T;
+    }
+    *fail = 1;
+    return T;
+}
+
+template <int M>
+__device__ __forceinline__ double mix_U(const MechDev& mc, const double* Y, double T) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        const double* u = mc.uc[a];
+        s += Y[a] * (u[0] + T * (u[1] + T * (u[2] + T * (u[3] + T * (u[4] + T * u[5])))));
+    }
+    return s;
+}
+
+__device__ __forceinline__ double species_U(const MechDev& mc, int a, double T) {
+    const double* u = mc.uc[a];
+    return u[0] + T * (u[1] + T * (u[2] + T * (u[3] + T * (u[4] + T * u[5]))));
+}
+
+__device__ __forceinline__ double species_cv(const MechDev& mc, int a, double T) {
+    const double* c = mc.cvc[a];
+    return c[0] + T * (c[1] + T * (c[2] + T * (c[3] + T * c[4])));
+}
+
+// g_a/(R_univ T) = h/(R T) - s/R for one species.
+__device__ __forceinline__ double gibbs_RT(const MechDev& mc, int a, double T, double lnT) {
+    const double* n = mc.nasa[a];
+    const double h = n[0] + T * (n[1] * 0.5 + T * (n[2] * (1.0 / 3.0) + T * (n[3] * 0.25 + T * n[4] * 0.2))) +
+                     n[5] / T;
+    const double s = n[0] * lnT + T * (n[1] + T * (n[2] * 0.5 + T * (n[3] * (1.0 / 3.0) + T * n[4] * 0.25))) +
+                     n[6];
+    return h - s;
+}
+
+// ---------------------------------------------------------------------------
+// chemistry (section 2.3, eq. R3): production rates and sub-steps
+// ---------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ void production_rates(const MechDev& mc, const double* rho_a, double T,
+                                                 double* wdot) {
+#pragma unroll
+    for (int a = 0; a < M; ++a) wdot[a] = 0.0;
+    const int R = mc.R;
+    if (R == 0) return;
+    double conc[M], gRT[M];
+    const double lnT = log(T);
+    const double invT = 1.0 / T;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        conc[a] = fmax(rho_a[a], 0.0) * mc.inv_m[a];
+        gRT[a] = gibbs_RT(mc, a, T, lnT);
+    }
+    const double lnc = mc.ln_cstd - lnT;
+    for (int r = 0; r < R; ++r) {
+        const double lnkf = mc.lnA[r] + mc.beta[r] * lnT - mc.Ta[r] * invT;
+        double fwd = exp(lnkf);
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            const int n = mc.nu_f[r][a];
+            if (n >= 1) fwd *= conc[a];
+            if (n >= 2) fwd *= conc[a];
+            if (n >= 3) fwd *= conc[a];
+        }
+        double q = fwd;
+        if (mc.rev[r]) {
+            double sg = 0.0;
+#pragma unroll
+            for (int a = 0; a < M; ++a) sg += mc.dnu[r][a] * gRT[a];
+            const double lnKc = -sg + mc.dnu_sum[r] * lnc;
+            double bwd = exp(lnkf - lnKc);
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+                const int n = mc.nu_r[r][a];
+                if (n >= 1) bwd *= conc[a];
+                if (n >= 2) bwd *= conc[a];
+                if (n >= 3) bwd *= conc[a];
+            }
+            q -= bwd;
+        }
+#pragma unroll
+        for (int a = 0; a < M; ++a) wdot[a] += mc.dnu[r][a] * q;
+    }
+#pragma unroll
+    for (int a = 0; a < M; ++a) wdot[a] *= mc.m[a];
+}
+
+// Delta rho_a over one step by l forward-Euler sub-steps at frozen U.
+template <int M>
+__device__ __forceinline__ void reaction_increment(const MechDev& mc, const double* rho_a, double rho,
+                                                   double U, double T, int l, double* drho, int* fail) {
+    double cur[M], w[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) cur[a] = rho_a[a];
+    if (mc.R == 0) {
+#pragma unroll
+        for (int a = 0; a < M; ++a) drho[a] = 0.0;
+        return;
+    }
+    const double inv_l = 1.0 / (double)l;
+    const double inv_rho = 1.0 / rho;
+    double Ts = T;
+    for (int s = 0; s < l; ++s) {
+        if (s > 0) {
+            double Y[M];
+#pragma unroll
+            for (int a = 0; a < M; ++a) Y[a] = cur[a] * inv_rho;
+            Ts = solve_T<M>(mc, Y, U, Ts, fail);
+        }
+        production_rates<M>(mc, cur, Ts, w);
+#pragma unroll
+        for (int a = 0; a < M; ++a) cur[a] += w[a] * inv_l;
+    }
+#pragma unroll
+    for (int a = 0; a < M; ++a) drho[a] = cur[a] - rho_a[a];
+}
+
+// ---------------------------------------------------------------------------
+// Stefan-Maxwell system (section 2.3, eq. transform1), dt = 1:
+//   (1 + 1/(2 tau_a)) V_a - 1/2 sum_{b != a} Y_b V_b / tau_ab = u_a - u.
+// The matrix is strictly row diagonally dominant with margin 1 (its
+// off-diagonal row sums are -1/(2 tau_a)), so Gaussian elimination without
+// pivoting is stable.  Three right-hand sides (x, y, z) at once.
+// ---------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ void sm_solve(const double* Y, const double (*itab)[M], const double* inv_tau,
+                                         double (*rhs)[3]) {
+    double A[M][M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+#pragma unroll
+        for (int b = 0; b < M; ++b) A[a][b] = (a == b) ? 1.0 + 0.5 * inv_tau[a] : -0.5 * Y[b] * itab[a][b];
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const double inv = 1.0 / A[k][k];
+#pragma unroll
+        for (int a = k + 1; a < M; ++a) {
+            const double f = A[a][k] * inv;
+#pragma unroll
+            for (int b = k + 1; b < M; ++b) A[a][b] -= f * A[k][b];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) rhs[a][d] -= f * rhs[k][d];
+        }
+    }
+#pragma unroll
+    for (int k = M - 1; k >= 0; --k) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double s = rhs[k][d];
+#pragma unroll
+            for (int b = k + 1; b < M; ++b) s -= A[k][b] * rhs[b][d];
+            rhs[k][d] = s / A[k][k];
+        }
+    }
+}
+
+}  // namespace rlbm

@@ -1,0 +1,757 @@
+// Host side of the C ABI (include/rlbm.h): validation, device memory plan,
+// interface-node tables, launches and timing.  No exception crosses the ABI.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "physics.hpp"
+#include "rlbm.h"
+
+using namespace rlbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(RLBM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                       \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Plan {
+    size_t off_lat, off_mech, off_blk, off_flag, off_ref, off_pop0, off_pop1, off_aux, off_ifindex, off_ifnode,
+        off_ifmask, off_iftype, off_ifT, off_ifout, off_bcbuf, off_out, off_partial, off_invout, total;
+};
+
+struct Geometry {
+    long long N = 0;
+    std::vector<int> if_index, if_node, if_type, if_out;
+    std::vector<unsigned> if_mask;
+    std::vector<double> if_T;
+    int n_out = 0;
+};
+
+bool face_valid(int t) { return t >= RLBM_FACE_PERIODIC && t <= RLBM_FACE_OUTLET; }
+
+int validate_desc(const rlbm_lattice_desc* d, int M) {
+    if (!d) return fail(RLBM_EINVAL, "null lattice descriptor");
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(RLBM_EINVAL, "lattice dimensions must be >= 1");
+    if ((long long)d->nx * d->ny * d->nz > (1LL << 31) - 1)
+        return fail(RLBM_EUNSUP, "more than 2^31 - 1 nodes");
+    for (int f = 0; f < 6; ++f)
+        if (!face_valid(d->faces[f].type)) return fail(RLBM_EINVAL, "unknown face type");
+    const int n[3] = {d->nx, d->ny, d->nz};
+    for (int ax = 0; ax < 3; ++ax) {
+        const bool p0 = d->faces[2 * ax].type == RLBM_FACE_PERIODIC;
+        const bool p1 = d->faces[2 * ax + 1].type == RLBM_FACE_PERIODIC;
+        if (p0 != p1) return fail(RLBM_EINVAL, "an axis must be periodic on both faces or on neither");
+        if (!p0 && n[ax] < 2) return fail(RLBM_EINVAL, "a non-periodic axis needs at least 2 nodes");
+    }
+    for (int f = 0; f < 6; ++f) {
+        const rlbm_face& fc = d->faces[f];
+        if (fc.type == RLBM_FACE_INLET) {
+            if (f != 0) return fail(RLBM_EUNSUP, "inlets are supported on the x- face only");
+            if (!(fc.rho_in > 0) || !(fc.T_in > 0) || !fc.Y_in)
+                return fail(RLBM_EINVAL, "inlet needs rho_in > 0, T_in > 0 and Y_in");
+            double s = 0;
+            for (int a = 0; a < M; ++a) {
+                if (!(fc.Y_in[a] >= 0)) return fail(RLBM_EINVAL, "inlet mass fractions must be >= 0");
+                s += fc.Y_in[a];
+            }
+            if (std::fabs(s - 1.0) > 1e-10) return fail(RLBM_EINVAL, "inlet mass fractions must sum to 1");
+        }
+        if (fc.type == RLBM_FACE_OUTLET) {
+            if (f != 1) return fail(RLBM_EUNSUP, "outlets are supported on the x+ face only");
+            if (!(fc.P_inf > 0) || !(fc.sigma >= 0)) return fail(RLBM_EINVAL, "outlet needs P_inf > 0, sigma >= 0");
+        }
+        if (fc.type == RLBM_FACE_WALL) {
+            if (!(fc.T_lo > 0) || !(fc.T_hi > 0) || !(fc.width > 0))
+                return fail(RLBM_EINVAL, "wall needs T_lo, T_hi, width > 0");
+        }
+    }
+    if (d->storage != RLBM_STORAGE_F64 && d->storage != RLBM_STORAGE_F32_DEV)
+        return fail(RLBM_EINVAL, "unknown storage format");
+    if (d->substeps < 1) return fail(RLBM_EINVAL, "substeps must be >= 1");
+    if (d->slaved < -1 || d->slaved >= M) return fail(RLBM_EINVAL, "slaved species index out of range");
+    return RLBM_OK;
+}
+
+// Interface nodes: incoming sets D (velocities whose source lies outside the
+// box through a non-periodic face) and the boundary type of every node.
+void build_geometry(const rlbm_lattice_desc* d, Geometry& g) {
+    const int nx = d->nx, ny = d->ny, nz = d->nz;
+    g.N = (long long)nx * ny * nz;
+    const int n[3] = {nx, ny, nz};
+    bool per[3];
+    for (int ax = 0; ax < 3; ++ax) per[ax] = d->faces[2 * ax].type == RLBM_FACE_PERIODIC;
+    bool any = !(per[0] && per[1] && per[2]);
+    g.if_index.assign(any ? (size_t)g.N : 0, -1);
+    if (!any) return;
+    // wall target temperature: first wall face touched in y-, y+, z-, z+, x-, x+
+    const int prio[6] = {2, 3, 4, 5, 0, 1};
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                const int c[3] = {x, y, z};
+                bool on[6];
+                bool touches = false;
+                for (int ax = 0; ax < 3; ++ax) {
+                    on[2 * ax] = !per[ax] && c[ax] == 0;
+                    on[2 * ax + 1] = !per[ax] && c[ax] == n[ax] - 1;
+                    touches |= on[2 * ax] || on[2 * ax + 1];
+                }
+                if (!touches) continue;
+                unsigned mask = 0;
+                for (int i = 0; i < Q; ++i) {
+                    const int ci[3] = {cx_of(i), cy_of(i), cz_of(i)};
+                    bool out = false;
+                    for (int ax = 0; ax < 3; ++ax) {
+                        if (per[ax]) continue;
+                        const int src = c[ax] - ci[ax];
+                        out |= src < 0 || src >= n[ax];
+                    }
+                    if (out) mask |= 1u << i;
+                }
+                int type = 0;
+                double Tw = 0.0;
+                for (int q = 0; q < 6 && type == 0; ++q) {
+                    const int f = prio[q];
+                    if (on[f] && d->faces[f].type == RLBM_FACE_WALL) {
+                        type = RLBM_FACE_WALL;
+                        const rlbm_face& fc = d->faces[f];
+                        Tw = fc.T_lo + (fc.T_hi - fc.T_lo) * 0.5 * (1.0 + std::tanh((x - fc.x0) / fc.width));
+                    }
+                }
+                if (type == 0 && on[0] && d->faces[0].type == RLBM_FACE_INLET) type = RLBM_FACE_INLET;
+                if (type == 0 && on[1] && d->faces[1].type == RLBM_FACE_OUTLET) type = RLBM_FACE_OUTLET;
+                if (type == 0) continue;   // cannot happen: every non-periodic face has a type
+                const long long node = ((long long)z * ny + y) * nx + x;
+                g.if_index[node] = (int)g.if_node.size();
+                g.if_node.push_back((int)node);
+                g.if_mask.push_back(mask);
+                g.if_type.push_back(type);
+                g.if_T.push_back(Tw);
+                g.if_out.push_back(type == RLBM_FACE_OUTLET ? g.n_out++ : -1);
+            }
+}
+
+Plan make_plan(const rlbm_lattice_desc* d, int M, int E, const Geometry& g) {
+    Plan p{};
+    const int L = M + 1;
+    const size_t N = (size_t)g.N;
+    const size_t s = d->storage == RLBM_STORAGE_F32_DEV ? 4 : 8;
+    const size_t nif = g.if_node.size();
+    const size_t nblocks = (N + 255) / 256;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
+    p.off_lat = take(sizeof(LatDev));
+    p.off_mech = take(sizeof(MechDev));
+    p.off_blk = take(4 * sizeof(int));
+    p.off_flag = take(sizeof(int));
+    p.off_ref = take((size_t)L * Q * sizeof(double));
+    p.off_pop0 = take((size_t)L * Q * N * s);
+    p.off_pop1 = take((size_t)L * Q * N * s);
+    p.off_aux = take((size_t)(AUX_Y + M) * N * sizeof(double));
+    p.off_ifindex = take(nif ? N * sizeof(int) : 0);
+    p.off_ifnode = take(nif * sizeof(int));
+    p.off_ifmask = take(nif * sizeof(unsigned));
+    p.off_iftype = take(nif * sizeof(int));
+    p.off_ifT = take(nif * sizeof(double));
+    p.off_ifout = take(nif * sizeof(int));
+    p.off_bcbuf = take((size_t)L * Q * nif * sizeof(double));
+    p.off_out = take((size_t)(5 + M) * g.n_out * sizeof(double));
+    p.off_partial = take(nblocks * (6 + E) * sizeof(double));
+    p.off_invout = take((6 + E) * sizeof(double));
+    p.total = o;
+    return p;
+}
+
+struct Timing {
+    int kernel;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct rlbm_mech {
+    MechDev dev;
+};
+
+struct rlbm_lattice {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    rlbm_lattice_desc desc{};
+    std::vector<double> Y_in;
+    int M = 0, L = 0, E = 0, storage = 0;
+    Geometry geo;
+    Plan plan{};
+    char* base = nullptr;
+    LatDev host{};            // mirror of the device entry
+    LatDev* d_lat = nullptr;
+    int* d_blk = nullptr;     // [0, node blocks] and [0, interface blocks]
+    int* d_flag = nullptr;
+    double* d_ref = nullptr;
+    double* d_partial = nullptr;
+    double* d_invout = nullptr;
+    long long steps_done = 0;
+    bool state_set = false;
+    bool timing = false;
+    std::vector<Timing> events;
+    double ms[3] = {0, 0, 0};
+    long long counts[3] = {0, 0, 0};
+};
+
+struct rlbm_batch {
+    std::vector<rlbm_lattice*> lats;
+    char* base = nullptr;
+    LatDev* d_table = nullptr;
+    int* d_blk = nullptr;     // [k + 1] node-block prefix, then [k + 1] interface-block prefix
+    std::vector<LatDev> host_table;
+    std::vector<int> host_blk;
+};
+
+extern "C" {
+
+const char* rlbm_last_error(void) { return g_last_error.c_str(); }
+
+int rlbm_mech_create(const rlbm_mech_desc* d, rlbm_mech** out) {
+    if (!d || !out) return fail(RLBM_EINVAL, "null argument");
+    *out = nullptr;
+    const int M = d->M, R = d->R, E = d->E;
+    if (M < 2 || M > RLBM_MAX_SPECIES) return fail(RLBM_EINVAL, "species count out of range");
+    if (!species_supported(M)) return fail(RLBM_EUNSUP, "species count has no compiled kernel (2, 3, 4, 9)");
+    if (R < 0 || R > RLBM_MAX_REACTIONS) return fail(RLBM_EINVAL, "reaction count out of range");
+    if (E < 0 || E > RLBM_MAX_ELEMENTS) return fail(RLBM_EINVAL, "element count out of range");
+    if (!d->molar_mass || !d->nasa || !d->D_ref) return fail(RLBM_EINVAL, "missing species data");
+    if (E > 0 && !d->composition) return fail(RLBM_EINVAL, "missing composition");
+    if (R > 0 && (!d->nu_f || !d->nu_r || !d->lnA || !d->beta || !d->Ta || !d->reversible))
+        return fail(RLBM_EINVAL, "missing reaction data");
+    if (!(d->R_univ > 0) || !(d->T_ref > 0) || !(d->P_ref > 0) || !(d->mu_ref > 0) || !(d->Pr > 0))
+        return fail(RLBM_EINVAL, "R_univ, T_ref, P_ref, mu_ref and Pr must be > 0");
+    rlbm_mech* m = new (std::nothrow) rlbm_mech();
+    if (!m) return fail(RLBM_EINVAL, "out of host memory");
+    MechDev& md = m->dev;
+    std::memset(&md, 0, sizeof(md));
+    md.M = M; md.R = R; md.E = E;
+    md.R_univ = d->R_univ;
+    md.ln_cstd = d->ln_cstd;
+    for (int a = 0; a < M; ++a) {
+        const double ma = d->molar_mass[a];
+        if (!(ma > 0)) { delete m; return fail(RLBM_EINVAL, "molar masses must be > 0"); }
+        md.m[a] = ma;
+        md.inv_m[a] = 1.0 / ma;
+        md.Ra[a] = d->R_univ / ma;
+        const double* n = d->nasa + 7 * a;
+        for (int k = 0; k < 7; ++k) md.nasa[a][k] = n[k];
+        const double R_a = md.Ra[a];
+        md.uc[a][0] = R_a * n[5];
+        md.uc[a][1] = R_a * (n[0] - 1.0);
+        md.uc[a][2] = R_a * n[1] / 2.0;
+        md.uc[a][3] = R_a * n[2] / 3.0;
+        md.uc[a][4] = R_a * n[3] / 4.0;
+        md.uc[a][5] = R_a * n[4] / 5.0;
+        md.cvc[a][0] = R_a * (n[0] - 1.0);
+        for (int k = 1; k < 5; ++k) md.cvc[a][k] = R_a * n[k];
+        for (int b = 0; b < M; ++b) {
+            if (b == a) continue;
+            const double D = d->D_ref[a * M + b];
+            if (!(D > 0) || D != d->D_ref[b * M + a]) {
+                delete m;
+                return fail(RLBM_EINVAL, "D_ref must be symmetric and > 0 off the diagonal");
+            }
+            md.Kab[a][b] = 1.0 / (D * ma * d->molar_mass[b]);
+        }
+        for (int e = 0; e < E; ++e) md.comp[a][e] = (double)d->composition[a * E + e];
+    }
+    for (int r = 0; r < R; ++r) {
+        md.lnA[r] = d->lnA[r];
+        md.beta[r] = d->beta[r];
+        md.Ta[r] = d->Ta[r];
+        md.rev[r] = d->reversible[r] ? 1 : 0;
+        double s = 0;
+        for (int a = 0; a < M; ++a) {
+            const int f = d->nu_f[r * M + a], b = d->nu_r[r * M + a];
+            if (f < 0 || f > 3 || b < 0 || b > 3) {
+                delete m;
+                return fail(RLBM_EUNSUP, "stoichiometric coefficients must be 0..3");
+            }
+            md.nu_f[r][a] = (int8_t)f;
+            md.nu_r[r][a] = (int8_t)b;
+            md.dnu[r][a] = (double)(b - f);
+            s += (double)(b - f);
+        }
+        md.dnu_sum[r] = s;
+    }
+    md.T_ref = d->T_ref;
+    md.inv_T_ref = 1.0 / d->T_ref;
+    md.P_ref = d->P_ref;
+    md.inv_P_ref = 1.0 / d->P_ref;
+    md.mu_ref = d->mu_ref;
+    md.mu_exp = d->mu_exp;
+    md.inv_Pr = 1.0 / d->Pr;
+    md.D_exp = d->D_exp;
+    *out = m;
+    return RLBM_OK;
+}
+
+void rlbm_mech_destroy(rlbm_mech* m) { delete m; }
+
+int rlbm_lattice_bytes(const rlbm_lattice_desc* d, const rlbm_mech* mech, size_t* bytes) {
+    if (!mech || !bytes) return fail(RLBM_EINVAL, "null argument");
+    const int rc = validate_desc(d, mech->dev.M);
+    if (rc) return rc;
+    Geometry g;
+    build_geometry(d, g);
+    *bytes = make_plan(d, mech->dev.M, mech->dev.E, g).total;
+    return RLBM_OK;
+}
+
+int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void* dev_mem, size_t bytes,
+                        void* stream, rlbm_lattice** out) {
+    if (!mech || !out || !dev_mem) return fail(RLBM_EINVAL, "null argument");
+    *out = nullptr;
+    const int M = mech->dev.M;
+    int rc = validate_desc(d, M);
+    if (rc) return rc;
+    if (((uintptr_t)dev_mem & 255) != 0) return fail(RLBM_EINVAL, "device memory must be 256-byte aligned");
+    rlbm_lattice* lat = new (std::nothrow) rlbm_lattice();
+    if (!lat) return fail(RLBM_EINVAL, "out of host memory");
+    lat->desc = *d;
+    lat->M = M;
+    lat->L = M + 1;
+    lat->E = mech->dev.E;
+    lat->storage = d->storage;
+    lat->stream = (hipStream_t)stream;
+    build_geometry(d, lat->geo);
+    lat->plan = make_plan(d, M, lat->E, lat->geo);
+    if (bytes < lat->plan.total) {
+        delete lat;
+        return fail(RLBM_ENOSPC, "device buffer smaller than rlbm_lattice_bytes");
+    }
+    if (hipGetDevice(&lat->device) != hipSuccess) {
+        delete lat;
+        return fail(RLBM_EHIP, "hipGetDevice failed");
+    }
+    char* base = (char*)dev_mem;
+    lat->base = base;
+    const Plan& p = lat->plan;
+    const Geometry& g = lat->geo;
+    const size_t nif = g.if_node.size();
+    LatDev& h = lat->host;
+    std::memset(&h, 0, sizeof(h));
+    h.nx = d->nx; h.ny = d->ny; h.nz = d->nz;
+    for (int ax = 0; ax < 3; ++ax) h.per[ax] = d->faces[2 * ax].type == RLBM_FACE_PERIODIC;
+    h.slaved = d->slaved < 0 ? M - 1 : d->slaved;
+    h.substeps = d->substeps;
+    h.storage = d->storage;
+    h.N = g.N;
+    h.n_if = (int)nif;
+    h.n_out = g.n_out;
+    h.mech = (const MechDev*)(base + p.off_mech);
+    h.pop[0] = base + p.off_pop0;
+    h.pop[1] = base + p.off_pop1;
+    h.aux = (double*)(base + p.off_aux);
+    h.if_index = nif ? (const int*)(base + p.off_ifindex) : nullptr;
+    h.if_node = (const int*)(base + p.off_ifnode);
+    h.if_mask = (const unsigned*)(base + p.off_ifmask);
+    h.if_type = (const int*)(base + p.off_iftype);
+    h.if_T = (const double*)(base + p.off_ifT);
+    h.if_out = (const int*)(base + p.off_ifout);
+    h.bcbuf = (double*)(base + p.off_bcbuf);
+    h.out_state = (double*)(base + p.off_out);
+    h.ref = d->storage == RLBM_STORAGE_F32_DEV ? (const double*)(base + p.off_ref) : nullptr;
+    const rlbm_face& fi = d->faces[0];
+    if (fi.type == RLBM_FACE_INLET) {
+        h.rho_in = fi.rho_in; h.u_in = fi.u_in; h.T_in = fi.T_in;
+        for (int a = 0; a < M; ++a) h.Y_in[a] = fi.Y_in[a];
+    }
+    const rlbm_face& fo = d->faces[1];
+    if (fo.type == RLBM_FACE_OUTLET) { h.P_inf = fo.P_inf; h.sigma = fo.sigma; }
+    h.parity0 = 0;
+    h.t_end = LLONG_MAX;
+    lat->d_lat = (LatDev*)(base + p.off_lat);
+    lat->d_blk = (int*)(base + p.off_blk);
+    lat->d_flag = (int*)(base + p.off_flag);
+    lat->d_ref = (double*)(base + p.off_ref);
+    lat->d_partial = (double*)(base + p.off_partial);
+    lat->d_invout = (double*)(base + p.off_invout);
+    const int nb_nodes = (int)((g.N + 255) / 256);
+    const int nb_if = (int)((nif + 63) / 64);
+    const int blk[4] = {0, nb_nodes, 0, nb_if};
+    const int zero = 0;
+#define UP(dst, src, n)                                                              \
+    do {                                                                             \
+        hipError_t e_ = hipMemcpy((dst), (src), (n), hipMemcpyHostToDevice);        \
+        if (e_ != hipSuccess) { delete lat; return hip_fail(e_, "upload"); }        \
+    } while (0)
+    UP(base + p.off_mech, &mech->dev, sizeof(MechDev));
+    UP(lat->d_lat, &h, sizeof(LatDev));
+    UP(lat->d_blk, blk, sizeof(blk));
+    UP(lat->d_flag, &zero, sizeof(int));
+    if (nif) {
+        UP(base + p.off_ifindex, g.if_index.data(), (size_t)g.N * sizeof(int));
+        UP(base + p.off_ifnode, g.if_node.data(), nif * sizeof(int));
+        UP(base + p.off_ifmask, g.if_mask.data(), nif * sizeof(unsigned));
+        UP(base + p.off_iftype, g.if_type.data(), nif * sizeof(int));
+        UP(base + p.off_ifT, g.if_T.data(), nif * sizeof(double));
+        UP(base + p.off_ifout, g.if_out.data(), nif * sizeof(int));
+    }
+#undef UP
+    if (fi.type == RLBM_FACE_INLET) lat->Y_in.assign(fi.Y_in, fi.Y_in + M);
+    *out = lat;
+    return RLBM_OK;
+}
+
+void rlbm_lattice_destroy(rlbm_lattice* lat) {
+    if (!lat) return;
+    for (auto& e : lat->events) {
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+    }
+    delete lat;
+}
+
+int rlbm_lattice_shape(const rlbm_lattice* lat, int32_t* L, int64_t* N, int64_t* n_interface, int32_t* slaved) {
+    if (!lat) return fail(RLBM_EINVAL, "null lattice");
+    if (L) *L = lat->L;
+    if (N) *N = lat->geo.N;
+    if (n_interface) *n_interface = (int64_t)lat->geo.if_node.size();
+    if (slaved) *slaved = lat->host.slaved;
+    return RLBM_OK;
+}
+
+int rlbm_set_state(rlbm_lattice* lat, const double* rho, const double* u, const double* T, const double* Y,
+                   int on_device) {
+    if (!lat || !rho || !u || !T || !Y) return fail(RLBM_EINVAL, "null argument");
+    HIP_TRY(hipSetDevice(lat->device), "hipSetDevice");
+    const int M = lat->M;
+    const size_t N = (size_t)lat->geo.N;
+    const size_t nf = (5 + (size_t)M) * N;   // rho, u(3), T, Y(M)
+    std::vector<double> hf(nf);
+    double* hr = hf.data();
+    double* hu = hr + N;
+    double* hT = hu + 3 * N;
+    double* hY = hT + N;
+    if (on_device) {
+        HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
+        HIP_TRY(hipMemcpy(hr, rho, N * sizeof(double), hipMemcpyDeviceToHost), "copy rho");
+        HIP_TRY(hipMemcpy(hu, u, 3 * N * sizeof(double), hipMemcpyDeviceToHost), "copy u");
+        HIP_TRY(hipMemcpy(hT, T, N * sizeof(double), hipMemcpyDeviceToHost), "copy T");
+        HIP_TRY(hipMemcpy(hY, Y, (size_t)M * N * sizeof(double), hipMemcpyDeviceToHost), "copy Y");
+    } else {
+        std::memcpy(hr, rho, N * sizeof(double));
+        std::memcpy(hu, u, 3 * N * sizeof(double));
+        std::memcpy(hT, T, N * sizeof(double));
+        std::memcpy(hY, Y, (size_t)M * N * sizeof(double));
+    }
+    double mean_rho = 0, mean_T = 0;
+    std::vector<double> mean_Y(M, 0.0);
+    for (size_t n = 0; n < N; ++n) {
+        if (!(hr[n] > 0) || !(hT[n] > 0) || !std::isfinite(hr[n]) || !std::isfinite(hT[n]))
+            return fail(RLBM_EINVAL, "rho and T must be finite and > 0");
+        double s = 0;
+        for (int a = 0; a < M; ++a) {
+            const double y = hY[(size_t)a * N + n];
+            if (!std::isfinite(y)) return fail(RLBM_EINVAL, "mass fractions must be finite");
+            s += y;
+            mean_Y[a] += y;
+        }
+        if (std::fabs(s - 1.0) > 1e-10) return fail(RLBM_EINVAL, "mass fractions must sum to 1 at every node");
+        for (int dd = 0; dd < 3; ++dd)
+            if (!std::isfinite(hu[dd * N + n])) return fail(RLBM_EINVAL, "velocity must be finite");
+        mean_rho += hr[n];
+        mean_T += hT[n];
+    }
+    mean_rho /= (double)N;
+    mean_T /= (double)N;
+    for (int a = 0; a < M; ++a) mean_Y[a] /= (double)N;
+    if (lat->desc.slaved < 0) {
+        int best = 0;
+        for (int a = 1; a < M; ++a)
+            if (mean_Y[a] > mean_Y[best]) best = a;
+        lat->host.slaved = best;
+    }
+    lat->steps_done = 0;
+    lat->host.parity0 = 0;
+    HIP_TRY(hipMemcpyAsync(lat->d_lat, &lat->host, sizeof(LatDev), hipMemcpyHostToDevice, lat->stream), "upload");
+    // device staging for the fields: the second population buffer is idle now
+    double* stage = (double*)lat->host.pop[1];
+    HIP_TRY(hipMemcpyAsync(stage, hf.data(), nf * sizeof(double), hipMemcpyHostToDevice, lat->stream), "upload");
+    double* dmeanY = stage + nf;
+    HIP_TRY(hipMemcpyAsync(dmeanY, mean_Y.data(), M * sizeof(double), hipMemcpyHostToDevice, lat->stream),
+            "upload");
+    if (lat->storage == RLBM_STORAGE_F32_DEV)
+        HIP_TRY(launch_refs(M, lat->d_lat, lat->d_ref, mean_rho, mean_T, dmeanY, lat->stream), "refs kernel");
+    HIP_TRY(launch_init(M, lat->storage, lat->d_lat, (long long)N, stage, stage + N, stage + 4 * N, stage + 5 * N,
+                        lat->stream),
+            "init kernel");
+    HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
+    lat->state_set = true;
+    return RLBM_OK;
+}
+
+static int step_one(rlbm_lattice* lat, long long t) {
+    const Plan& p = lat->plan;
+    (void)p;
+    const int nb_nodes = (int)((lat->geo.N + 255) / 256);
+    const int nb_if = (int)((lat->geo.if_node.size() + 63) / 64);
+    for (int phase = 0; phase < 3; ++phase) {
+        StepLaunch a;
+        a.lats = lat->d_lat;
+        a.blk = phase == 0 ? lat->d_blk + 2 : lat->d_blk;
+        a.n_lat = 1;
+        a.blocks = phase == 0 ? nb_if : nb_nodes;
+        a.t = t;
+        a.flag = lat->d_flag;
+        a.stream = lat->stream;
+        if (a.blocks == 0) continue;
+        Timing ev{};
+        if (lat->timing) {
+            ev.kernel = phase;
+            HIP_TRY(hipEventCreate(&ev.a), "hipEventCreate");
+            HIP_TRY(hipEventCreate(&ev.b), "hipEventCreate");
+            HIP_TRY(hipEventRecord(ev.a, lat->stream), "hipEventRecord");
+        }
+        HIP_TRY(launch_phase(phase, lat->M, lat->storage, a), "step kernel launch");
+        if (lat->timing) {
+            HIP_TRY(hipEventRecord(ev.b, lat->stream), "hipEventRecord");
+            lat->events.push_back(ev);
+        }
+    }
+    return RLBM_OK;
+}
+
+int rlbm_step(rlbm_lattice* lat, int64_t n) {
+    if (!lat) return fail(RLBM_EINVAL, "null lattice");
+    if (n < 0) return fail(RLBM_EINVAL, "negative step count");
+    if (!lat->state_set) return fail(RLBM_EINVAL, "rlbm_set_state has not been called");
+    if (n == 0) return RLBM_OK;
+    HIP_TRY(hipSetDevice(lat->device), "hipSetDevice");
+    for (int64_t s = 0; s < n; ++s) {
+        const int rc = step_one(lat, lat->steps_done);
+        if (rc) return rc;
+        lat->steps_done++;
+    }
+    return RLBM_OK;
+}
+
+static int check_flag(rlbm_lattice* lat) {
+    int flag = 0;
+    HIP_TRY(hipMemcpy(&flag, lat->d_flag, sizeof(int), hipMemcpyDeviceToHost), "read flag");
+    if (flag) {
+        const int zero = 0;
+        HIP_TRY(hipMemcpy(lat->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice), "clear flag");
+        return fail(RLBM_ENONFINITE, "temperature iteration did not converge (non-physical state)");
+    }
+    return RLBM_OK;
+}
+
+int rlbm_read_fields(rlbm_lattice* lat, double* rho, double* u, double* T, double* Y, double* P, int on_device) {
+    if (!lat) return fail(RLBM_EINVAL, "null lattice");
+    if (!lat->state_set) return fail(RLBM_EINVAL, "rlbm_set_state has not been called");
+    HIP_TRY(hipSetDevice(lat->device), "hipSetDevice");
+    const int M = lat->M;
+    const size_t N = (size_t)lat->geo.N;
+    if (on_device) {
+        HIP_TRY(launch_fields(M, lat->storage, lat->d_lat, (long long)N, lat->steps_done, rho, u, T, Y, P,
+                              lat->d_flag, lat->stream),
+                "fields kernel");
+        HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
+        return check_flag(lat);
+    }
+    double* tmp = nullptr;
+    const size_t nf = (6 + (size_t)M) * N;
+    HIP_TRY(hipMalloc(&tmp, nf * sizeof(double)), "hipMalloc");
+    double *dr = tmp, *du = dr + N, *dT = du + 3 * N, *dY = dT + N, *dP = dY + (size_t)M * N;
+    hipError_t e = launch_fields(M, lat->storage, lat->d_lat, (long long)N, lat->steps_done, rho ? dr : nullptr,
+                                 u ? du : nullptr, T ? dT : nullptr, Y ? dY : nullptr, P ? dP : nullptr,
+                                 lat->d_flag, lat->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(lat->stream);
+    if (e == hipSuccess && rho) e = hipMemcpy(rho, dr, N * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && u) e = hipMemcpy(u, du, 3 * N * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && T) e = hipMemcpy(T, dT, N * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && Y) e = hipMemcpy(Y, dY, (size_t)M * N * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && P) e = hipMemcpy(P, dP, N * sizeof(double), hipMemcpyDeviceToHost);
+    hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "read fields");
+    return check_flag(lat);
+}
+
+static int pops_io(rlbm_lattice* lat, double* buf, int on_device, int write) {
+    if (!lat || !buf) return fail(RLBM_EINVAL, "null argument");
+    if (!lat->state_set) return fail(RLBM_EINVAL, "rlbm_set_state has not been called");
+    HIP_TRY(hipSetDevice(lat->device), "hipSetDevice");
+    const size_t N = (size_t)lat->geo.N;
+    const size_t n = (size_t)lat->L * Q * N;
+    if (on_device) {
+        HIP_TRY(launch_pops(lat->storage, lat->d_lat, (long long)N, lat->L, lat->steps_done, buf, write, lat->stream),
+                "populations kernel");
+        HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
+        return RLBM_OK;
+    }
+    double* tmp = nullptr;
+    HIP_TRY(hipMalloc(&tmp, n * sizeof(double)), "hipMalloc");
+    hipError_t e = hipSuccess;
+    if (write) e = hipMemcpy(tmp, buf, n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_pops(lat->storage, lat->d_lat, (long long)N, lat->L, lat->steps_done, tmp, write, lat->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(lat->stream);
+    if (e == hipSuccess && !write) e = hipMemcpy(buf, tmp, n * sizeof(double), hipMemcpyDeviceToHost);
+    hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "populations transfer");
+    return RLBM_OK;
+}
+
+int rlbm_read_populations(rlbm_lattice* lat, double* buf, int on_device) { return pops_io(lat, buf, on_device, 0); }
+
+int rlbm_write_populations(rlbm_lattice* lat, const double* buf, int on_device) {
+    return pops_io(lat, const_cast<double*>(buf), on_device, 1);
+}
+
+int rlbm_invariants(rlbm_lattice* lat, double* out, int n_out) {
+    if (!lat || !out) return fail(RLBM_EINVAL, "null argument");
+    if (!lat->state_set) return fail(RLBM_EINVAL, "rlbm_set_state has not been called");
+    const int nv = 6 + lat->E;
+    if (n_out < nv) return fail(RLBM_EINVAL, "output array too small (needs 6 + E)");
+    HIP_TRY(hipSetDevice(lat->device), "hipSetDevice");
+    HIP_TRY(launch_invariants(lat->M, lat->storage, lat->d_lat, lat->geo.N, lat->steps_done, lat->d_partial, nv,
+                              lat->d_invout, lat->stream),
+            "invariants kernel");
+    HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
+    HIP_TRY(hipMemcpy(out, lat->d_invout, nv * sizeof(double), hipMemcpyDeviceToHost), "read invariants");
+    return RLBM_OK;
+}
+
+int rlbm_set_timing(rlbm_lattice* lat, int enable) {
+    if (!lat) return fail(RLBM_EINVAL, "null lattice");
+    lat->timing = enable != 0;
+    return RLBM_OK;
+}
+
+int rlbm_kernel_times(rlbm_lattice* lat, double* ms, int64_t* counts, int n) {
+    if (!lat) return fail(RLBM_EINVAL, "null lattice");
+    HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
+    for (auto& e : lat->events) {
+        float t = 0;
+        HIP_TRY(hipEventElapsedTime(&t, e.a, e.b), "hipEventElapsedTime");
+        lat->ms[e.kernel] += t;
+        lat->counts[e.kernel] += 1;
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+    }
+    lat->events.clear();
+    for (int k = 0; k < n && k < 3; ++k) {
+        if (ms) ms[k] = lat->ms[k];
+        if (counts) counts[k] = lat->counts[k];
+        lat->ms[k] = 0;
+        lat->counts[k] = 0;
+    }
+    return RLBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+int rlbm_batch_bytes(int32_t k, size_t* bytes) {
+    if (k < 1 || !bytes) return fail(RLBM_EINVAL, "batch needs k >= 1");
+    *bytes = align256((size_t)k * sizeof(LatDev)) + align256(2 * (size_t)(k + 1) * sizeof(int));
+    return RLBM_OK;
+}
+
+int rlbm_batch_create(rlbm_lattice* const* lats, int32_t k, void* dev_mem, size_t bytes, rlbm_batch** out) {
+    if (!lats || k < 1 || !dev_mem || !out) return fail(RLBM_EINVAL, "null argument or k < 1");
+    *out = nullptr;
+    size_t need = 0;
+    rlbm_batch_bytes(k, &need);
+    if (bytes < need) return fail(RLBM_ENOSPC, "device buffer smaller than rlbm_batch_bytes");
+    if (((uintptr_t)dev_mem & 255) != 0) return fail(RLBM_EINVAL, "device memory must be 256-byte aligned");
+    for (int j = 0; j < k; ++j) {
+        if (!lats[j]) return fail(RLBM_EINVAL, "null lattice in batch");
+        if (lats[j]->M != lats[0]->M || lats[j]->storage != lats[0]->storage || lats[j]->device != lats[0]->device)
+            return fail(RLBM_EINVAL, "batched lattices need the same species count, storage and device");
+    }
+    rlbm_batch* b = new (std::nothrow) rlbm_batch();
+    if (!b) return fail(RLBM_EINVAL, "out of host memory");
+    b->lats.assign(lats, lats + k);
+    b->base = (char*)dev_mem;
+    b->d_table = (LatDev*)b->base;
+    b->d_blk = (int*)(b->base + align256((size_t)k * sizeof(LatDev)));
+    *out = b;
+    return RLBM_OK;
+}
+
+int rlbm_batch_step(rlbm_batch* b, const int64_t* steps) {
+    if (!b || !steps) return fail(RLBM_EINVAL, "null argument");
+    const int k = (int)b->lats.size();
+    rlbm_lattice* l0 = b->lats[0];
+    long long tmax = 0;
+    for (int j = 0; j < k; ++j) {
+        if (steps[j] < 0) return fail(RLBM_EINVAL, "negative step count");
+        if (!b->lats[j]->state_set) return fail(RLBM_EINVAL, "rlbm_set_state has not been called");
+        tmax = std::max<long long>(tmax, steps[j]);
+    }
+    if (tmax == 0) return RLBM_OK;
+    HIP_TRY(hipSetDevice(l0->device), "hipSetDevice");
+    b->host_table.resize(k);
+    b->host_blk.assign(2 * (k + 1), 0);
+    for (int j = 0; j < k; ++j) {
+        rlbm_lattice* lat = b->lats[j];
+        LatDev e = lat->host;
+        e.parity0 = (int)(lat->steps_done & 1);
+        e.t_end = steps[j];
+        b->host_table[j] = e;
+        const int nbn = steps[j] ? (int)((lat->geo.N + 255) / 256) : 0;
+        const int nbi = steps[j] ? (int)((lat->geo.if_node.size() + 63) / 64) : 0;
+        b->host_blk[j + 1] = b->host_blk[j] + nbn;
+        b->host_blk[(k + 1) + j + 1] = b->host_blk[(k + 1) + j] + nbi;
+    }
+    HIP_TRY(hipMemcpyAsync(b->d_table, b->host_table.data(), k * sizeof(LatDev), hipMemcpyHostToDevice, l0->stream),
+            "upload batch table");
+    HIP_TRY(hipMemcpyAsync(b->d_blk, b->host_blk.data(), b->host_blk.size() * sizeof(int), hipMemcpyHostToDevice,
+                           l0->stream),
+            "upload batch table");
+    const int nb_nodes = b->host_blk[k];
+    const int nb_if = b->host_blk[2 * (k + 1) - 1];
+    for (long long t = 0; t < tmax; ++t) {
+        for (int phase = 0; phase < 3; ++phase) {
+            StepLaunch a;
+            a.lats = b->d_table;
+            a.blk = phase == 0 ? b->d_blk + (k + 1) : b->d_blk;
+            a.n_lat = k;
+            a.blocks = phase == 0 ? nb_if : nb_nodes;
+            a.t = t;
+            a.flag = l0->d_flag;
+            a.stream = l0->stream;
+            if (a.blocks == 0) continue;
+            HIP_TRY(launch_phase(phase, l0->M, l0->storage, a), "batch kernel launch");
+        }
+    }
+    // keep the host table alive until the copies above have been consumed
+    HIP_TRY(hipStreamSynchronize(l0->stream), "hipStreamSynchronize");
+    for (int j = 0; j < k; ++j) b->lats[j]->steps_done += steps[j];
+    return RLBM_OK;
+}
+
+void rlbm_batch_destroy(rlbm_batch* b) { delete b; }
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and validates descriptors.  No call here touches a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2108_07605_amd import rlbm, workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rlbm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rlbm_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = rlbm.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(rlbm.EXPORTS)
+
+
+def test_mechanism_validation(mech9):
+    m = rlbm.Mechanism(mech9)
+    assert m.M == 9 and m.R == len(mech9["lnA"]) and m.E == 3
+    bad = dict(mech9)
+    bad["molar_mass"] = [-1.0] + list(mech9["molar_mass"][1:])
+    with pytest.raises(rlbm.RlbmError) as e:
+        rlbm.Mechanism(bad)
+    assert e.value.code == -1
+    D = np.array(mech9["transport"]["D_ref"])
+    D[0, 1] *= 2.0                       # not symmetric
+    bad = dict(mech9)
+    bad["transport"] = dict(mech9["transport"], D_ref=D.tolist())
+    with pytest.raises(rlbm.RlbmError):
+        rlbm.Mechanism(bad)
+
+
+def test_unsupported_species_count():
+    mech = wl.mechanism_abc()
+    five = dict(mech)
+    five["M"] = 5
+    for k in ("molar_mass",):
+        five[k] = list(mech[k]) + [10.0, 20.0]
+    five["nasa"] = list(mech["nasa"]) + [mech["nasa"][0]] * 2
+    five["composition"] = list(mech["composition"]) + [[1, 0], [0, 1]]
+    five["nu_f"] = [list(r) + [0, 0] for r in mech["nu_f"]]
+    five["nu_r"] = [list(r) + [0, 0] for r in mech["nu_r"]]
+    D = np.full((5, 5), 1e-3)
+    five["transport"] = dict(mech["transport"], D_ref=D.tolist())
+    with pytest.raises(rlbm.RlbmError) as e:
+        rlbm.Mechanism(five)
+    assert e.value.code == -4
+
+
+def test_lattice_bytes_plan(mech9):
+    m = rlbm.Mechanism(mech9)
+    case = wl.make_case("channel2d", nx=64, ny=16, nz=1, mech=mech9)
+    b64 = rlbm.lattice_bytes(case, m, "f64")
+    b32 = rlbm.lattice_bytes(case, m, "f32dev")
+    N, L = 64 * 16, 10
+    assert b64 >= 2 * L * 27 * N * 8 and b32 >= 2 * L * 27 * N * 4
+    assert b64 - b32 >= 2 * L * 27 * N * 4 - 2048
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda c: c["faces"].__setitem__(3, {"type": "periodic"}), -1),   # y axis half periodic
+    (lambda c: c["faces"].__setitem__(0, {"type": "outlet", "P_inf": 1.0, "sigma": 0.25}), -4),
+    (lambda c: c.__setitem__("substeps", 0), -1),
+    (lambda c: c.__setitem__("nx", 0), -1),
+])
+def test_lattice_descriptor_validation(mech9, mutate, code):
+    m = rlbm.Mechanism(mech9)
+    case = wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9)
+    mutate(case)
+    with pytest.raises(rlbm.RlbmError) as e:
+        rlbm.lattice_bytes(case, m, "f64")
+    assert e.value.code == code
+
+
+def test_inlet_composition_must_sum_to_one(mech9):
+    m = rlbm.Mechanism(mech9)
+    case = wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9)
+    y = list(case["faces"][0]["Y"])
+    y[0] += 0.1
+    case["faces"][0] = dict(case["faces"][0], Y=y)
+    with pytest.raises(rlbm.RlbmError) as e:
+        rlbm.lattice_bytes(case, m, "f64")
+    assert e.value.code == -1

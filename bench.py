@@ -127,7 +127,7 @@ def main():
         bytes_node = 2 * L * 27 * s                      # populations read + written once
         ms_step = r["ms_total"] / args.steps
         mlups = N / (ms_step * 1e-3) / 1e6
-        coll_ms, coll_n = r["kernels"]["collide"]
+        coll_name = max(r["kernels"], key=lambda kk: r["kernels"][kk][0]); coll_ms, coll_n = r["kernels"][coll_name]
         coll_avg = coll_ms / max(coll_n, 1)
         achieved = bytes_node * N / (coll_avg * 1e-3) / 1e9
         traffic = _traffic(st)
@@ -137,7 +137,7 @@ def main():
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                          "traffic": traffic,
-                         "kernel": "k_collide", "alg_bytes_per_node": bytes_node},
+                         "kernel": "k_" + coll_name, "alg_bytes_per_node": bytes_node},
             "step_frac_of_hbm_roofline": mlups * 1e6 * bytes_node / (HBM_PEAK_GBS * 1e9),
         }
     main_st = storages[0]

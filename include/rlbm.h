@@ -181,7 +181,7 @@ int rlbm_lattice_shape(const rlbm_lattice* lat, int32_t* L, int64_t* N, int64_t*
 
 /* Per-kernel timing with HIP events recorded on the lattice stream around
  * every launch while enabled.  rlbm_kernel_times synchronises and returns,
- * for kernel k in {0: boundary, 1: moments, 2: collide}, the accumulated
+ * for kernel k in {0: boundary, 1: local physics, 2: chemistry, 3: gradients, 4: update}, the accumulated
  * milliseconds ms[k] and launch counts counts[k] since the last reset. */
 int rlbm_set_timing(rlbm_lattice* lat, int enable);
 int rlbm_kernel_times(rlbm_lattice* lat, double* ms, int64_t* counts, int n);

@@ -99,68 +99,109 @@ __device__ __forceinline__ long long pull_src(const LatDev& L, const Nbr& n, int
     return ((long long)zs * L.ny + ys) * L.nx + xs;
 }
 
-// Population (lattice l, velocity i) after advection (and boundary
-// reconstruction, if this is an interface node with slot k >= 0).
-template <typename S>
-__device__ __forceinline__ double gather(const LatDev& L, const void* src, int k, const Nbr& n,
-                                         long long node, int l, int i) {
-    const int li = l * Q + i;
-    if (k >= 0) return L.bcbuf[(size_t)li * L.n_if + k];
-    return Codec<S>::ld(src, (size_t)li * L.N + pull_src(L, n, i), L.ref, li);
+// ---------------------------------------------------------------------------
+// pull-advection addressing for the hot kernels
+// ---------------------------------------------------------------------------
+// Node offsets of the source x - c for c = -1, 0, +1 along each axis, with
+// periodic wrap.  Along non-periodic axes only interface nodes would leave
+// the box, and those read the boundary buffer instead, so the wrapped value
+// is only ever an in-bounds placeholder.
+struct PullOff {
+    int x[3], y[3], z[3];   // index c + 1
+};
+
+__device__ __forceinline__ void pull_offsets(const LatDev& L, int x, int y, int z, PullOff& o) {
+    const int nx = L.nx, ny = L.ny, nz = L.nz, sxy = nx * ny;
+    o.x[0] = x == nx - 1 ? -(nx - 1) : 1;   // c = -1: source x + 1
+    o.x[1] = 0;
+    o.x[2] = x == 0 ? nx - 1 : -1;          // c = +1: source x - 1
+    o.y[0] = y == ny - 1 ? -(ny - 1) * nx : nx;
+    o.y[1] = 0;
+    o.y[2] = y == 0 ? (ny - 1) * nx : -nx;
+    o.z[0] = z == nz - 1 ? -(nz - 1) * sxy : sxy;
+    o.z[1] = 0;
+    o.z[2] = z == 0 ? (nz - 1) * sxy : -sxy;
 }
+
+__device__ __forceinline__ int sel3(int c, int m, int z, int p) { return c < 0 ? m : (c == 0 ? z : p); }
 
 template <int M>
 __device__ __forceinline__ int lat_of(int a, int slaved) { return a - (a > slaved ? 1 : 0); }
 
-// ---------------------------------------------------------------------------
-// moments of one node's (post-advection, post-boundary) populations
-// ---------------------------------------------------------------------------
+// Load population (lattice l, velocity i) of this node after advection and
+// boundary reconstruction: interface nodes (slot k >= 0) read the boundary
+// buffer, all others pull from node + off in the source buffer.
+template <typename S>
+__device__ __forceinline__ double ldpop(const LatDev& L, const void* src, int k, int node_off, int l, int i) {
+    const int li = l * Q + i;
+    if (k >= 0) return Codec<S>::ld(L.bcbuf, (size_t)li * L.n_if + k, L.ref, li);
+    return Codec<S>::ld(src, (size_t)li * L.N + node_off, L.ref, li);
+}
+
 template <int M>
 struct Moments {
     double rho, j[3], rhoE, q[3], P[6];   // P: xx, yy, zz, xy, xz, yz
     double rho_a[M], j_a[M][3];
 };
 
+// Moments of the node's post-advection, post-boundary populations (eqs.
+// density1, momentum1, fdensity, f1momMomentum, g0momTotalEnergy), the
+// slaved species by difference (eq. strongest).  FULL adds P = sum f c c,
+// q = sum g c and the species momenta.
 template <int M, typename S, bool FULL>
-__device__ __forceinline__ void node_moments(const LatDev& L, const void* src, int k, const Nbr& n,
-                                             long long node, Moments<M>& m) {
+__device__ __forceinline__ void node_moments(const LatDev& L, const void* src, int k, int node, const PullOff& o,
+                                             Moments<M>& m) {
     const int s = L.slaved;
     m.rho = m.rhoE = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) m.j[d] = m.q[d] = 0.0;
 #pragma unroll
     for (int d = 0; d < 6; ++d) m.P[d] = 0.0;
-    const int lf = M - 1, lg = M;
-#pragma unroll 1
-    for (int i = 0; i < Q; ++i) {
-        const double cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
-        const double f = gather<S>(L, src, k, n, node, lf, i);
-        m.rho += f;
-        m.j[0] += f * cx; m.j[1] += f * cy; m.j[2] += f * cz;
-        if (FULL) {
-            m.P[0] += f * cx * cx; m.P[1] += f * cy * cy; m.P[2] += f * cz * cz;
-            m.P[3] += f * cx * cy; m.P[4] += f * cx * cz; m.P[5] += f * cy * cz;
-        }
-        const double g = gather<S>(L, src, k, n, node, lg, i);
-        m.rhoE += g;
-        if (FULL) { m.q[0] += g * cx; m.q[1] += g * cy; m.q[2] += g * cz; }
-    }
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-        m.rho_a[a] = 0.0;
-        m.j_a[a][0] = m.j_a[a][1] = m.j_a[a][2] = 0.0;
-        if (a == s) continue;
-        const int l = lat_of<M>(a, s);
-        double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll 1
-        for (int i = 0; i < Q; ++i) {
-            const double f = gather<S>(L, src, k, n, node, l, i);
-            r += f;
-            jx += f * (double)cx_of(i); jy += f * (double)cy_of(i); jz += f * (double)cz_of(i);
+    for (int a = 0; a < M; ++a) m.rho_a[a] = m.j_a[a][0] = m.j_a[a][1] = m.j_a[a][2] = 0.0;
+    // momentum and energy lattices
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
+        const int off = node + o.x[cx + 1] + o.y[cy + 1] + o.z[cz + 1];
+        const double f = ldpop<S>(L, src, k, off, M - 1, i);
+        const double g = ldpop<S>(L, src, k, off, M, i);
+        m.rho += f;
+        m.rhoE += g;
+        if (cx) m.j[0] += cx > 0 ? f : -f;
+        if (cy) m.j[1] += cy > 0 ? f : -f;
+        if (cz) m.j[2] += cz > 0 ? f : -f;
+        if (FULL) {
+            if (cx) { m.P[0] += f; m.q[0] += cx > 0 ? g : -g; }
+            if (cy) { m.P[1] += f; m.q[1] += cy > 0 ? g : -g; }
+            if (cz) { m.P[2] += f; m.q[2] += cz > 0 ? g : -g; }
+            if (cx * cy) m.P[3] += cx * cy > 0 ? f : -f;
+            if (cx * cz) m.P[4] += cx * cz > 0 ? f : -f;
+            if (cy * cz) m.P[5] += cy * cz > 0 ? f : -f;
         }
-        m.rho_a[a] = r; m.j_a[a][0] = jx; m.j_a[a][1] = jy; m.j_a[a][2] = jz;
     }
-    // slaved species (section 3.6, eq. strongest)
+    // species lattices, one at a time
+#pragma unroll 1
+    for (int l = 0; l < M - 1; ++l) {
+        double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
+            const int off = node + o.x[cx + 1] + o.y[cy + 1] + o.z[cz + 1];
+            const double v = ldpop<S>(L, src, k, off, l, i);
+            r += v;
+            if (FULL) {
+                if (cx) jx += cx > 0 ? v : -v;
+                if (cy) jy += cy > 0 ? v : -v;
+                if (cz) jz += cz > 0 ? v : -v;
+            }
+        }
+        const int a = l + (l >= s ? 1 : 0);
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            if (c == a) { m.rho_a[c] = r; m.j_a[c][0] = jx; m.j_a[c][1] = jy; m.j_a[c][2] = jz; }
+        }
+    }
     double rs = m.rho, jsx = m.j[0], jsy = m.j[1], jsz = m.j[2];
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -174,252 +215,441 @@ __device__ __forceinline__ void node_moments(const LatDev& L, const void* src, i
 }
 
 // ---------------------------------------------------------------------------
-// k_moments
+// k_local: everything a node needs from its own populations
 // ---------------------------------------------------------------------------
+// Stefan-Maxwell system (eq. transform1, dt = 1), Doolittle LU without
+// pivoting, rows generated on the fly:
+//   A_aa = 1 + inv_tau_a / 2,   A_ab = -common K_ab Y_b / 2  (a != b).
+// A is strictly row diagonally dominant (margin 1), so no pivoting is needed.
+// V holds u_a - u on entry and the diffusion velocities on exit.
+template <int M>
+__device__ __forceinline__ void sm_solve_lu(const MechDev& mc, const double* Y, double common,
+                                            const double* inv_tau, double (*V)[3]) {
+    double Uu[M][M];
+    double inv_diag[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        double lrow[M];
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+            double a = -0.5 * common * mc.Kab[i][j] * Y[j];
+#pragma unroll
+            for (int kk = 0; kk < j; ++kk) a -= lrow[kk] * Uu[kk][j];
+            lrow[j] = a * inv_diag[j];
+        }
+#pragma unroll
+        for (int j = i; j < M; ++j) {
+            double a = (i == j) ? 1.0 + 0.5 * inv_tau[i] : -0.5 * common * mc.Kab[i][j] * Y[j];
+#pragma unroll
+            for (int kk = 0; kk < i; ++kk) a -= lrow[kk] * Uu[kk][j];
+            Uu[i][j] = a;
+        }
+        inv_diag[i] = 1.0 / Uu[i][i];
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) {
+            double yv = V[i][dd];
+#pragma unroll
+            for (int kk = 0; kk < i; ++kk) yv -= lrow[kk] * V[kk][dd];
+            V[i][dd] = yv;
+        }
+    }
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) {
+            double sm = V[i][dd];
+#pragma unroll
+            for (int j = i + 1; j < M; ++j) sm -= Uu[i][j] * V[j][dd];
+            V[i][dd] = sm * inv_diag[i];
+        }
+    }
+}
+
 template <int M, typename S>
-__global__ __launch_bounds__(256) void k_moments(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                                 int n_lat, long long t, int* __restrict__ flag) {
+__global__ __launch_bounds__(256) void k_local(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+                                               int n_lat, long long t, int* __restrict__ flag) {
     const int b = blockIdx.x;
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
     if (t >= L.t_end) return;
-    const long long node = (long long)(b - blk[lj]) * 256 + threadIdx.x;
+    const int node = (b - blk[lj]) * 256 + threadIdx.x;
     if (node >= L.N) return;
     const MechDev& mc = *L.mech;
     const void* src = L.pop[(L.parity0 + t) & 1];
-    Nbr n;
-    make_nbr(L, node, n);
+    const int x = node % L.nx, r = node / L.nx, y = r % L.ny, z = r / L.ny;
+    PullOff o;
+    pull_offsets(L, x, y, z, o);
     const int k = L.n_if ? L.if_index[node] : -1;
-    Moments<M> m;
-    node_moments<M, S, false>(L, src, k, n, node, m);
-    const double inv_rho = 1.0 / m.rho;
-    double Y[M];
-#pragma unroll
-    for (int a = 0; a < M; ++a) Y[a] = m.rho_a[a] * inv_rho;
-    const double u[3] = {m.j[0] * inv_rho, m.j[1] * inv_rho, m.j[2] * inv_rho};
-    const double U = m.rhoE * inv_rho - 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     double* aux = L.aux;
+    double* prm = L.prm;
     const size_t N = (size_t)L.N;
-    int fail = 0;
-    const double T = solve_T<M>(mc, Y, U, aux[AUX_T * N + node], &fail);
-    if (fail) atomicOr(flag, 1);
-    const double th = mc.R_univ * mix_inv_m<M>(mc, Y) * T;
-    aux[AUX_RHO * N + node] = m.rho;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        aux[(AUX_U + d) * N + node] = u[d];
-        aux[(AUX_PHI + d) * N + node] = m.rho * u[d] * (1.0 - 3.0 * th) - m.rho * u[d] * u[d] * u[d];
-    }
-    aux[AUX_T * N + node] = T;
-#pragma unroll
-    for (int a = 0; a < M; ++a) aux[(AUX_Y + a) * N + node] = Y[a];
-}
 
-// ---------------------------------------------------------------------------
-// k_collide
-// ---------------------------------------------------------------------------
-template <int M, typename S>
-__global__ __launch_bounds__(256) void k_collide(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                                 int n_lat, long long t, int* __restrict__ flag) {
-    const int b = blockIdx.x;
-    const int lj = find_lattice(blk, n_lat, b);
-    const LatDev& L = lats[lj];
-    if (t >= L.t_end) return;
-    const long long node = (long long)(b - blk[lj]) * 256 + threadIdx.x;
-    if (node >= L.N) return;
-    const MechDev& mc = *L.mech;
-    const int par = (L.parity0 + t) & 1;
-    const void* src = L.pop[par];
-    void* dst = L.pop[par ^ 1];
-    const int s = L.slaved;
-    Nbr n;
-    make_nbr(L, node, n);
-    const int k = L.n_if ? L.if_index[node] : -1;
     Moments<M> m;
-    node_moments<M, S, true>(L, src, k, n, node, m);
-    const double* aux = L.aux;
-    const size_t N = (size_t)L.N;
-
+    node_moments<M, S, true>(L, src, k, node, o, m);
     const double rho = m.rho, inv_rho = 1.0 / rho;
     const double u[3] = {m.j[0] * inv_rho, m.j[1] * inv_rho, m.j[2] * inv_rho};
     const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     double Y[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) Y[a] = m.rho_a[a] * inv_rho;
-    const double T = aux[AUX_T * N + node];
     const double U = m.rhoE * inv_rho - 0.5 * usq;
+    int fail = 0;
+    // temperature (eq. temperature), Newton from the previous step's value
+    const double T = solve_T<M>(mc, Y, U, aux[AUX_T * N + node], &fail);
     const double inv_mix_m = mix_inv_m<M>(mc, Y);
     const double th = mc.R_univ * inv_mix_m * T;
     const double P = rho * th;
 
-    // same-time gradients, isotropic D3Q27 stencil: d phi/dx_a = 3 sum_i w_i c_ia phi(x + c_i)
-    double d[3] = {0.0, 0.0, 0.0};
-    double G[M][3];
-#pragma unroll
-    for (int a = 0; a < M; ++a) G[a][0] = G[a][1] = G[a][2] = 0.0;
-#pragma unroll 1
-    for (int i = 0; i < Q; ++i) {
-        if (i == 13) continue;
-        const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
-        const double w = 3.0 * (cx ? 1.0 / 6.0 : 2.0 / 3.0) * (cy ? 1.0 / 6.0 : 2.0 / 3.0) *
-                         (cz ? 1.0 / 6.0 : 2.0 / 3.0);
-        const size_t nb = ((size_t)n.zg[1 + cz] * L.ny + n.yg[1 + cy]) * L.nx + n.xg[1 + cx];
-        if (cx) d[0] += w * cx * aux[(AUX_PHI + 0) * N + nb];
-        if (cy) d[1] += w * cy * aux[(AUX_PHI + 1) * N + nb];
-        if (cz) d[2] += w * cz * aux[(AUX_PHI + 2) * N + nb];
-#pragma unroll
-        for (int a = 0; a < M; ++a) {
-            const double y = aux[(AUX_Y + a) * N + nb];
-            G[a][0] += w * cx * y; G[a][1] += w * cy * y; G[a][2] += w * cz * y;
-        }
-    }
-
     // relaxation parameters (sections 2.3 and 3.4)
     const double lnr = log(T * mc.inv_T_ref);
     const double common = mc.R_univ * T / inv_mix_m * P * mc.inv_P_ref * exp(-mc.D_exp * lnr);
-    double inv_tau[M], beta[M];
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-        double sum = 0.0;
-#pragma unroll
-        for (int c = 0; c < M; ++c)
-            if (c != a) sum += Y[c] * mc.Kab[a][c];
-        inv_tau[a] = common * sum;
-        beta[a] = inv_tau[a] / (2.0 + inv_tau[a]);
-    }
     const double mu = mc.mu_ref * exp(mc.mu_exp * lnr);
     const double omega = 1.0 / (mu / P + 0.5);
     const double omega1 = 1.0 / (mu * mc.inv_Pr / P + 0.5);
 
-    // Stefan-Maxwell diffusion velocities (eq. transform1)
-    double V[M][3];
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-        const bool small = m.rho_a[a] <= 1e-14 * rho;
-        const double inv = small ? 0.0 : 1.0 / m.rho_a[a];
-#pragma unroll
-        for (int dd = 0; dd < 3; ++dd) V[a][dd] = small ? 0.0 : m.j_a[a][dd] * inv - u[dd];
-    }
+    // local part of the energy-lattice flux
+    //   Qb = (omega - omega1)(q - u.(P - P^eq) - q^eq) + omega1 rho sum_a H_a Y_a V_a
+    double Qb[3];
     {
-        double itab[M][M];
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-#pragma unroll
-            for (int c = 0; c < M; ++c) itab[a][c] = common * mc.Kab[a][c];
-        sm_solve<M>(Y, itab, inv_tau, V);
-    }
-
-    // reaction sub-steps (eq. R3)
-    double drho[M];
-    int fail = 0;
-    reaction_increment<M>(mc, m.rho_a, rho, U, T, L.substeps, drho, &fail);
-    if (fail) atomicOr(flag, 1);
-
-    // energy-lattice quasi-equilibrium flux, singularity-free form:
-    //   Q = (omega - omega1)(q - u.(P - P^eq) + q^ex - q^eq)
-    //       + omega1 rho sum_a H_a Y_a V_a + (2 - omega1)/2 P sum_a H_a grad Y_a
-    double Qv[3];
-    {
-        double diff[3] = {0.0, 0.0, 0.0}, corr[3] = {0.0, 0.0, 0.0};
         double H = 0.0;
 #pragma unroll
-        for (int a = 0; a < M; ++a) {
-            const double Ha = species_U(mc, a, T) + mc.Ra[a] * T;
-            H += Y[a] * Ha;
-#pragma unroll
-            for (int dd = 0; dd < 3; ++dd) {
-                diff[dd] += Ha * Y[a] * V[a][dd];
-                corr[dd] += Ha * G[a][dd];
-            }
-        }
+        for (int a = 0; a < M; ++a) H += Y[a] * (species_U(mc, a, T) + mc.Ra[a] * T);
         const double hq = rho * (H + 0.5 * usq);
         const double Pt[3][3] = {{m.P[0], m.P[3], m.P[4]}, {m.P[3], m.P[1], m.P[5]}, {m.P[4], m.P[5], m.P[2]}};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             double uP = 0.0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double Peq = rho * ((a == c ? th : 0.0) + u[c] * u[a]);
-                uP += u[c] * (Pt[c][a] - Peq);
-            }
-            const double qex = -0.5 * u[a] * d[a];
-            Qv[a] = (omega - omega1) * (m.q[a] - uP + qex - hq * u[a]) + omega1 * rho * diff[a] +
-                    0.5 * (2.0 - omega1) * P * corr[a];
+            for (int c = 0; c < 3; ++c) uP += u[c] * (Pt[c][a] - rho * ((a == c ? th : 0.0) + u[c] * u[a]));
+            Qb[a] = (omega - omega1) * (m.q[a] - uP - hq * u[a]);
         }
     }
 
-    // per-species product-form parameters: equilibrium (u, u^2 + theta_b) and
-    // quasi-equilibrium (u + V_b, (u + V_b)^2 + theta_b)
-    double hE[M][3], hS[M][3], xS[M][3];
+    // Stefan-Maxwell diffusion velocities; u_a := u for absent species
+    double V[M][3];
+    double inv_tau[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-        const double tha = mc.Ra[a] * T;
+        const bool small = m.rho_a[a] <= 1e-14 * rho;
+        const double inv = small ? 0.0 : 1.0 / m.rho_a[a];
 #pragma unroll
-        for (int dd = 0; dd < 3; ++dd) {
-            hE[a][dd] = 0.5 * (u[dd] * u[dd] + tha);
-            const double xi = u[dd] + V[a][dd];
-            xS[a][dd] = 0.5 * xi;
-            hS[a][dd] = 0.5 * (xi * xi + tha);
-        }
+        for (int dd = 0; dd < 3; ++dd) V[a][dd] = small ? 0.0 : m.j_a[a][dd] * inv - u[dd];
+        double sum = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+            if (c != a) sum += Y[c] * mc.Kab[a][c];
+        inv_tau[a] = common * sum;
     }
-    // extended equilibrium of the momentum lattice (eqs. feqmix, Pex)
-    double hX[3];
-    const double exf = (2.0 - omega) / (2.0 * rho * omega);
-#pragma unroll
-    for (int dd = 0; dd < 3; ++dd) hX[dd] = 0.5 * (th + u[dd] * u[dd] + exf * d[dd]);
-    GeqAxis gx, gy, gz;
-    geq_axis(u[0], th, gx);
-    geq_axis(u[1], th, gy);
-    geq_axis(u[2], th, gz);
-    const double hu[3] = {0.5 * u[0], 0.5 * u[1], 0.5 * u[2]};
-
-#pragma unroll 1
-    for (int i = 0; i < Q; ++i) {
-        const int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);
-        // W_bi and W*_bi for all species
-        double Wd[M], D[M];
+    sm_solve_lu<M>(mc, Y, common, inv_tau, V);
+    {
+        double diff[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < M; ++a) {
-            const double e0 = c0 == 0 ? 1.0 - 2.0 * hE[a][0] : hE[a][0] + c0 * hu[0];
-            const double e1 = c1 == 0 ? 1.0 - 2.0 * hE[a][1] : hE[a][1] + c1 * hu[1];
-            const double e2 = c2 == 0 ? 1.0 - 2.0 * hE[a][2] : hE[a][2] + c2 * hu[2];
-            const double s0 = c0 == 0 ? 1.0 - 2.0 * hS[a][0] : hS[a][0] + c0 * xS[a][0];
-            const double s1 = c1 == 0 ? 1.0 - 2.0 * hS[a][1] : hS[a][1] + c1 * xS[a][1];
-            const double s2 = c2 == 0 ? 1.0 - 2.0 * hS[a][2] : hS[a][2] + c2 * xS[a][2];
-            Wd[a] = e0 * e1 * e2;
-            D[a] = m.rho_a[a] * (Wd[a] - s0 * s1 * s2);
+            const double hy = (species_U(mc, a, T) + mc.Ra[a] * T) * Y[a];
+#pragma unroll
+            for (int dd = 0; dd < 3; ++dd) diff[dd] += hy * V[a][dd];
         }
-        // species collision (eq. finalNumericalEquationsReactive, eq. fStar)
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) Qb[dd] += omega1 * rho * diff[dd];
+    }
+
+    // neighbour-facing fields
+    aux[AUX_RHO * N + node] = rho;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        aux[(AUX_U + d) * N + node] = u[d];
+        aux[(AUX_PHI + d) * N + node] = rho * u[d] * (1.0 - 3.0 * th) - rho * u[d] * u[d] * u[d];
+    }
+    aux[AUX_T * N + node] = T;
+#pragma unroll
+    for (int a = 0; a < M; ++a) aux[(AUX_Y + a) * N + node] = Y[a];
+    // enthalpy-weighted composition moments: sum_a H_a(T') Y_a = sum_k T'^k Pk
+#pragma unroll
+    for (int kk = 0; kk < 6; ++kk) {
+        double pk = 0.0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) pk += mc.hc[a][kk] * Y[a];
+        aux[(AUX_Y + M + kk) * N + node] = pk;
+    }
+
+    prm[PRM_RHO * N + node] = rho;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) prm[(PRM_U + d) * N + node] = u[d];
+    prm[PRM_T * N + node] = T;
+    prm[PRM_UINT * N + node] = U;
+    prm[PRM_TH * N + node] = th;
+    prm[PRM_OMEGA * N + node] = omega;
+    prm[PRM_COMMON * N + node] = common;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) prm[(PRM_QB + d) * N + node] = Qb[d];
+    prm[PRM_WQ * N + node] = omega - omega1;
+    prm[PRM_CC * N + node] = 0.5 * (2.0 - omega1) * P;
+
+    if (fail) atomicOr(flag, 1);
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        const int r0 = PRM_SP + 6 * a;
+        prm[(r0 + 0) * N + node] = m.rho_a[a];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) prm[(r0 + 1 + d) * N + node] = V[a][d];
+        prm[(r0 + 4) * N + node] = inv_tau[a] / (2.0 + inv_tau[a]);   // beta_a = dt / (2 tau_a + dt)
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_chem: reaction increment of every node (eq. R3), l forward-Euler
+// sub-steps at frozen specific internal energy; reads rho_a, rho, U, T from
+// the per-node record and writes Delta rho_a into it
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+                                              int n_lat, long long t, int* __restrict__ flag) {
+    const int b = blockIdx.x;
+    const int lj = find_lattice(blk, n_lat, b);
+    const LatDev& L = lats[lj];
+    if (t >= L.t_end) return;
+    const int node = (b - blk[lj]) * 256 + threadIdx.x;
+    if (node >= L.N) return;
+    const MechDev& mc = *L.mech;
+    double* prm = L.prm;
+    const size_t N = (size_t)L.N;
+    double rho_a[M], drho[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) rho_a[a] = prm[(PRM_SP + 6 * a) * N + node];
+    const double rho = prm[PRM_RHO * N + node];
+    const double U = prm[PRM_UINT * N + node];
+    const double T = prm[PRM_T * N + node];
+    int fail = 0;
+    reaction_increment<M>(mc, rho_a, rho, U, T, L.substeps, drho, &fail);
+    if (fail) atomicOr(flag, 1);
+#pragma unroll
+    for (int a = 0; a < M; ++a) prm[(PRM_SP + 6 * a + 5) * N + node] = drho[a];
+}
+
+// ---------------------------------------------------------------------------
+// k_grad: same-time gradients with the isotropic D3Q27 stencil
+//   d phi/dx_a = 3 sum_i w_i c_ia phi(x + c_i)
+// of Phi_a (extension, eqs. Pex, qex) and of sum_b H_b Y_b with H_b at this
+// node's temperature (Fourier correction, eq. corrFourier), from the fields
+// k_local published.  Ghost values beyond a non-periodic face repeat the
+// nearest node.  Writes rows PRM_GRAD..PRM_GRAD+5 of the per-node record.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+                                              int n_lat, long long t, int* __restrict__ flag) {
+    const int b = blockIdx.x;
+    const int lj = find_lattice(blk, n_lat, b);
+    const LatDev& L = lats[lj];
+    if (t >= L.t_end) return;
+    const int node = (b - blk[lj]) * 256 + threadIdx.x;
+    if (node >= L.N) return;
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int x = node % nx, r = node / nx, y = r % ny, z = r / ny;
+    const size_t N = (size_t)L.N;
+    const double* aux = L.aux;
+    double* prm = L.prm;
+    const double T = prm[PRM_T * N + node];
+    const double T2 = T * T, T3 = T2 * T, T4 = T3 * T, T5 = T4 * T;
+    const bool px = L.per[0], py = L.per[1], pz = L.per[2];
+    const int gx[3] = {x == 0 ? (px ? nx - 1 : 0) : x - 1, x, x == nx - 1 ? (px ? 0 : x) : x + 1};
+    const int gy[3] = {y == 0 ? (py ? ny - 1 : 0) : y - 1, y, y == ny - 1 ? (py ? 0 : y) : y + 1};
+    const int gz[3] = {z == 0 ? (pz ? nz - 1 : 0) : z - 1, z, z == nz - 1 ? (pz ? 0 : z) : z + 1};
+    const double* Pk = aux + (size_t)(AUX_Y + M) * N;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+    for (int czi = 0; czi < 3; ++czi) {
+        const int cz = czi - 1;
+        const size_t zrow = (size_t)sel3(cz, gz[0], gz[1], gz[2]) * ny;
+        const double wz = cz ? 1.0 / 6.0 : 2.0 / 3.0;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const int cx = j % 3 - 1, cy = j / 3 - 1;
+            if (cx == 0 && cy == 0 && cz == 0) continue;
+            const double w = 3.0 * (cx ? 1.0 / 6.0 : 2.0 / 3.0) * (cy ? 1.0 / 6.0 : 2.0 / 3.0) * wz;
+            const size_t nb = (zrow + gy[cy + 1]) * nx + gx[cx + 1];
+            const double hy = Pk[nb] + T * Pk[N + nb] + T2 * Pk[2 * N + nb] + T3 * Pk[3 * N + nb] +
+                              T4 * Pk[4 * N + nb] + T5 * Pk[5 * N + nb];
+            if (cx) { acc[0] += (cx * w) * aux[(AUX_PHI + 0) * N + nb]; acc[3] += (cx * w) * hy; }
+            if (cy) { acc[1] += (cy * w) * aux[(AUX_PHI + 1) * N + nb]; acc[4] += (cy * w) * hy; }
+            if (cz) { acc[2] += (cz * w) * aux[(AUX_PHI + 2) * N + nb]; acc[5] += (cz * w) * hy; }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) prm[(size_t)(prm_grad(M) + q) * N + node] = acc[q];
+}
+
+// ---------------------------------------------------------------------------
+// k_update: the collision of every stored lattice.  A block of three waves
+// covers 64 consecutive nodes and three of the nine velocity groups
+// (c_y, c_z) = (g % 3 - 1, g / 3 - 1), one group per wave, i.e. three
+// velocities per thread; the per-node record is staged in LDS.
+// ---------------------------------------------------------------------------
+constexpr int UPD_NODES = 64;
+constexpr int UPD_WAVES = 3;
+constexpr int UPD_THREADS = UPD_WAVES * UPD_NODES;
+
+__device__ __forceinline__ double psi_rt(int c, double xi, double P) {
+    const double side = 0.5 * (P + (c > 0 ? xi : -xi));
+    return c == 0 ? 1.0 - P : side;
+}
+
+// Raw stored value (FP64, or FP32 deviation) of population (l, i) after
+// advection and boundary reconstruction.
+template <typename S>
+__device__ __forceinline__ S ld_raw(const LatDev& L, const void* src, int k, int off, int l, int i) {
+    const int li = l * Q + i;
+    if (k >= 0) return static_cast<const S*>(L.bcbuf)[(size_t)li * L.n_if + k];
+    return static_cast<const S*>(src)[(size_t)li * L.N + off];
+}
+
+template <int M, typename S>
+__global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+                                                        int n_lat, long long t, int* __restrict__ flag) {
+    constexpr int NR = prm_rows(M);
+    __shared__ double sp[NR][UPD_NODES];          // per-node record
+    const int b = blockIdx.x;
+    const int lj = find_lattice(blk, n_lat, b);
+    const LatDev& L = lats[lj];
+    if (t >= L.t_end) return;
+    const int local = b - blk[lj];
+    const int node0 = (local / 3) * UPD_NODES;
+    const int lane = threadIdx.x % UPD_NODES;
+    const int grp = (local % 3) * UPD_WAVES + threadIdx.x / UPD_NODES;
+    const int node = node0 + lane;
+    const bool valid = node < L.N;
+    const MechDev& mc = *L.mech;
+    const int par = (L.parity0 + t) & 1;
+    const void* src = L.pop[par];
+    void* dst = L.pop[par ^ 1];
+    const int s = L.slaved;
+    const size_t N = (size_t)L.N;
+    const double* prm = L.prm;
+
+    const int x = node % L.nx, r = node / L.nx, y = r % L.ny, z = r / L.ny;
+    const int k = (L.n_if && valid) ? L.if_index[node] : -1;
+    PullOff o;
+    pull_offsets(L, x, y, z, o);
+    const int c1 = grp % 3 - 1, c2 = grp / 3 - 1;
+    const int offyz = node + sel3(c1, o.y[0], 0, o.y[2]) + sel3(c2, o.z[0], 0, o.z[2]);
+    // populations of this thread's three velocities, loaded up front
+    S fin[3][M + 1];
+    if (valid) {
+#pragma unroll
+        for (int cxi = 0; cxi < 3; ++cxi) {
+            const int i = 9 * (c2 + 1) + 3 * (c1 + 1) + cxi;
+            const int off = offyz + o.x[cxi];
+#pragma unroll
+            for (int l = 0; l <= M; ++l) fin[cxi][l] = ld_raw<S>(L, src, k, off, l, i);
+        }
+    }
+    for (int idx = threadIdx.x; idx < NR * UPD_NODES; idx += UPD_THREADS) {
+        const int row = idx / UPD_NODES, j = idx % UPD_NODES;
+        const int nd = node0 + j;
+        sp[row][j] = nd < L.N ? prm[(size_t)row * N + nd] : 1.0;
+    }
+    __syncthreads();
+    if (!valid) return;
+
+    const double rho = sp[PRM_RHO][lane];
+    const double u[3] = {sp[PRM_U][lane], sp[PRM_U + 1][lane], sp[PRM_U + 2][lane]};
+    const double T = sp[PRM_T][lane];
+    const double U = sp[PRM_UINT][lane];
+    const double th = sp[PRM_TH][lane];
+    const double omega = sp[PRM_OMEGA][lane];
+    const double common = sp[PRM_COMMON][lane];
+    const int GR = prm_grad(M);
+    double d[3], Qv[3];
+    {
+        const double wq = sp[PRM_WQ][lane], cc = sp[PRM_CC][lane];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            d[a] = sp[GR + a][lane];
+            Qv[a] = sp[PRM_QB + a][lane] + wq * (-0.5 * u[a] * d[a]) + cc * sp[GR + 3 + a][lane];
+        }
+    }
+    const double u2[3] = {u[0] * u[0], u[1] * u[1], u[2] * u[2]};
+    const double exf = (2.0 - omega) / (2.0 * rho * omega);
+    double hX[3];
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) hX[dd] = th + u2[dd] + exf * d[dd];   // P^ex (eq. Pex)
+    const double fyz = psi_rt(c1, u[1], hX[1]) * psi_rt(c2, u[2], hX[2]);
+    GeqAxis gax, gay, gaz;
+    geq_axis(u[0], th, gax);
+    geq_axis(u[1], th, gay);
+    geq_axis(u[2], th, gaz);
+    const double Wy = c1 < 0 ? gay.W[0] : (c1 == 0 ? gay.W[1] : gay.W[2]);
+    const double ky = c1 < 0 ? gay.k[0] : (c1 == 0 ? gay.k[1] : gay.k[2]);
+    const double Wz = c2 < 0 ? gaz.W[0] : (c2 == 0 ? gaz.W[1] : gaz.W[2]);
+    const double kz = c2 < 0 ? gaz.k[0] : (c2 == 0 ? gaz.k[1] : gaz.k[2]);
+    const double wyz = Wy * Wz, kyz = ky * Wz + Wy * kz;
+    const double fcm = common / rho;             // F_ai = common Y_a sum_b K_ab D_bi
+
+    // y/z product-form factors of every species: equilibrium (xi = u) and
+    // quasi-equilibrium (xi = u + V_b, eq. xiPstar2), the latter scaled by rho_b
+    double pe[M], ps[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        const int r0 = PRM_SP + 6 * a;
+        const double tha = mc.Ra[a] * T;
+        const double ey = psi_rt(c1, u[1], u2[1] + tha);
+        const double ez = psi_rt(c2, u[2], u2[2] + tha);
+        const double xy = u[1] + sp[r0 + 2][lane], xz = u[2] + sp[r0 + 3][lane];
+        pe[a] = ey * ez;
+        ps[a] = sp[r0][lane] * psi_rt(c1, xy, xy * xy + tha) * psi_rt(c2, xz, xz * xz + tha);
+    }
+#pragma unroll
+    for (int cxi = 0; cxi < 3; ++cxi) {
+        reload_barrier();
+        const int c0 = cxi - 1;
+        const int i = 9 * (c2 + 1) + 3 * (c1 + 1) + cxi;
+        double W[M], D[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            const int r0 = PRM_SP + 6 * a;
+            const double tha = mc.Ra[a] * T;
+            const double ex = c0 == 0 ? 1.0 - u2[0] - tha : 0.5 * (u2[0] + tha + c0 * u[0]);
+            const double xx = u[0] + sp[r0 + 1][lane];
+            const double sx = c0 == 0 ? 1.0 - xx * xx - tha : 0.5 * (xx * xx + tha + c0 * xx);
+            W[a] = pe[a] * ex;
+            D[a] = sp[r0][lane] * W[a] - ps[a] * sx;      // f_bi^eq - f_bi^*
+        }
+        // species (eq. finalNumericalEquationsReactive with eq. fStar)
 #pragma unroll
         for (int a = 0; a < M; ++a) {
             if (a == s) continue;
-            const int l = lat_of<M>(a, s);
+            const int r0 = PRM_SP + 6 * a;
             double F = 0.0;
 #pragma unroll
             for (int c = 0; c < M; ++c)
                 if (c != a) F += mc.Kab[a][c] * D[c];
-            F *= common * Y[a];
-            const double f = gather<S>(L, src, k, n, node, l, i);
-            const double out = f + 2.0 * beta[a] * (m.rho_a[a] * Wd[a] - f) + (beta[a] - 1.0) * F + Wd[a] * drho[a];
+            const double ra = sp[r0][lane], be = sp[r0 + 4][lane], dr = sp[r0 + 5][lane];
+            F *= fcm * ra;
+            const int l = lat_of<M>(a, s);
+            double f = 0.0;
+#pragma unroll
+            for (int ll = 0; ll < M - 1; ++ll)
+                if (ll == l) f = (double)fin[cxi][ll];
             const int li = l * Q + i;
+            if constexpr (sizeof(S) == 4) f += L.ref[li];
+            const double out = f + 2.0 * be * (ra * W[a] - f) + (be - 1.0) * F + W[a] * dr;
             Codec<S>::st(dst, (size_t)li * N + node, out, L.ref, li);
         }
-        // momentum lattice with the extended equilibrium (eq. f)
+        // momentum lattice, extended equilibrium (eqs. f, feqmix)
         {
-            const double e0 = c0 == 0 ? 1.0 - 2.0 * hX[0] : hX[0] + c0 * hu[0];
-            const double e1 = c1 == 0 ? 1.0 - 2.0 * hX[1] : hX[1] + c1 * hu[1];
-            const double e2 = c2 == 0 ? 1.0 - 2.0 * hX[2] : hX[2] + c2 * hu[2];
-            const double f = gather<S>(L, src, k, n, node, M - 1, i);
-            const double out = f + omega * (rho * e0 * e1 * e2 - f);
             const int li = (M - 1) * Q + i;
-            Codec<S>::st(dst, (size_t)li * N + node, out, L.ref, li);
+            double f = (double)fin[cxi][M - 1];
+            if constexpr (sizeof(S) == 4) f += L.ref[li];
+            const double ex = c0 == 0 ? 1.0 - hX[0] : 0.5 * (hX[0] + c0 * u[0]);
+            Codec<S>::st(dst, (size_t)li * N + node, f + omega * (rho * ex * fyz - f), L.ref, li);
         }
-        // energy lattice (eq. g)
+        // energy lattice (eqs. g, geq_i, gstar)
         {
-            const double g = gather<S>(L, src, k, n, node, M, i);
-            double out = g + omega * (geq_i(i, rho, U, gx, gy, gz) - g);
-            if (c2_of(i) == 1) out += 0.5 * (c0 * Qv[0] + c1 * Qv[1] + c2 * Qv[2]);
             const int li = M * Q + i;
+            double g = (double)fin[cxi][M];
+            if constexpr (sizeof(S) == 4) g += L.ref[li];
+            const double geq = rho * (U * gax.W[cxi] * wyz + gax.k[cxi] * wyz + gax.W[cxi] * kyz);
+            double out = g + omega * (geq - g);
+            if (c0 * c0 + c1 * c1 + c2 * c2 == 1) out += 0.5 * (c0 * Qv[0] + c1 * Qv[1] + c2 * Qv[2]);
             Codec<S>::st(dst, (size_t)li * N + node, out, L.ref, li);
         }
     }
@@ -676,7 +906,7 @@ __global__ __launch_bounds__(64) void k_boundary(const LatDev* __restrict__ lats
             } else {
                 out = incoming(i) ? 2.0 * a_eq - l_eq : a_eq + streamed(l, i) - l_eq;
             }
-            L.bcbuf[(size_t)(l * Q + i) * L.n_if + k] = out;
+            Codec<S>::st(L.bcbuf, (size_t)(l * Q + i) * L.n_if + k, out, L.ref, l * Q + i);
         }
     }
     if (fail) atomicOr(flag, 1);
@@ -912,10 +1142,16 @@ static hipError_t launch_step_phase(int phase, int M, const StepLaunch& a) {
         RLBM_DISPATCH(M, hipLaunchKernelGGL((k_boundary<MM, S>), dim3(a.blocks), dim3(64), 0, a.stream, a.lats,
                                                 a.blk, a.n_lat, a.t, a.flag))
     } else if (phase == 1) {
-        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_moments<MM, S>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
+        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_local<MM, S>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
+                                                a.blk, a.n_lat, a.t, a.flag))
+    } else if (phase == 2) {
+        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
+                                                a.blk, a.n_lat, a.t, a.flag))
+    } else if (phase == 3) {
+        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_grad<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
                                                 a.blk, a.n_lat, a.t, a.flag))
     } else {
-        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_collide<MM, S>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
+        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_update<MM, S>), dim3(a.blocks), dim3(UPD_THREADS), 0, a.stream, a.lats,
                                                 a.blk, a.n_lat, a.t, a.flag))
     }
     return hipGetLastError();

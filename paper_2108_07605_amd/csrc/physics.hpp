@@ -31,6 +31,7 @@ struct MechDev {
     double Ra[MAXM];            // R_univ / m_a
     double uc[MAXM][6];         // U_a(T) = sum_k uc[a][k] T^k
     double cvc[MAXM][5];        // C_{a,v}(T) = sum_k cvc[a][k] T^k  (= dU_a/dT)
+    double hc[MAXM][6];         // H_a(T) = sum_k hc[a][k] T^k
     double nasa[MAXM][7];       // raw NASA-7 coefficients (Gibbs functions)
     double R_univ, ln_cstd;
     // reactions
@@ -53,14 +54,15 @@ struct LatDev {
     int n_if, n_out;
     const MechDev* mech;
     void* pop[2];               // ping-pong population buffers [L][27][N]
-    double* aux;                // [8 + M][N]: rho, ux, uy, uz, T, Phi_x,y,z, Y_0..Y_{M-1}
+    double* aux;                // [14 + M][N]: rho, ux, uy, uz, T, Phi_x,y,z, Y_0..Y_{M-1}, P_0..P_5
+    double* prm;                // [14 + 6 M][N] per-node record from k_local for k_update
     const int* if_index;        // [N]: interface slot or -1 (NULL if n_if == 0)
     const int* if_node;         // [n_if]
     const unsigned* if_mask;    // [n_if] incoming set D as a 27-bit mask
     const int* if_type;         // [n_if] RLBM_FACE_WALL / INLET / OUTLET
     const double* if_T;         // [n_if] wall target temperature
     const int* if_out;          // [n_if] outlet slot or -1
-    double* bcbuf;              // [L * 27][n_if] post-boundary populations (FP64)
+    void* bcbuf;                // [L * 27][n_if] post-boundary populations (storage format)
     double* out_state;          // [5 + M][n_out]: rho, ux, uy, uz, T, Y
     const double* ref;          // [L * 27] reference populations (FP32 storage)
     double rho_in, u_in, T_in, P_inf, sigma;
@@ -71,6 +73,20 @@ struct LatDev {
 };
 
 constexpr int AUX_RHO = 0, AUX_U = 1, AUX_T = 4, AUX_PHI = 5, AUX_Y = 8;
+
+// Per-node record written by k_local for k_update (structure of arrays,
+// row r of node n at prm[r * N + n]):
+constexpr int PRM_RHO = 0, PRM_U = 1, PRM_T = 4, PRM_UINT = 5, PRM_TH = 6, PRM_OMEGA = 7, PRM_COMMON = 8,
+              PRM_QB = 9, PRM_WQ = 12, PRM_CC = 13, PRM_SP = 14;
+// species rows: PRM_SP + 6 a + {0: rho_a, 1..3: V_a, 4: beta_a, 5: drho_a}
+__host__ __device__ constexpr int prm_grad(int M) { return PRM_SP + 6 * M; }   // d (3), sum H grad Y (3)
+__host__ __device__ constexpr int prm_rows(int M) { return PRM_SP + 6 * M + 6; }
+
+
+// Compiler barrier: memory may have changed, so mechanism constants used after
+// it are re-read (cheap scalar loads) rather than kept live in vector
+// registers across loop iterations, which would cost occupancy.
+__device__ __forceinline__ void reload_barrier() { asm volatile("" ::: "memory"); }
 
 // ---------------------------------------------------------------------------
 // product form (section 2.2, eqs. phi0, phiPlus, phis, prod)
@@ -168,10 +184,10 @@ __device__ __forceinline__ double species_cv(const MechDev& mc, int a, double T)
 }
 
 // g_a/(R_univ T) = h/(R T) - s/R for one species.
-__device__ __forceinline__ double gibbs_RT(const MechDev& mc, int a, double T, double lnT) {
+__device__ __forceinline__ double gibbs_RT(const MechDev& mc, int a, double T, double lnT, double invT) {
     const double* n = mc.nasa[a];
     const double h = n[0] + T * (n[1] * 0.5 + T * (n[2] * (1.0 / 3.0) + T * (n[3] * 0.25 + T * n[4] * 0.2))) +
-                     n[5] / T;
+                     n[5] * invT;
     const double s = n[0] * lnT + T * (n[1] + T * (n[2] * 0.5 + T * (n[3] * (1.0 / 3.0) + T * n[4] * 0.25))) +
                      n[6];
     return h - s;
@@ -193,10 +209,11 @@ __device__ __forceinline__ void production_rates(const MechDev& mc, const double
 #pragma unroll
     for (int a = 0; a < M; ++a) {
         conc[a] = fmax(rho_a[a], 0.0) * mc.inv_m[a];
-        gRT[a] = gibbs_RT(mc, a, T, lnT);
+        gRT[a] = gibbs_RT(mc, a, T, lnT, invT);
     }
     const double lnc = mc.ln_cstd - lnT;
     for (int r = 0; r < R; ++r) {
+        reload_barrier();
         const double lnkf = mc.lnA[r] + mc.beta[r] * lnT - mc.Ta[r] * invT;
         double fwd = exp(lnkf);
 #pragma unroll
@@ -245,6 +262,7 @@ __device__ __forceinline__ void reaction_increment(const MechDev& mc, const doub
     const double inv_rho = 1.0 / rho;
     double Ts = T;
     for (int s = 0; s < l; ++s) {
+        reload_barrier();
         if (s > 0) {
             double Y[M];
 #pragma unroll

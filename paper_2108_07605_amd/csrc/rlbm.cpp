@@ -38,8 +38,10 @@ int hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+constexpr int NPHASE = 5;   // boundary, local, chemistry, gradients, update
+
 struct Plan {
-    size_t off_lat, off_mech, off_blk, off_flag, off_ref, off_pop0, off_pop1, off_aux, off_ifindex, off_ifnode,
+    size_t off_lat, off_mech, off_blk, off_flag, off_ref, off_pop0, off_pop1, off_aux, off_prm, off_ifindex, off_ifnode,
         off_ifmask, off_iftype, off_ifT, off_ifout, off_bcbuf, off_out, off_partial, off_invout, total;
 };
 
@@ -166,12 +168,13 @@ Plan make_plan(const rlbm_lattice_desc* d, int M, int E, const Geometry& g) {
     auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
     p.off_lat = take(sizeof(LatDev));
     p.off_mech = take(sizeof(MechDev));
-    p.off_blk = take(4 * sizeof(int));
+    p.off_blk = take(6 * sizeof(int));
     p.off_flag = take(sizeof(int));
     p.off_ref = take((size_t)L * Q * sizeof(double));
     p.off_pop0 = take((size_t)L * Q * N * s);
     p.off_pop1 = take((size_t)L * Q * N * s);
-    p.off_aux = take((size_t)(AUX_Y + M) * N * sizeof(double));
+    p.off_aux = take((size_t)(AUX_Y + M + 6) * N * sizeof(double));
+    p.off_prm = take((size_t)prm_rows(M) * N * sizeof(double));
     p.off_ifindex = take(nif ? N * sizeof(int) : 0);
     p.off_ifnode = take(nif * sizeof(int));
     p.off_ifmask = take(nif * sizeof(unsigned));
@@ -217,8 +220,8 @@ struct rlbm_lattice {
     bool state_set = false;
     bool timing = false;
     std::vector<Timing> events;
-    double ms[3] = {0, 0, 0};
-    long long counts[3] = {0, 0, 0};
+    double ms[NPHASE] = {0, 0, 0, 0, 0};
+    long long counts[NPHASE] = {0, 0, 0, 0, 0};
 };
 
 struct rlbm_batch {
@@ -272,6 +275,8 @@ int rlbm_mech_create(const rlbm_mech_desc* d, rlbm_mech** out) {
         md.uc[a][5] = R_a * n[4] / 5.0;
         md.cvc[a][0] = R_a * (n[0] - 1.0);
         for (int k = 1; k < 5; ++k) md.cvc[a][k] = R_a * n[k];
+        for (int k = 0; k < 6; ++k) md.hc[a][k] = md.uc[a][k];
+        md.hc[a][1] += R_a;   // H_a = U_a + R_a T
         for (int b = 0; b < M; ++b) {
             if (b == a) continue;
             const double D = d->D_ref[a * M + b];
@@ -371,13 +376,14 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     h.pop[0] = base + p.off_pop0;
     h.pop[1] = base + p.off_pop1;
     h.aux = (double*)(base + p.off_aux);
+    h.prm = (double*)(base + p.off_prm);
     h.if_index = nif ? (const int*)(base + p.off_ifindex) : nullptr;
     h.if_node = (const int*)(base + p.off_ifnode);
     h.if_mask = (const unsigned*)(base + p.off_ifmask);
     h.if_type = (const int*)(base + p.off_iftype);
     h.if_T = (const double*)(base + p.off_ifT);
     h.if_out = (const int*)(base + p.off_ifout);
-    h.bcbuf = (double*)(base + p.off_bcbuf);
+    h.bcbuf = base + p.off_bcbuf;
     h.out_state = (double*)(base + p.off_out);
     h.ref = d->storage == RLBM_STORAGE_F32_DEV ? (const double*)(base + p.off_ref) : nullptr;
     const rlbm_face& fi = d->faces[0];
@@ -397,7 +403,8 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     lat->d_invout = (double*)(base + p.off_invout);
     const int nb_nodes = (int)((g.N + 255) / 256);
     const int nb_if = (int)((nif + 63) / 64);
-    const int blk[4] = {0, nb_nodes, 0, nb_if};
+    const int nb64 = 3 * (int)((g.N + 63) / 64);
+    const int blk[6] = {0, nb_nodes, 0, nb_if, 0, nb64};
     const int zero = 0;
 #define UP(dst, src, n)                                                              \
     do {                                                                             \
@@ -425,8 +432,8 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
 void rlbm_lattice_destroy(rlbm_lattice* lat) {
     if (!lat) return;
     for (auto& e : lat->events) {
-        hipEventDestroy(e.a);
-        hipEventDestroy(e.b);
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
     }
     delete lat;
 }
@@ -515,12 +522,13 @@ static int step_one(rlbm_lattice* lat, long long t) {
     (void)p;
     const int nb_nodes = (int)((lat->geo.N + 255) / 256);
     const int nb_if = (int)((lat->geo.if_node.size() + 63) / 64);
-    for (int phase = 0; phase < 3; ++phase) {
+    const int nb64 = 3 * (int)((lat->geo.N + 63) / 64);
+    for (int phase = 0; phase < NPHASE; ++phase) {
         StepLaunch a;
         a.lats = lat->d_lat;
-        a.blk = phase == 0 ? lat->d_blk + 2 : lat->d_blk;
+        a.blk = phase == 0 ? lat->d_blk + 2 : (phase == 4 ? lat->d_blk + 4 : lat->d_blk);
         a.n_lat = 1;
-        a.blocks = phase == 0 ? nb_if : nb_nodes;
+        a.blocks = phase == 0 ? nb_if : (phase == 4 ? nb64 : nb_nodes);
         a.t = t;
         a.flag = lat->d_flag;
         a.stream = lat->stream;
@@ -592,7 +600,7 @@ int rlbm_read_fields(rlbm_lattice* lat, double* rho, double* u, double* T, doubl
     if (e == hipSuccess && T) e = hipMemcpy(T, dT, N * sizeof(double), hipMemcpyDeviceToHost);
     if (e == hipSuccess && Y) e = hipMemcpy(Y, dY, (size_t)M * N * sizeof(double), hipMemcpyDeviceToHost);
     if (e == hipSuccess && P) e = hipMemcpy(P, dP, N * sizeof(double), hipMemcpyDeviceToHost);
-    hipFree(tmp);
+    (void)hipFree(tmp);
     if (e != hipSuccess) return hip_fail(e, "read fields");
     return check_flag(lat);
 }
@@ -617,7 +625,7 @@ static int pops_io(rlbm_lattice* lat, double* buf, int on_device, int write) {
         e = launch_pops(lat->storage, lat->d_lat, (long long)N, lat->L, lat->steps_done, tmp, write, lat->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(lat->stream);
     if (e == hipSuccess && !write) e = hipMemcpy(buf, tmp, n * sizeof(double), hipMemcpyDeviceToHost);
-    hipFree(tmp);
+    (void)hipFree(tmp);
     if (e != hipSuccess) return hip_fail(e, "populations transfer");
     return RLBM_OK;
 }
@@ -656,11 +664,11 @@ int rlbm_kernel_times(rlbm_lattice* lat, double* ms, int64_t* counts, int n) {
         HIP_TRY(hipEventElapsedTime(&t, e.a, e.b), "hipEventElapsedTime");
         lat->ms[e.kernel] += t;
         lat->counts[e.kernel] += 1;
-        hipEventDestroy(e.a);
-        hipEventDestroy(e.b);
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
     }
     lat->events.clear();
-    for (int k = 0; k < n && k < 3; ++k) {
+    for (int k = 0; k < n && k < NPHASE; ++k) {
         if (ms) ms[k] = lat->ms[k];
         if (counts) counts[k] = lat->counts[k];
         lat->ms[k] = 0;
@@ -674,7 +682,7 @@ int rlbm_kernel_times(rlbm_lattice* lat, double* ms, int64_t* counts, int n) {
 // ---------------------------------------------------------------------------
 int rlbm_batch_bytes(int32_t k, size_t* bytes) {
     if (k < 1 || !bytes) return fail(RLBM_EINVAL, "batch needs k >= 1");
-    *bytes = align256((size_t)k * sizeof(LatDev)) + align256(2 * (size_t)(k + 1) * sizeof(int));
+    *bytes = align256((size_t)k * sizeof(LatDev)) + align256(3 * (size_t)(k + 1) * sizeof(int));
     return RLBM_OK;
 }
 
@@ -713,7 +721,7 @@ int rlbm_batch_step(rlbm_batch* b, const int64_t* steps) {
     if (tmax == 0) return RLBM_OK;
     HIP_TRY(hipSetDevice(l0->device), "hipSetDevice");
     b->host_table.resize(k);
-    b->host_blk.assign(2 * (k + 1), 0);
+    b->host_blk.assign(3 * (k + 1), 0);
     for (int j = 0; j < k; ++j) {
         rlbm_lattice* lat = b->lats[j];
         LatDev e = lat->host;
@@ -722,8 +730,10 @@ int rlbm_batch_step(rlbm_batch* b, const int64_t* steps) {
         b->host_table[j] = e;
         const int nbn = steps[j] ? (int)((lat->geo.N + 255) / 256) : 0;
         const int nbi = steps[j] ? (int)((lat->geo.if_node.size() + 63) / 64) : 0;
+        const int nb6 = steps[j] ? 3 * (int)((lat->geo.N + 63) / 64) : 0;
         b->host_blk[j + 1] = b->host_blk[j] + nbn;
         b->host_blk[(k + 1) + j + 1] = b->host_blk[(k + 1) + j] + nbi;
+        b->host_blk[2 * (k + 1) + j + 1] = b->host_blk[2 * (k + 1) + j] + nb6;
     }
     HIP_TRY(hipMemcpyAsync(b->d_table, b->host_table.data(), k * sizeof(LatDev), hipMemcpyHostToDevice, l0->stream),
             "upload batch table");
@@ -732,13 +742,14 @@ int rlbm_batch_step(rlbm_batch* b, const int64_t* steps) {
             "upload batch table");
     const int nb_nodes = b->host_blk[k];
     const int nb_if = b->host_blk[2 * (k + 1) - 1];
+    const int nb64 = b->host_blk[3 * (k + 1) - 1];
     for (long long t = 0; t < tmax; ++t) {
-        for (int phase = 0; phase < 3; ++phase) {
+        for (int phase = 0; phase < NPHASE; ++phase) {
             StepLaunch a;
             a.lats = b->d_table;
-            a.blk = phase == 0 ? b->d_blk + (k + 1) : b->d_blk;
+            a.blk = phase == 0 ? b->d_blk + (k + 1) : (phase == 4 ? b->d_blk + 2 * (k + 1) : b->d_blk);
             a.n_lat = k;
-            a.blocks = phase == 0 ? nb_if : nb_nodes;
+            a.blocks = phase == 0 ? nb_if : (phase == 4 ? nb64 : nb_nodes);
             a.t = t;
             a.flag = l0->d_flag;
             a.stream = l0->stream;

@@ -284,10 +284,11 @@ class Lattice:
         _check(lib().rlbm_set_timing(self.handle, 1 if on else 0))
 
     def kernel_times(self):
-        ms = (c_double * 3)()
-        cnt = (c_int64 * 3)()
-        _check(lib().rlbm_kernel_times(self.handle, ms, cnt, 3))
-        return {name: (ms[k], cnt[k]) for k, name in enumerate(("boundary", "moments", "collide"))}
+        ms = (c_double * 5)()
+        cnt = (c_int64 * 5)()
+        _check(lib().rlbm_kernel_times(self.handle, ms, cnt, 5))
+        return {name: (ms[k], cnt[k])
+                for k, name in enumerate(("boundary", "local", "chem", "grad", "update"))}
 
 
 class Batch:

@@ -31,20 +31,24 @@ struct Codec;
 
 template <>
 struct Codec<double> {
-    static __device__ __forceinline__ double ld(const void* p, size_t idx, const double*, int) {
+    template <typename RP>
+    static __device__ __forceinline__ double ld(const void* p, size_t idx, RP, int) {
         return static_cast<const double*>(p)[idx];
     }
-    static __device__ __forceinline__ void st(void* p, size_t idx, double v, const double*, int) {
+    template <typename RP>
+    static __device__ __forceinline__ void st(void* p, size_t idx, double v, RP, int) {
         static_cast<double*>(p)[idx] = v;
     }
 };
 
 template <>
 struct Codec<float> {
-    static __device__ __forceinline__ double ld(const void* p, size_t idx, const double* ref, int li) {
+    template <typename RP>
+    static __device__ __forceinline__ double ld(const void* p, size_t idx, RP ref, int li) {
         return (double)static_cast<const float*>(p)[idx] + ref[li];
     }
-    static __device__ __forceinline__ void st(void* p, size_t idx, double v, const double* ref, int li) {
+    template <typename RP>
+    static __device__ __forceinline__ void st(void* p, size_t idx, double v, RP ref, int li) {
         static_cast<float*>(p)[idx] = __double2float_rn(v - ref[li]);
     }
 };
@@ -124,6 +128,7 @@ __device__ __forceinline__ void pull_offsets(const LatDev& L, int x, int y, int 
 }
 
 __device__ __forceinline__ int sel3(int c, int m, int z, int p) { return c < 0 ? m : (c == 0 ? z : p); }
+__device__ __forceinline__ double sel3d(int c, double m, double z, double p) { return c < 0 ? m : (c == 0 ? z : p); }
 
 template <int M>
 __device__ __forceinline__ int lat_of(int a, int slaved) { return a - (a > slaved ? 1 : 0); }
@@ -136,6 +141,15 @@ __device__ __forceinline__ double ldpop(const LatDev& L, const void* src, int k,
     const int li = l * Q + i;
     if (k >= 0) return Codec<S>::ld(L.bcbuf, (size_t)li * L.n_if + k, L.ref, li);
     return Codec<S>::ld(src, (size_t)li * L.N + node_off, L.ref, li);
+}
+
+// Raw stored value (FP64, or FP32 deviation) of population (l, i) at node
+// offset off after advection and boundary reconstruction.
+template <typename S>
+__device__ __forceinline__ S ld_raw_off(const LatDev& L, const void* src, int k, int off, int l, int i) {
+    const int li = l * Q + i;
+    if (k >= 0) return static_cast<const S*>(L.bcbuf)[(size_t)li * L.n_if + k];
+    return static_cast<const S*>(src)[(size_t)li * L.N + off];
 }
 
 template <int M>
@@ -180,15 +194,29 @@ __device__ __forceinline__ void node_moments(const LatDev& L, const void* src, i
             if (cy * cz) m.P[5] += cy * cz > 0 ? f : -f;
         }
     }
-    // species lattices, one at a time
+    // species lattices, one at a time, the next one's loads in flight while
+    // the current one is summed
+    S cur[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        cur[i] = ld_raw_off<S>(L, src, k, node + o.x[cx_of(i) + 1] + o.y[cy_of(i) + 1] + o.z[cz_of(i) + 1], 0, i);
 #pragma unroll 1
     for (int l = 0; l < M - 1; ++l) {
+        reload_barrier();
+        const RLBM_CONST double* ref = as_const(L.ref) + opaque_zero();
+        S nxt[Q];
+        if (l + 1 < M - 1) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                nxt[i] = ld_raw_off<S>(L, src, k, node + o.x[cx_of(i) + 1] + o.y[cy_of(i) + 1] + o.z[cz_of(i) + 1],
+                                       l + 1, i);
+        }
         double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
-            const int off = node + o.x[cx + 1] + o.y[cy + 1] + o.z[cz + 1];
-            const double v = ldpop<S>(L, src, k, off, l, i);
+            double v = (double)cur[i];
+            if constexpr (sizeof(S) == 4) v += ref[l * Q + i];
             r += v;
             if (FULL) {
                 if (cx) jx += cx > 0 ? v : -v;
@@ -201,6 +229,8 @@ __device__ __forceinline__ void node_moments(const LatDev& L, const void* src, i
         for (int c = 0; c < M; ++c) {
             if (c == a) { m.rho_a[c] = r; m.j_a[c][0] = jx; m.j_a[c][1] = jy; m.j_a[c][2] = jz; }
         }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
     }
     double rs = m.rho, jsx = m.j[0], jsy = m.j[1], jsz = m.j[2];
 #pragma unroll
@@ -223,7 +253,7 @@ __device__ __forceinline__ void node_moments(const LatDev& L, const void* src, i
 // A is strictly row diagonally dominant (margin 1), so no pivoting is needed.
 // V holds u_a - u on entry and the diffusion velocities on exit.
 template <int M>
-__device__ __forceinline__ void sm_solve_lu(const MechDev& mc, const double* Y, double common,
+__device__ __forceinline__ void sm_solve_lu(MechC mc, const double* Y, double common,
                                             const double* inv_tau, double (*V)[3]) {
     double Uu[M][M];
     double inv_diag[M];
@@ -274,7 +304,7 @@ __global__ __launch_bounds__(256) void k_local(const LatDev* __restrict__ lats, 
     if (t >= L.t_end) return;
     const int node = (b - blk[lj]) * 256 + threadIdx.x;
     if (node >= L.N) return;
-    const MechDev& mc = *L.mech;
+    MechC mc = *as_const(L.mech);
     const void* src = L.pop[(L.parity0 + t) & 1];
     const int x = node % L.nx, r = node / L.nx, y = r % L.ny, z = r / L.ny;
     PullOff o;
@@ -410,7 +440,7 @@ __global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, c
     if (t >= L.t_end) return;
     const int node = (b - blk[lj]) * 256 + threadIdx.x;
     if (node >= L.N) return;
-    const MechDev& mc = *L.mech;
+    MechC mc = *as_const(L.mech);
     double* prm = L.prm;
     const size_t N = (size_t)L.N;
     double rho_a[M], drho[M];
@@ -514,10 +544,11 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
     const int local = b - blk[lj];
     const int node0 = (local / 3) * UPD_NODES;
     const int lane = threadIdx.x % UPD_NODES;
-    const int grp = (local % 3) * UPD_WAVES + threadIdx.x / UPD_NODES;
+    // the velocity group is uniform across the wave
+    const int grp = (local % 3) * UPD_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x / UPD_NODES);
     const int node = node0 + lane;
     const bool valid = node < L.N;
-    const MechDev& mc = *L.mech;
+    MechC mc = *as_const(L.mech);
     const int par = (L.parity0 + t) & 1;
     const void* src = L.pop[par];
     void* dst = L.pop[par ^ 1];
@@ -531,16 +562,12 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
     pull_offsets(L, x, y, z, o);
     const int c1 = grp % 3 - 1, c2 = grp / 3 - 1;
     const int offyz = node + sel3(c1, o.y[0], 0, o.y[2]) + sel3(c2, o.z[0], 0, o.z[2]);
-    // populations of this thread's three velocities, loaded up front
-    S fin[3][M + 1];
+    // populations of the first of the three velocities, loaded before staging
+    S fin[M + 1];
     if (valid) {
+        const int i0 = 9 * (c2 + 1) + 3 * (c1 + 1);
 #pragma unroll
-        for (int cxi = 0; cxi < 3; ++cxi) {
-            const int i = 9 * (c2 + 1) + 3 * (c1 + 1) + cxi;
-            const int off = offyz + o.x[cxi];
-#pragma unroll
-            for (int l = 0; l <= M; ++l) fin[cxi][l] = ld_raw<S>(L, src, k, off, l, i);
-        }
+        for (int l = 0; l <= M; ++l) fin[l] = ld_raw<S>(L, src, k, offyz + o.x[0], l, i0);
     }
     for (int idx = threadIdx.x; idx < NR * UPD_NODES; idx += UPD_THREADS) {
         const int row = idx / UPD_NODES, j = idx % UPD_NODES;
@@ -549,70 +576,40 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
     }
     __syncthreads();
     if (!valid) return;
-
-    const double rho = sp[PRM_RHO][lane];
-    const double u[3] = {sp[PRM_U][lane], sp[PRM_U + 1][lane], sp[PRM_U + 2][lane]};
-    const double T = sp[PRM_T][lane];
-    const double U = sp[PRM_UINT][lane];
-    const double th = sp[PRM_TH][lane];
-    const double omega = sp[PRM_OMEGA][lane];
-    const double common = sp[PRM_COMMON][lane];
     const int GR = prm_grad(M);
-    double d[3], Qv[3];
-    {
-        const double wq = sp[PRM_WQ][lane], cc = sp[PRM_CC][lane];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            d[a] = sp[GR + a][lane];
-            Qv[a] = sp[PRM_QB + a][lane] + wq * (-0.5 * u[a] * d[a]) + cc * sp[GR + 3 + a][lane];
-        }
-    }
-    const double u2[3] = {u[0] * u[0], u[1] * u[1], u[2] * u[2]};
-    const double exf = (2.0 - omega) / (2.0 * rho * omega);
-    double hX[3];
-#pragma unroll
-    for (int dd = 0; dd < 3; ++dd) hX[dd] = th + u2[dd] + exf * d[dd];   // P^ex (eq. Pex)
-    const double fyz = psi_rt(c1, u[1], hX[1]) * psi_rt(c2, u[2], hX[2]);
-    GeqAxis gax, gay, gaz;
-    geq_axis(u[0], th, gax);
-    geq_axis(u[1], th, gay);
-    geq_axis(u[2], th, gaz);
-    const double Wy = c1 < 0 ? gay.W[0] : (c1 == 0 ? gay.W[1] : gay.W[2]);
-    const double ky = c1 < 0 ? gay.k[0] : (c1 == 0 ? gay.k[1] : gay.k[2]);
-    const double Wz = c2 < 0 ? gaz.W[0] : (c2 == 0 ? gaz.W[1] : gaz.W[2]);
-    const double kz = c2 < 0 ? gaz.k[0] : (c2 == 0 ? gaz.k[1] : gaz.k[2]);
-    const double wyz = Wy * Wz, kyz = ky * Wz + Wy * kz;
-    const double fcm = common / rho;             // F_ai = common Y_a sum_b K_ab D_bi
 
-    // y/z product-form factors of every species: equilibrium (xi = u) and
-    // quasi-equilibrium (xi = u + V_b, eq. xiPstar2), the latter scaled by rho_b
-    double pe[M], ps[M];
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-        const int r0 = PRM_SP + 6 * a;
-        const double tha = mc.Ra[a] * T;
-        const double ey = psi_rt(c1, u[1], u2[1] + tha);
-        const double ez = psi_rt(c2, u[2], u2[2] + tha);
-        const double xy = u[1] + sp[r0 + 2][lane], xz = u[2] + sp[r0 + 3][lane];
-        pe[a] = ey * ez;
-        ps[a] = sp[r0][lane] * psi_rt(c1, xy, xy * xy + tha) * psi_rt(c2, xz, xz * xz + tha);
-    }
-#pragma unroll
+#pragma unroll 1
     for (int cxi = 0; cxi < 3; ++cxi) {
         reload_barrier();
+        MechC mc = in_loop(*as_const(L.mech));
+        const RLBM_CONST double* ref = as_const(L.ref) + opaque_zero();
         const int c0 = cxi - 1;
         const int i = 9 * (c2 + 1) + 3 * (c1 + 1) + cxi;
-        double W[M], D[M];
+        // prefetch the next velocity's populations
+        S fnx[M + 1];
+        if (cxi < 2) {
+            const int off = offyz + (cxi == 0 ? o.x[1] : o.x[2]);
+#pragma unroll
+            for (int l = 0; l <= M; ++l) fnx[l] = ld_raw<S>(L, src, k, off, l, i + 1);
+        }
+        const double rho = sp[PRM_RHO][lane];
+        const double T = sp[PRM_T][lane];
+        const double ux = sp[PRM_U][lane], uy = sp[PRM_U + 1][lane], uz = sp[PRM_U + 2][lane];
+        const double th = sp[PRM_TH][lane];
+        // species equilibria (xi = u) and quasi-equilibria (xi = u + V_b,
+        // eq. xiPstar2): D_b = f_bi^eq - f_bi^*
+        double D[M];
 #pragma unroll
         for (int a = 0; a < M; ++a) {
             const int r0 = PRM_SP + 6 * a;
             const double tha = mc.Ra[a] * T;
-            const double ex = c0 == 0 ? 1.0 - u2[0] - tha : 0.5 * (u2[0] + tha + c0 * u[0]);
-            const double xx = u[0] + sp[r0 + 1][lane];
-            const double sx = c0 == 0 ? 1.0 - xx * xx - tha : 0.5 * (xx * xx + tha + c0 * xx);
-            W[a] = pe[a] * ex;
-            D[a] = sp[r0][lane] * W[a] - ps[a] * sx;      // f_bi^eq - f_bi^*
+            const double ra = sp[r0][lane];
+            const double vx = ux + sp[r0 + 1][lane], vy = uy + sp[r0 + 2][lane], vz = uz + sp[r0 + 3][lane];
+            const double we = psi_rt(c0, ux, ux * ux + tha) * psi_rt(c1, uy, uy * uy + tha) * psi_rt(c2, uz, uz * uz + tha);
+            const double ws = psi_rt(c0, vx, vx * vx + tha) * psi_rt(c1, vy, vy * vy + tha) * psi_rt(c2, vz, vz * vz + tha);
+            D[a] = ra * (we - ws);
         }
+        const double fcm = sp[PRM_COMMON][lane] / rho;   // F_ai = common Y_a sum_b K_ab D_bi
         // species (eq. finalNumericalEquationsReactive with eq. fStar)
 #pragma unroll
         for (int a = 0; a < M; ++a) {
@@ -623,35 +620,57 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
             for (int c = 0; c < M; ++c)
                 if (c != a) F += mc.Kab[a][c] * D[c];
             const double ra = sp[r0][lane], be = sp[r0 + 4][lane], dr = sp[r0 + 5][lane];
+            const double tha = mc.Ra[a] * T;
+            const double W = psi_rt(c0, ux, ux * ux + tha) * psi_rt(c1, uy, uy * uy + tha) * psi_rt(c2, uz, uz * uz + tha);
             F *= fcm * ra;
             const int l = lat_of<M>(a, s);
             double f = 0.0;
 #pragma unroll
             for (int ll = 0; ll < M - 1; ++ll)
-                if (ll == l) f = (double)fin[cxi][ll];
+                if (ll == l) f = (double)fin[ll];
             const int li = l * Q + i;
-            if constexpr (sizeof(S) == 4) f += L.ref[li];
-            const double out = f + 2.0 * be * (ra * W[a] - f) + (be - 1.0) * F + W[a] * dr;
-            Codec<S>::st(dst, (size_t)li * N + node, out, L.ref, li);
+            if constexpr (sizeof(S) == 4) f += ref[li];
+            const double out = f + 2.0 * be * (ra * W - f) + (be - 1.0) * F + W * dr;
+            Codec<S>::st(dst, (size_t)li * N + node, out, ref, li);
         }
-        // momentum lattice, extended equilibrium (eqs. f, feqmix)
+        const double omega = sp[PRM_OMEGA][lane];
+        const double dx = sp[GR][lane], dy = sp[GR + 1][lane], dz = sp[GR + 2][lane];
+        // momentum lattice, extended equilibrium (eqs. f, feqmix, Pex)
         {
+            const double exf = (2.0 - omega) / (2.0 * rho * omega);
             const int li = (M - 1) * Q + i;
-            double f = (double)fin[cxi][M - 1];
-            if constexpr (sizeof(S) == 4) f += L.ref[li];
-            const double ex = c0 == 0 ? 1.0 - hX[0] : 0.5 * (hX[0] + c0 * u[0]);
-            Codec<S>::st(dst, (size_t)li * N + node, f + omega * (rho * ex * fyz - f), L.ref, li);
+            double f = (double)fin[M - 1];
+            if constexpr (sizeof(S) == 4) f += ref[li];
+            const double fe = rho * psi_rt(c0, ux, th + ux * ux + exf * dx) * psi_rt(c1, uy, th + uy * uy + exf * dy) *
+                              psi_rt(c2, uz, th + uz * uz + exf * dz);
+            Codec<S>::st(dst, (size_t)li * N + node, f + omega * (fe - f), ref, li);
         }
         // energy lattice (eqs. g, geq_i, gstar)
         {
+            GeqAxis gax, gay, gaz;
+            geq_axis(ux, th, gax);
+            geq_axis(uy, th, gay);
+            geq_axis(uz, th, gaz);
+            const double Wx = sel3d(c0, gax.W[0], gax.W[1], gax.W[2]), kx = sel3d(c0, gax.k[0], gax.k[1], gax.k[2]);
+            const double Wy = sel3d(c1, gay.W[0], gay.W[1], gay.W[2]), ky = sel3d(c1, gay.k[0], gay.k[1], gay.k[2]);
+            const double Wz = sel3d(c2, gaz.W[0], gaz.W[1], gaz.W[2]), kz = sel3d(c2, gaz.k[0], gaz.k[1], gaz.k[2]);
+            const double U = sp[PRM_UINT][lane];
+            const double geq = rho * (U * Wx * Wy * Wz + kx * Wy * Wz + Wx * (ky * Wz + Wy * kz));
             const int li = M * Q + i;
-            double g = (double)fin[cxi][M];
-            if constexpr (sizeof(S) == 4) g += L.ref[li];
-            const double geq = rho * (U * gax.W[cxi] * wyz + gax.k[cxi] * wyz + gax.W[cxi] * kyz);
+            double g = (double)fin[M];
+            if constexpr (sizeof(S) == 4) g += ref[li];
             double out = g + omega * (geq - g);
-            if (c0 * c0 + c1 * c1 + c2 * c2 == 1) out += 0.5 * (c0 * Qv[0] + c1 * Qv[1] + c2 * Qv[2]);
-            Codec<S>::st(dst, (size_t)li * N + node, out, L.ref, li);
+            if (c0 * c0 + c1 * c1 + c2 * c2 == 1) {
+                const double wq = sp[PRM_WQ][lane], cc = sp[PRM_CC][lane];
+                const double Qx = sp[PRM_QB][lane] + wq * (-0.5 * ux * dx) + cc * sp[GR + 3][lane];
+                const double Qy = sp[PRM_QB + 1][lane] + wq * (-0.5 * uy * dy) + cc * sp[GR + 4][lane];
+                const double Qz = sp[PRM_QB + 2][lane] + wq * (-0.5 * uz * dz) + cc * sp[GR + 5][lane];
+                out += 0.5 * (c0 * Qx + c1 * Qy + c2 * Qz);
+            }
+            Codec<S>::st(dst, (size_t)li * N + node, out, ref, li);
         }
+#pragma unroll
+        for (int l = 0; l <= M; ++l) fin[l] = fnx[l];
     }
 }
 
@@ -671,7 +690,7 @@ struct EqState {
 };
 
 template <int M>
-__device__ __forceinline__ void eq_prepare(const MechDev& mc, EqState<M>& e, double T) {
+__device__ __forceinline__ void eq_prepare(MechC mc, EqState<M>& e, double T) {
     e.th = mc.R_univ * mix_inv_m<M>(mc, e.Y) * T;
     e.U = mix_U<M>(mc, e.Y, T);
     geq_axis(e.u[0], e.th, e.gx);
@@ -680,7 +699,7 @@ __device__ __forceinline__ void eq_prepare(const MechDev& mc, EqState<M>& e, dou
 }
 
 template <int M>
-__device__ __forceinline__ double eq_value(const MechDev& mc, const EqState<M>& e, double T, int l, int slaved,
+__device__ __forceinline__ double eq_value(MechC mc, const EqState<M>& e, double T, int l, int slaved,
                                            int i) {
     const int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);
     if (l == M) return geq_i(i, e.rho, e.U, e.gx, e.gy, e.gz);
@@ -709,7 +728,7 @@ __global__ __launch_bounds__(64) void k_boundary(const LatDev* __restrict__ lats
     if (t >= L.t_end) return;
     const int k = (b - blk[lj]) * 64 + threadIdx.x;
     if (k >= L.n_if) return;
-    const MechDev& mc = *L.mech;
+    MechC mc = *as_const(L.mech);
     const void* src = L.pop[(L.parity0 + t) & 1];
     const long long node = L.if_node[k];
     const unsigned Dm = L.if_mask[k];
@@ -922,7 +941,7 @@ __global__ __launch_bounds__(256) void k_init(const LatDev* __restrict__ lat, co
     const LatDev& L = *lat;
     const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
     if (node >= L.N) return;
-    const MechDev& mc = *L.mech;
+    MechC mc = *as_const(L.mech);
     const size_t N = (size_t)L.N;
     void* dst = L.pop[L.parity0];
     EqState<M> e;
@@ -974,7 +993,7 @@ __global__ void k_refs(const LatDev* __restrict__ lat, double* __restrict__ ref,
     const LatDev& L = *lat;
     const int li = blockIdx.x * blockDim.x + threadIdx.x;
     if (li >= (M + 1) * Q) return;
-    const MechDev& mc = *L.mech;
+    MechC mc = *as_const(L.mech);
     EqState<M> e;
     e.rho = rho;
     e.u[0] = e.u[1] = e.u[2] = 0.0;
@@ -994,7 +1013,7 @@ __global__ __launch_bounds__(256) void k_fields(const LatDev* __restrict__ lat, 
     const LatDev& L = *lat;
     const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
     if (node >= L.N) return;
-    const MechDev& mc = *L.mech;
+    MechC mc = *as_const(L.mech);
     const size_t N = (size_t)L.N;
     const void* src = L.pop[(L.parity0 + t) & 1];
     const int s = L.slaved;
@@ -1052,7 +1071,7 @@ template <int M, typename S>
 __global__ __launch_bounds__(256) void k_invariants(const LatDev* __restrict__ lat, long long t,
                                                     double* __restrict__ partial, int nv) {
     const LatDev& L = *lat;
-    const MechDev& mc = *L.mech;
+    MechC mc = *as_const(L.mech);
     const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
     const size_t N = (size_t)L.N;
     const int s = L.slaved;

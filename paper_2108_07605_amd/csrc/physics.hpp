@@ -88,6 +88,30 @@ __host__ __device__ constexpr int prm_rows(int M) { return PRM_SP + 6 * M + 6; }
 // registers across loop iterations, which would cost occupancy.
 __device__ __forceinline__ void reload_barrier() { asm volatile("" ::: "memory"); }
 
+// Read-only kernel inputs (mechanism, reference populations) are accessed
+// through the constant address space: the compiler may then always use
+// scalar loads for them, also after a reload barrier.
+#define RLBM_CONST __attribute__((address_space(4)))
+using MechC = const RLBM_CONST MechDev&;
+template <typename T>
+__device__ __forceinline__ const RLBM_CONST T* as_const(const T* p) {
+    return (const RLBM_CONST T*)((unsigned long long)p);
+}
+
+// A zero the compiler cannot see through, held in a scalar register.  Adding
+// it to a constant-space pointer inside a loop keeps the loads through that
+// pointer in the loop (scalar loads) instead of hoisting every constant into
+// registers up front, which would cost occupancy.
+__device__ __forceinline__ int opaque_zero() {
+    int z;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+    return z;
+}
+template <typename T>
+__device__ __forceinline__ const RLBM_CONST T& in_loop(const RLBM_CONST T& r) {
+    return *(&r + opaque_zero());
+}
+
 // ---------------------------------------------------------------------------
 // product form (section 2.2, eqs. phi0, phiPlus, phis, prod)
 // ---------------------------------------------------------------------------
@@ -131,7 +155,7 @@ __device__ __forceinline__ double geq_i(int i, double rho, double U, const GeqAx
 // thermochemistry (section 3.1, eqs. specUa, U, temperature)
 // ---------------------------------------------------------------------------
 template <int M>
-__device__ __forceinline__ double mix_inv_m(const MechDev& mc, const double* Y) {
+__device__ __forceinline__ double mix_inv_m(MechC mc, const double* Y) {
     double s = 0.0;
 #pragma unroll
     for (int a = 0; a < M; ++a) s += Y[a] * mc.inv_m[a];
@@ -140,7 +164,7 @@ __device__ __forceinline__ double mix_inv_m(const MechDev& mc, const double* Y) 
 
 // Collapse sum_a Y_a U_a(T) into one quintic and solve for T by Newton.
 template <int M>
-__device__ __forceinline__ double solve_T(const MechDev& mc, const double* Y, double U,
+__device__ __forceinline__ double solve_T(MechC mc, const double* Y, double U,
                                           double T, int* fail) {
     double c[6];
 #pragma unroll
@@ -163,29 +187,29 @@ __device__ __forceinline__ double solve_T(const MechDev& mc, const double* Y, do
 }
 
 template <int M>
-__device__ __forceinline__ double mix_U(const MechDev& mc, const double* Y, double T) {
+__device__ __forceinline__ double mix_U(MechC mc, const double* Y, double T) {
     double s = 0.0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-        const double* u = mc.uc[a];
+        const RLBM_CONST double* u = mc.uc[a];
         s += Y[a] * (u[0] + T * (u[1] + T * (u[2] + T * (u[3] + T * (u[4] + T * u[5])))));
     }
     return s;
 }
 
-__device__ __forceinline__ double species_U(const MechDev& mc, int a, double T) {
-    const double* u = mc.uc[a];
+__device__ __forceinline__ double species_U(MechC mc, int a, double T) {
+    const RLBM_CONST double* u = mc.uc[a];
     return u[0] + T * (u[1] + T * (u[2] + T * (u[3] + T * (u[4] + T * u[5]))));
 }
 
-__device__ __forceinline__ double species_cv(const MechDev& mc, int a, double T) {
-    const double* c = mc.cvc[a];
+__device__ __forceinline__ double species_cv(MechC mc, int a, double T) {
+    const RLBM_CONST double* c = mc.cvc[a];
     return c[0] + T * (c[1] + T * (c[2] + T * (c[3] + T * c[4])));
 }
 
 // g_a/(R_univ T) = h/(R T) - s/R for one species.
-__device__ __forceinline__ double gibbs_RT(const MechDev& mc, int a, double T, double lnT, double invT) {
-    const double* n = mc.nasa[a];
+__device__ __forceinline__ double gibbs_RT(MechC mc, int a, double T, double lnT, double invT) {
+    const RLBM_CONST double* n = mc.nasa[a];
     const double h = n[0] + T * (n[1] * 0.5 + T * (n[2] * (1.0 / 3.0) + T * (n[3] * 0.25 + T * n[4] * 0.2))) +
                      n[5] * invT;
     const double s = n[0] * lnT + T * (n[1] + T * (n[2] * 0.5 + T * (n[3] * (1.0 / 3.0) + T * n[4] * 0.25))) +
@@ -197,8 +221,9 @@ __device__ __forceinline__ double gibbs_RT(const MechDev& mc, int a, double T, d
 // chemistry (section 2.3, eq. R3): production rates and sub-steps
 // ---------------------------------------------------------------------------
 template <int M>
-__device__ __forceinline__ void production_rates(const MechDev& mc, const double* rho_a, double T,
+__device__ __forceinline__ void production_rates(MechC mc0, const double* rho_a, double T,
                                                  double* wdot) {
+    MechC mc = mc0;
 #pragma unroll
     for (int a = 0; a < M; ++a) wdot[a] = 0.0;
     const int R = mc.R;
@@ -213,7 +238,7 @@ __device__ __forceinline__ void production_rates(const MechDev& mc, const double
     }
     const double lnc = mc.ln_cstd - lnT;
     for (int r = 0; r < R; ++r) {
-        reload_barrier();
+        MechC mc = in_loop(mc0);
         const double lnkf = mc.lnA[r] + mc.beta[r] * lnT - mc.Ta[r] * invT;
         double fwd = exp(lnkf);
 #pragma unroll
@@ -248,12 +273,12 @@ __device__ __forceinline__ void production_rates(const MechDev& mc, const double
 
 // Delta rho_a over one step by l forward-Euler sub-steps at frozen U.
 template <int M>
-__device__ __forceinline__ void reaction_increment(const MechDev& mc, const double* rho_a, double rho,
+__device__ __forceinline__ void reaction_increment(MechC mc0, const double* rho_a, double rho,
                                                    double U, double T, int l, double* drho, int* fail) {
     double cur[M], w[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) cur[a] = rho_a[a];
-    if (mc.R == 0) {
+    if (mc0.R == 0) {
 #pragma unroll
         for (int a = 0; a < M; ++a) drho[a] = 0.0;
         return;
@@ -262,7 +287,7 @@ __device__ __forceinline__ void reaction_increment(const MechDev& mc, const doub
     const double inv_rho = 1.0 / rho;
     double Ts = T;
     for (int s = 0; s < l; ++s) {
-        reload_barrier();
+        MechC mc = in_loop(mc0);
         if (s > 0) {
             double Y[M];
 #pragma unroll

@@ -65,44 +65,6 @@ __device__ __forceinline__ int find_lattice(const int* blk, int n_lat, int b) {
     return lo;
 }
 
-struct Nbr {
-    int x, y, z;
-    int xw[3], yw[3], zw[3];   // wrapped x-1, x, x+1 (pull: bulk nodes never leave the box)
-    int xg[3], yg[3], zg[3];   // gradient stencil: wrapped (periodic) or clamped
-};
-
-__device__ __forceinline__ void make_nbr(const LatDev& L, long long node, Nbr& n) {
-    const int nx = L.nx, ny = L.ny, nz = L.nz;
-    n.x = (int)(node % nx);
-    const long long r = node / nx;
-    n.y = (int)(r % ny);
-    n.z = (int)(r / ny);
-    const int d[3] = {n.x, n.y, n.z};
-    const int e[3] = {nx, ny, nz};
-    int* w[3] = {n.xw, n.yw, n.zw};
-    int* g[3] = {n.xg, n.yg, n.zg};
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        const int v = d[ax], m = e[ax];
-        const int vm = v == 0 ? m - 1 : v - 1;
-        const int vp = v == m - 1 ? 0 : v + 1;
-        w[ax][0] = vm; w[ax][1] = v; w[ax][2] = vp;
-        if (L.per[ax]) {
-            g[ax][0] = vm; g[ax][1] = v; g[ax][2] = vp;
-        } else {
-            g[ax][0] = v == 0 ? 0 : v - 1;
-            g[ax][1] = v;
-            g[ax][2] = v == m - 1 ? m - 1 : v + 1;
-        }
-    }
-}
-
-// Source node of velocity i for a pull at this node: x - c_i (wrapped).
-__device__ __forceinline__ long long pull_src(const LatDev& L, const Nbr& n, int i) {
-    const int xs = n.xw[1 - cx_of(i)], ys = n.yw[1 - cy_of(i)], zs = n.zw[1 - cz_of(i)];
-    return ((long long)zs * L.ny + ys) * L.nx + xs;
-}
-
 // ---------------------------------------------------------------------------
 // pull-advection addressing for the hot kernels
 // ---------------------------------------------------------------------------
@@ -677,46 +639,104 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
 // ---------------------------------------------------------------------------
 // boundary reconstruction (section 4)
 // ---------------------------------------------------------------------------
-// Equilibrium of lattice l at velocity i for the state (rho, Y, u, T) with
-// species velocities us (section 4.1, eqs. faEqGeneral, fEqGeneral,
-// gEqGeneral).
-template <int M>
+// Equilibrium of lattice l at velocity i for the state (rho, Y, u, T)
+// (section 4.1, eqs. faEqGeneral, fEqGeneral, gEqGeneral).  With SPV the
+// species equilibria use per-species velocities us (the wall's local state,
+// eq. locua); otherwise the mixture velocity.
+template <int M, bool SPV>
 struct EqState {
-    double rho, th, U;
-    double Y[M];
+    double rho, th, U, T;
     double u[3];
-    double us[M][3];
-    GeqAxis gx, gy, gz;
+    double Y[M];
+    double us[SPV ? M : 1][3];
 };
 
-template <int M>
-__device__ __forceinline__ void eq_prepare(MechC mc, EqState<M>& e, double T) {
+template <int M, bool SPV>
+__device__ __forceinline__ void eq_prepare(MechC mc, EqState<M, SPV>& e, double T) {
+    e.T = T;
     e.th = mc.R_univ * mix_inv_m<M>(mc, e.Y) * T;
     e.U = mix_U<M>(mc, e.Y, T);
-    geq_axis(e.u[0], e.th, e.gx);
-    geq_axis(e.u[1], e.th, e.gy);
-    geq_axis(e.u[2], e.th, e.gz);
 }
 
-template <int M>
-__device__ __forceinline__ double eq_value(MechC mc, const EqState<M>& e, double T, int l, int slaved,
-                                           int i) {
+template <int M, bool SPV>
+__device__ __forceinline__ double eq_value(MechC mc, const EqState<M, SPV>& e, int l, int slaved, int i) {
     const int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);
-    if (l == M) return geq_i(i, e.rho, e.U, e.gx, e.gy, e.gz);
+    if (l == M) {
+        GeqAxis gx, gy, gz;
+        geq_axis(e.u[0], e.th, gx);
+        geq_axis(e.u[1], e.th, gy);
+        geq_axis(e.u[2], e.th, gz);
+        const double Wx = sel3d(c0, gx.W[0], gx.W[1], gx.W[2]), kx = sel3d(c0, gx.k[0], gx.k[1], gx.k[2]);
+        const double Wy = sel3d(c1, gy.W[0], gy.W[1], gy.W[2]), ky = sel3d(c1, gy.k[0], gy.k[1], gy.k[2]);
+        const double Wz = sel3d(c2, gz.W[0], gz.W[1], gz.W[2]), kz = sel3d(c2, gz.k[0], gz.k[1], gz.k[2]);
+        return e.rho * (e.U * Wx * Wy * Wz + kx * Wy * Wz + Wx * (ky * Wz + Wy * kz));
+    }
     if (l == M - 1)
         return e.rho * psi(c0, e.u[0], e.u[0] * e.u[0] + e.th) * psi(c1, e.u[1], e.u[1] * e.u[1] + e.th) *
                psi(c2, e.u[2], e.u[2] * e.u[2] + e.th);
     const int a = l + (l >= slaved ? 1 : 0);
-    double Ya = 0.0, tha = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0;
+    double Ya = 0.0, tha = 0.0, w0 = e.u[0], w1 = e.u[1], w2 = e.u[2];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
         if (c == a) {
             Ya = e.Y[c];
-            tha = mc.Ra[c] * T;
-            w0 = e.us[c][0]; w1 = e.us[c][1]; w2 = e.us[c][2];
+            tha = mc.Ra[c] * e.T;
+            if constexpr (SPV) { w0 = e.us[c][0]; w1 = e.us[c][1]; w2 = e.us[c][2]; }
         }
     }
     return e.rho * Ya * psi(c0, w0, w0 * w0 + tha) * psi(c1, w1, w1 * w1 + tha) * psi(c2, w2, w2 * w2 + tha);
+}
+
+// Local state (section 4, steps "local"): moments of the populations with
+// the incoming links D set to the imposed equilibrium A and the outgoing
+// links from advection, temperature by eq. temperature.
+template <int M, bool SPV, typename S, typename Streamed, typename Incoming, bool ASPV>
+__device__ __forceinline__ void bc_local(MechC mc, const EqState<M, ASPV>& A, int s, Streamed streamed,
+                                         Incoming incoming, EqState<M, SPV>& Lc, int* fail) {
+    double rl = 0.0, jl[3] = {0.0, 0.0, 0.0}, El = 0.0, ra[M], ja[M][3];
+#pragma unroll
+    for (int a = 0; a < M; ++a) ra[a] = ja[a][0] = ja[a][1] = ja[a][2] = 0.0;
+#pragma unroll 1
+    for (int l = 0; l <= M; ++l) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 1
+        for (int i = 0; i < Q; ++i) {
+            const double v = incoming(i) ? eq_value<M, ASPV>(mc, A, l, s, i) : streamed(l, i);
+            s0 += v; s1 += v * cx_of(i); s2 += v * cy_of(i); s3 += v * cz_of(i);
+        }
+        if (l == M) {
+            El = s0;
+        } else if (l == M - 1) {
+            rl = s0; jl[0] = s1; jl[1] = s2; jl[2] = s3;
+        } else {
+            const int a = l + (l >= s ? 1 : 0);
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+                if (c == a) { ra[c] = s0; ja[c][0] = s1; ja[c][1] = s2; ja[c][2] = s3; }
+        }
+    }
+    double rs = rl, j0 = jl[0], j1 = jl[1], j2 = jl[2];
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+        if (a != s) { rs -= ra[a]; j0 -= ja[a][0]; j1 -= ja[a][1]; j2 -= ja[a][2]; }
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+        if (a == s) { ra[a] = rs; ja[a][0] = j0; ja[a][1] = j1; ja[a][2] = j2; }
+    Lc.rho = rl;
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) Lc.u[dd] = jl[dd] / rl;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        Lc.Y[a] = ra[a] / rl;
+        if constexpr (SPV) {
+            const bool small = ra[a] <= 1e-14 * rl;
+#pragma unroll
+            for (int dd = 0; dd < 3; ++dd) Lc.us[a][dd] = small ? Lc.u[dd] : ja[a][dd] / ra[a];
+        }
+    }
+    const double Ul = El / rl - 0.5 * (Lc.u[0] * Lc.u[0] + Lc.u[1] * Lc.u[1] + Lc.u[2] * Lc.u[2]);
+    const double T_l = solve_T<M>(mc, Lc.Y, Ul, A.T, fail);
+    eq_prepare<M, SPV>(mc, Lc, T_l);
 }
 
 template <int M, typename S>
@@ -735,198 +755,163 @@ __global__ __launch_bounds__(64) void k_boundary(const LatDev* __restrict__ lats
     const int type = L.if_type[k];
     const int s = L.slaved;
     const size_t N = (size_t)L.N;
-    Nbr n;
-    make_nbr(L, node, n);
+    const int x = (int)(node % L.nx), r = (int)(node / L.nx), y = r % L.ny, z = r / L.ny;
+    PullOff o;
+    pull_offsets(L, x, y, z, o);
     const int nL = M + 1;
     int fail = 0;
 
+    // population (l, i) after advection (outgoing links; the source lies in
+    // the box for every velocity not in D)
     auto streamed = [&](int l, int i) -> double {
         const int li = l * Q + i;
-        return Codec<S>::ld(src, (size_t)li * N + pull_src(L, n, i), L.ref, li);
+        const int off = (int)node + sel3(cx_of(i), o.x[0], 0, o.x[2]) + sel3(cy_of(i), o.y[0], 0, o.y[2]) +
+                        sel3(cz_of(i), o.z[0], 0, o.z[2]);
+        return Codec<S>::ld(src, (size_t)li * N + off, L.ref, li);
     };
     auto incoming = [&](int i) -> bool { return (Dm >> i) & 1u; };
+    auto put = [&](int l, int i, double v) {
+        Codec<S>::st(L.bcbuf, (size_t)(l * Q + i) * L.n_if + k, v, L.ref, l * Q + i);
+    };
 
-    EqState<M> A;     // imposed equilibrium: target (wall), inlet or outlet state
-    double T_A;
     if (type == RLBM_FACE_WALL) {
-        // TMS step 1: bounce-back density and mass fractions (eqs. BBrho, BBY)
-        double rb = 0.0, rY[M];
+        // Tamm-Mott-Smith wall (section 4.2.2)
+        EqState<M, false> A;   // target: bounce-back rho and Y, u^tgt = 0, T^tgt
+        {
+            // step 1: bounce-back density and mass fractions (eqs. BBrho, BBY)
+            double rb = 0.0, rY[M];
 #pragma unroll
-        for (int a = 0; a < M; ++a) rY[a] = 0.0;
-        for (int l = 0; l < nL - 1; ++l) {
-            double sum = 0.0;
+            for (int a = 0; a < M; ++a) rY[a] = 0.0;
+#pragma unroll 1
+            for (int l = 0; l < nL - 1; ++l) {
+                double sum = 0.0;
+#pragma unroll 1
+                for (int i = 0; i < Q; ++i) {
+                    const int lo = l * Q + (Q - 1 - i);
+                    sum += incoming(i) ? Codec<S>::ld(src, (size_t)lo * N + node, L.ref, lo) : streamed(l, i);
+                }
+                if (l == M - 1) {
+                    rb = sum;
+                } else {
+                    const int a = l + (l >= s ? 1 : 0);
+#pragma unroll
+                    for (int c = 0; c < M; ++c)
+                        if (c == a) rY[c] = sum;
+                }
+            }
+            double rs = rb;
+#pragma unroll
+            for (int a = 0; a < M; ++a)
+                if (a != s) rs -= rY[a];
+#pragma unroll
+            for (int a = 0; a < M; ++a) A.Y[a] = (a == s ? rs : rY[a]) / rb;
+            A.rho = rb;
+            A.u[0] = A.u[1] = A.u[2] = 0.0;
+            eq_prepare<M, false>(mc, A, L.if_T[k]);
+        }
+        // step 3: local state with species velocities (eqs. locRho..locT)
+        EqState<M, true> Lc;
+        bc_local<M, true, S>(mc, A, s, streamed, incoming, Lc, &fail);
+        // step 4 (eqs. ftms, gtms, fatms)
+#pragma unroll 1
+        for (int l = 0; l < nL; ++l)
+#pragma unroll 1
             for (int i = 0; i < Q; ++i) {
-                const int li = l * Q + i;
-                sum += incoming(i) ? Codec<S>::ld(src, (size_t)(l * Q + (Q - 1 - i)) * N + node, L.ref,
-                                                  l * Q + (Q - 1 - i))
-                                   : streamed(l, i);
-                (void)li;
+                const double a_eq = eq_value<M, false>(mc, A, l, s, i);
+                const double l_eq = eq_value<M, true>(mc, Lc, l, s, i);
+                put(l, i, incoming(i) ? 2.0 * a_eq - l_eq : a_eq + streamed(l, i) - l_eq);
             }
-            if (l == M - 1) {
-                rb = sum;
-            } else {
-                const int a = l + (l >= s ? 1 : 0);
-#pragma unroll
-                for (int c = 0; c < M; ++c)
-                    if (c == a) rY[c] = sum;
-            }
-        }
-        double rs = rb;
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-            if (a != s) rs -= rY[a];
-#pragma unroll
-        for (int a = 0; a < M; ++a) {
-            if (a == s) rY[a] = rs;
-            A.Y[a] = rY[a] / rb;
-        }
-        A.rho = rb;
-        A.u[0] = A.u[1] = A.u[2] = 0.0;
-#pragma unroll
-        for (int a = 0; a < M; ++a) A.us[a][0] = A.us[a][1] = A.us[a][2] = 0.0;
-        T_A = L.if_T[k];
     } else if (type == RLBM_FACE_INLET) {
+        // flux inlet (section 4.3)
+        EqState<M, false> A;   // inlet equilibrium (eqs. in_f, in_g, in_fa)
         A.rho = L.rho_in;
         A.u[0] = L.u_in; A.u[1] = 0.0; A.u[2] = 0.0;
 #pragma unroll
-        for (int a = 0; a < M; ++a) {
-            A.Y[a] = L.Y_in[a];
-            A.us[a][0] = L.u_in; A.us[a][1] = 0.0; A.us[a][2] = 0.0;
-        }
-        T_A = L.T_in;
-    } else {
-        // outlet: LODI state from the previous outlet state and the previous
-        // post-boundary moments of the first interior node (section 4.4)
-        const int ko = L.if_out[k];
-        const size_t No = (size_t)L.n_out;
-        double* os = L.out_state;
-        const double rho0 = os[0 * No + ko];
-        const double u0[3] = {os[1 * No + ko], os[2 * No + ko], os[3 * No + ko]};
-        const double T0 = os[4 * No + ko];
-        double Y0[M], Y1[M];
-        const size_t in = (size_t)node - 1;
-#pragma unroll
-        for (int a = 0; a < M; ++a) {
-            Y0[a] = os[(5 + a) * No + ko];
-            Y1[a] = L.aux[(AUX_Y + a) * N + in];
-        }
-        const double rho1 = L.aux[AUX_RHO * N + in];
-        const double u1[3] = {L.aux[(AUX_U + 0) * N + in], L.aux[(AUX_U + 1) * N + in], L.aux[(AUX_U + 2) * N + in]};
-        const double T1 = L.aux[AUX_T * N + in];
-        const double R0 = mc.R_univ * mix_inv_m<M>(mc, Y0);
-        const double P0 = rho0 * R0 * T0;
-        const double P1 = rho1 * mc.R_univ * mix_inv_m<M>(mc, Y1) * T1;
-        double Cv = 0.0;
-#pragma unroll
-        for (int a = 0; a < M; ++a) Cv += Y0[a] * species_cv(mc, a, T0);
-        const double gam = (Cv + R0) / Cv;
-        const double c = sqrt(gam * P0 / rho0);
-        const double un = u0[0];
-        const double Ma = un / c;
-        const double L1 = L.sigma * (1.0 - Ma * Ma) * c / (double)L.nx * (P0 - L.P_inf);
-        const double L2 = un * (c * c * (rho0 - rho1) - (P0 - P1));
-        const double L3 = un * (u0[1] - u1[1]);
-        const double L4 = un * (u0[2] - u1[2]);
-        const double L5 = (un + c) * ((P0 - P1) + rho0 * c * (u0[0] - u1[0]));
-        const double rho_o = rho0 - (L2 + 0.5 * (L5 + L1)) / (c * c);
-        const double P_o = P0 - 0.5 * (L5 + L1);
-        A.rho = rho_o;
-        A.u[0] = un - (L5 - L1) / (2.0 * rho0 * c);
-        A.u[1] = u0[1] - L3;
-        A.u[2] = u0[2] - L4;
-#pragma unroll
-        for (int a = 0; a < M; ++a) {
-            A.Y[a] = Y0[a] - un * (Y0[a] - Y1[a]);
-            A.us[a][0] = A.u[0]; A.us[a][1] = A.u[1]; A.us[a][2] = A.u[2];
-        }
-        T_A = P_o / (rho_o * mc.R_univ * mix_inv_m<M>(mc, A.Y));
-        os[0 * No + ko] = A.rho;
-        os[1 * No + ko] = A.u[0]; os[2 * No + ko] = A.u[1]; os[3 * No + ko] = A.u[2];
-        os[4 * No + ko] = T_A;
-#pragma unroll
-        for (int a = 0; a < M; ++a) os[(5 + a) * No + ko] = A.Y[a];
-    }
-    eq_prepare<M>(mc, A, T_A);
-
-    // local state with the incoming links set to the imposed equilibrium
-    // (eqs. locRho..locT, inletlocRho..inletlocT, outletlocRho..outletlocT)
-    EqState<M> Lc;
-    double rl = 0.0, jl[3] = {0.0, 0.0, 0.0}, El = 0.0, ra[M], ja[M][3];
-#pragma unroll
-    for (int a = 0; a < M; ++a) ra[a] = ja[a][0] = ja[a][1] = ja[a][2] = 0.0;
-    for (int l = 0; l < nL; ++l) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        for (int i = 0; i < Q; ++i) {
-            const double v = incoming(i) ? eq_value<M>(mc, A, T_A, l, s, i) : streamed(l, i);
-            s0 += v; s1 += v * cx_of(i); s2 += v * cy_of(i); s3 += v * cz_of(i);
-        }
-        if (l == M) {
-            El = s0;
-        } else if (l == M - 1) {
-            rl = s0; jl[0] = s1; jl[1] = s2; jl[2] = s3;
-        } else {
-            const int a = l + (l >= s ? 1 : 0);
-#pragma unroll
-            for (int c = 0; c < M; ++c)
-                if (c == a) { ra[c] = s0; ja[c][0] = s1; ja[c][1] = s2; ja[c][2] = s3; }
-        }
-    }
-    {
-        double rs = rl, j0 = jl[0], j1 = jl[1], j2 = jl[2];
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-            if (a != s) { rs -= ra[a]; j0 -= ja[a][0]; j1 -= ja[a][1]; j2 -= ja[a][2]; }
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-            if (a == s) { ra[a] = rs; ja[a][0] = j0; ja[a][1] = j1; ja[a][2] = j2; }
-    }
-    Lc.rho = rl;
-#pragma unroll
-    for (int dd = 0; dd < 3; ++dd) Lc.u[dd] = jl[dd] / rl;
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-        Lc.Y[a] = ra[a] / rl;
-        const bool small = ra[a] <= 1e-14 * rl;
-#pragma unroll
-        for (int dd = 0; dd < 3; ++dd) {
-            // TMS local species equilibria use the species velocities (eq. locua);
-            // inlet and outlet local equilibria use the mixture velocity.
-            Lc.us[a][dd] = (type == RLBM_FACE_WALL && !small) ? ja[a][dd] / ra[a] : Lc.u[dd];
-        }
-    }
-    const double Ul = El / rl - 0.5 * (Lc.u[0] * Lc.u[0] + Lc.u[1] * Lc.u[1] + Lc.u[2] * Lc.u[2]);
-    const double T_l = solve_T<M>(mc, Lc.Y, Ul, T_A, &fail);
-    eq_prepare<M>(mc, Lc, T_l);
-
-    // inlet target: local density and composition at the imposed u, T (eqs. in_tgt_*)
-    EqState<M> Tg;
-    const bool inlet = type == RLBM_FACE_INLET;
-    if (inlet) {
+        for (int a = 0; a < M; ++a) A.Y[a] = L.Y_in[a];
+        eq_prepare<M, false>(mc, A, L.T_in);
+        EqState<M, false> Lc;  // local state (eqs. inletlocRho..inletlocT)
+        bc_local<M, false, S>(mc, A, s, streamed, incoming, Lc, &fail);
+        // target: local density and composition at the imposed u, T (eqs. in_tgt_*)
+        EqState<M, false> Tg;
         Tg.rho = Lc.rho;
         Tg.u[0] = L.u_in; Tg.u[1] = 0.0; Tg.u[2] = 0.0;
 #pragma unroll
-        for (int a = 0; a < M; ++a) {
-            Tg.Y[a] = Lc.Y[a];
-            Tg.us[a][0] = L.u_in; Tg.us[a][1] = 0.0; Tg.us[a][2] = 0.0;
-        }
-        eq_prepare<M>(mc, Tg, L.T_in);
-    }
-
-    // final populations (eqs. ftms/gtms/fatms, f_inlet/g_inlet/fa_inlet,
-    // f_outlet/g_outlet/fa_outlet)
-    for (int l = 0; l < nL; ++l) {
-        for (int i = 0; i < Q; ++i) {
-            const double a_eq = eq_value<M>(mc, A, T_A, l, s, i);
-            const double l_eq = eq_value<M>(mc, Lc, T_l, l, s, i);
-            double out;
-            if (inlet) {
-                const double t_eq = eq_value<M>(mc, Tg, L.T_in, l, s, i);
-                out = incoming(i) ? t_eq + a_eq - l_eq : t_eq + streamed(l, i) - l_eq;
-            } else {
-                out = incoming(i) ? 2.0 * a_eq - l_eq : a_eq + streamed(l, i) - l_eq;
+        for (int a = 0; a < M; ++a) Tg.Y[a] = Lc.Y[a];
+        eq_prepare<M, false>(mc, Tg, L.T_in);
+        // (eqs. f_inlet, g_inlet, fa_inlet)
+#pragma unroll 1
+        for (int l = 0; l < nL; ++l)
+#pragma unroll 1
+            for (int i = 0; i < Q; ++i) {
+                const double t_eq = eq_value<M, false>(mc, Tg, l, s, i);
+                const double l_eq = eq_value<M, false>(mc, Lc, l, s, i);
+                put(l, i, incoming(i) ? t_eq + eq_value<M, false>(mc, A, l, s, i) - l_eq
+                                      : t_eq + streamed(l, i) - l_eq);
             }
-            Codec<S>::st(L.bcbuf, (size_t)(l * Q + i) * L.n_if + k, out, L.ref, l * Q + i);
+    } else {
+        // outlet (section 4.4): LODI state from the previous outlet state and
+        // the previous post-boundary moments of the first interior node
+        EqState<M, false> A;
+        {
+            const int ko = L.if_out[k];
+            const size_t No = (size_t)L.n_out;
+            double* os = L.out_state;
+            const double rho0 = os[0 * No + ko];
+            const double u0[3] = {os[1 * No + ko], os[2 * No + ko], os[3 * No + ko]};
+            const double T0 = os[4 * No + ko];
+            double Y0[M], Y1[M];
+            const size_t in = (size_t)node - 1;
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+                Y0[a] = os[(5 + a) * No + ko];
+                Y1[a] = L.aux[(AUX_Y + a) * N + in];
+            }
+            const double rho1 = L.aux[AUX_RHO * N + in];
+            const double u1[3] = {L.aux[(AUX_U + 0) * N + in], L.aux[(AUX_U + 1) * N + in],
+                                  L.aux[(AUX_U + 2) * N + in]};
+            const double T1 = L.aux[AUX_T * N + in];
+            const double R0 = mc.R_univ * mix_inv_m<M>(mc, Y0);
+            const double P0 = rho0 * R0 * T0;
+            const double P1 = rho1 * mc.R_univ * mix_inv_m<M>(mc, Y1) * T1;
+            double Cv = 0.0;
+#pragma unroll
+            for (int a = 0; a < M; ++a) Cv += Y0[a] * species_cv(mc, a, T0);
+            const double gam = (Cv + R0) / Cv;
+            const double c = sqrt(gam * P0 / rho0);
+            const double un = u0[0];
+            const double Ma = un / c;
+            const double L1 = L.sigma * (1.0 - Ma * Ma) * c / (double)L.nx * (P0 - L.P_inf);
+            const double L2 = un * (c * c * (rho0 - rho1) - (P0 - P1));
+            const double L3 = un * (u0[1] - u1[1]);
+            const double L4 = un * (u0[2] - u1[2]);
+            const double L5 = (un + c) * ((P0 - P1) + rho0 * c * (u0[0] - u1[0]));
+            const double rho_o = rho0 - (L2 + 0.5 * (L5 + L1)) / (c * c);
+            const double P_o = P0 - 0.5 * (L5 + L1);
+            A.rho = rho_o;
+            A.u[0] = un - (L5 - L1) / (2.0 * rho0 * c);
+            A.u[1] = u0[1] - L3;
+            A.u[2] = u0[2] - L4;
+#pragma unroll
+            for (int a = 0; a < M; ++a) A.Y[a] = Y0[a] - un * (Y0[a] - Y1[a]);   // eq. convectiveBC
+            const double T_o = P_o / (rho_o * mc.R_univ * mix_inv_m<M>(mc, A.Y));
+            os[0 * No + ko] = A.rho;
+            os[1 * No + ko] = A.u[0]; os[2 * No + ko] = A.u[1]; os[3 * No + ko] = A.u[2];
+            os[4 * No + ko] = T_o;
+#pragma unroll
+            for (int a = 0; a < M; ++a) os[(5 + a) * No + ko] = A.Y[a];
+            eq_prepare<M, false>(mc, A, T_o);
         }
+        EqState<M, false> Lc;  // local state (eqs. outletlocRho..outletlocT)
+        bc_local<M, false, S>(mc, A, s, streamed, incoming, Lc, &fail);
+        // (eqs. f_outlet, g_outlet, fa_outlet)
+#pragma unroll 1
+        for (int l = 0; l < nL; ++l)
+#pragma unroll 1
+            for (int i = 0; i < Q; ++i) {
+                const double a_eq = eq_value<M, false>(mc, A, l, s, i);
+                const double l_eq = eq_value<M, false>(mc, Lc, l, s, i);
+                put(l, i, incoming(i) ? 2.0 * a_eq - l_eq : a_eq + streamed(l, i) - l_eq);
+            }
     }
     if (fail) atomicOr(flag, 1);
 }
@@ -944,21 +929,18 @@ __global__ __launch_bounds__(256) void k_init(const LatDev* __restrict__ lat, co
     MechC mc = *as_const(L.mech);
     const size_t N = (size_t)L.N;
     void* dst = L.pop[L.parity0];
-    EqState<M> e;
+    EqState<M, false> e;
     e.rho = rho_in[node];
     const double T = T_in[node];
 #pragma unroll
     for (int dd = 0; dd < 3; ++dd) e.u[dd] = u_in[dd * N + node];
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-        e.Y[a] = Y_in[a * N + node];
-        e.us[a][0] = e.u[0]; e.us[a][1] = e.u[1]; e.us[a][2] = e.u[2];
-    }
-    eq_prepare<M>(mc, e, T);
+    for (int a = 0; a < M; ++a) e.Y[a] = Y_in[a * N + node];
+    eq_prepare<M, false>(mc, e, T);
     for (int l = 0; l <= M; ++l)
         for (int i = 0; i < Q; ++i) {
             const int li = l * Q + i;
-            Codec<S>::st(dst, (size_t)li * N + node, eq_value<M>(mc, e, T, l, L.slaved, i), L.ref, li);
+            Codec<S>::st(dst, (size_t)li * N + node, eq_value<M, false>(mc, e, l, L.slaved, i), L.ref, li);
         }
     double* aux = L.aux;
     aux[AUX_RHO * N + node] = e.rho;
@@ -994,16 +976,13 @@ __global__ void k_refs(const LatDev* __restrict__ lat, double* __restrict__ ref,
     const int li = blockIdx.x * blockDim.x + threadIdx.x;
     if (li >= (M + 1) * Q) return;
     MechC mc = *as_const(L.mech);
-    EqState<M> e;
+    EqState<M, false> e;
     e.rho = rho;
     e.u[0] = e.u[1] = e.u[2] = 0.0;
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-        e.Y[a] = Y[a];
-        e.us[a][0] = e.us[a][1] = e.us[a][2] = 0.0;
-    }
-    eq_prepare<M>(mc, e, T);
-    ref[li] = eq_value<M>(mc, e, T, li / Q, L.slaved, li % Q);
+    for (int a = 0; a < M; ++a) e.Y[a] = Y[a];
+    eq_prepare<M, false>(mc, e, T);
+    ref[li] = eq_value<M, false>(mc, e, li / Q, L.slaved, li % Q);
 }
 
 template <int M, typename S>

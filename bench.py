@@ -20,7 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_update_channel3d_512x64x64_traffic.json")
 
 
 def _kernel_hash():
@@ -31,17 +31,19 @@ def _kernel_hash():
     return h.hexdigest()[:16]
 
 
-def _traffic(storage):
-    """HBM bytes per collide launch from committed rocprofv3 counter runs, or
-    None when absent or taken on different kernel sources."""
+def _traffic(storage, kernel, dims):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counter runs
+    (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a copy kernel of
+    known size), or None when absent, taken on another workload, or taken on
+    different kernel sources."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != _kernel_hash():
+    if t.get("kernel_hash") != _kernel_hash() or t.get("dims") != list(dims):
         return None
-    rec = t.get(storage)
+    rec = t.get(storage, {}).get(kernel)
     return None if rec is None else rec.get("bytes_per_launch")
 
 
@@ -52,9 +54,13 @@ def _time_storage(case, storage, steps, warmup):
     lat.set_state()
     stream = lat.stream
     lat.step(warmup)
+    lat.kernel_times()                  # drop anything recorded so far
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    # per-kernel durations: the library records HIP events around every
+    # launch on the lattice stream during the timed steps themselves
+    lat.set_timing(True)
     e0.record(stream)
     t0 = time.perf_counter()
     lat.step(steps)
@@ -62,11 +68,8 @@ def _time_storage(case, storage, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    # per-kernel durations: HIP events around every launch on the lattice stream
-    lat.set_timing(True)
-    lat.step(steps)
-    kt = lat.kernel_times()
     lat.set_timing(False)
+    kt = lat.kernel_times()
     inv = lat.invariants()
     ok = inv[-1] == 0.0
     del lat
@@ -78,22 +81,36 @@ def _cpu_baseline(budget_s=20.0):
     """The oracle, as it stands, on a bounded sample of the same workload: a
     64x16x16 channel with the same mechanism and boundaries, stepped until
     about budget_s of CPU time."""
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from threadpoolctl import threadpool_limits
     from oracle import Oracle
     from paper_2108_07605_amd import workloads as wl
     case = wl.make_case("channel3d", nx=64, ny=16, nz=16)
-    o = Oracle(case)
-    o.step(1)
-    t0 = time.perf_counter()
-    n = 0
-    while time.perf_counter() - t0 < budget_s:
+    with threadpool_limits(limits=1):      # BLAS/OpenMP pools of NumPy: one thread
+        o = Oracle(case)
         o.step(1)
-        n += 1
-    dt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < budget_s:
+            o.step(1)
+            n += 1
+        dt = time.perf_counter() - t0
     N = case["nx"] * case["ny"] * case["nz"]
     return {"value": N * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"channel3d 64x16x16 (16384 nodes), same mechanism and boundaries, "
                       f"{n} steps in {dt:.1f} s, FP64 NumPy, 1 thread"}
+
+
+def _copy_probe(mib):
+    """A copy kernel of known size: 5 launches of an out-of-place elementwise
+    copy reading and writing mib MiB each."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.rand(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
 
 
 def main():
@@ -107,7 +124,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--storage", default="both", choices=["both", "f32dev", "f64"])
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.copy_probe:
+        _copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see the sharding note in DESIGN.md)", file=sys.stderr)
@@ -127,10 +150,13 @@ def main():
         bytes_node = 2 * L * 27 * s                      # populations read + written once
         ms_step = r["ms_total"] / args.steps
         mlups = N / (ms_step * 1e-3) / 1e6
-        coll_name = max(r["kernels"], key=lambda kk: r["kernels"][kk][0]); coll_ms, coll_n = r["kernels"][coll_name]
+        # dominant kernel: the largest share of the step; it is the collision
+        # (k_update), whose algorithmic traffic is the population read + write
+        coll_name = max(r["kernels"], key=lambda kk: r["kernels"][kk][0])
+        coll_ms, coll_n = r["kernels"][coll_name]
         coll_avg = coll_ms / max(coll_n, 1)
         achieved = bytes_node * N / (coll_avg * 1e-3) / 1e9
-        traffic = _traffic(st)
+        traffic = _traffic(st, "k_" + coll_name, (case["nx"], case["ny"], case["nz"]))
         res[st] = {
             "mlups": mlups, "ms_per_step": ms_step, "finite": r["finite"],
             "kernels_ms_avg": {k: v[0] / max(v[1], 1) for k, v in r["kernels"].items()},

@@ -471,168 +471,263 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, c
 }
 
 // ---------------------------------------------------------------------------
-// k_update: the collision of every stored lattice.  A block of three waves
-// covers 64 consecutive nodes and three of the nine velocity groups
-// (c_y, c_z) = (g % 3 - 1, g / 3 - 1), one group per wave, i.e. three
-// velocities per thread; the per-node record is staged in LDS.
+// k_update: the collision of every stored lattice (section 2.3 eq.
+// finalNumericalEquationsReactive, section 3.2 eq. f, section 3.3 eq. g).
+// A block of three waves covers 64 consecutive nodes; wave w takes the nine
+// velocities with c_z = w - 1, one node per lane.  The per-node record is
+// staged once in LDS with the species in slot order (the stored species in
+// lattice order, then the slaved one), so every per-species quantity sits at
+// a compile-time index.  Product-form factors along y and z are formed once
+// per row of three velocities (fixed c_y, c_z); the x factor per velocity.
 // ---------------------------------------------------------------------------
 constexpr int UPD_NODES = 64;
 constexpr int UPD_WAVES = 3;
 constexpr int UPD_THREADS = UPD_WAVES * UPD_NODES;
 
-__device__ __forceinline__ double psi_rt(int c, double xi, double P) {
-    const double side = 0.5 * (P + (c > 0 ? xi : -xi));
-    return c == 0 ? 1.0 - P : side;
+// Product-form factor with a compile-time velocity component C.
+template <int C>
+__device__ __forceinline__ double psi_c(double xi, double P) {
+    if constexpr (C == 0) return 1.0 - P;
+    else if constexpr (C > 0) return 0.5 * (P + xi);
+    else return 0.5 * (P - xi);
 }
 
-// Raw stored value (FP64, or FP32 deviation) of population (l, i) after
-// advection and boundary reconstruction.
+// Product-form factor with a wave-uniform component c, as a + b xi + d P.
+struct PsiCoef {
+    double a, b, d;
+};
+__device__ __forceinline__ PsiCoef psi_coef(int c) {
+    PsiCoef r;
+    r.a = c == 0 ? 1.0 : 0.0;
+    r.b = 0.5 * (double)c;
+    r.d = c == 0 ? -1.0 : 0.5;
+    return r;
+}
+__device__ __forceinline__ double psi_u(const PsiCoef& k, double xi, double P) {
+    return fma(k.b, xi, fma(k.d, P, k.a));
+}
+// Energy-equilibrium axis factors (W, k) of eq. geq_i for a uniform c.
+__device__ __forceinline__ void geq_wk(int c, double u, double th, double& W, double& k) {
+    const double u2 = u * u;
+    const double P = th + u2;
+    const double o1 = th * u + 0.5 * u2 * u;
+    const double o2 = th * th + 2.5 * th * u2 + 0.5 * u2 * u2;
+    const PsiCoef pc = psi_coef(c);
+    W = psi_u(pc, u, P);
+    // k_0 = u^2/2 - o2, k_{+-1} = (o2 +- o1)/2
+    k = c == 0 ? 0.5 * u2 - o2 : 0.5 * (o2 + (double)c * o1);
+}
+
+// Byte-offset addressing: a uniform base plus a 32-bit per-lane offset keeps
+// every population access in the scalar-base form (no 64-bit address math).
 template <typename S>
-__device__ __forceinline__ S ld_raw(const LatDev& L, const void* src, int k, int off, int l, int i) {
-    const int li = l * Q + i;
-    if (k >= 0) return static_cast<const S*>(L.bcbuf)[(size_t)li * L.n_if + k];
-    return static_cast<const S*>(src)[(size_t)li * L.N + off];
+__device__ __forceinline__ S ld_at(const RLBM_GLOBAL S* base, int idx) {
+    return *(const RLBM_GLOBAL S*)((const RLBM_GLOBAL char*)base + (unsigned)(idx * (int)sizeof(S)));
+}
+template <typename S>
+__device__ __forceinline__ void st_at(RLBM_GLOBAL S* base, int idx, S v) {
+    *(RLBM_GLOBAL S*)((RLBM_GLOBAL char*)base + (unsigned)(idx * (int)sizeof(S))) = v;
 }
 
 template <int M, typename S>
 __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                                         int n_lat, long long t, int* __restrict__ flag) {
     constexpr int NR = prm_rows(M);
-    __shared__ double sp[NR][UPD_NODES];          // per-node record
+    constexpr int NL = M + 1;        // stored lattices
+    __shared__ double sp[NR][UPD_NODES];
     const int b = blockIdx.x;
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
     if (t >= L.t_end) return;
-    const int local = b - blk[lj];
-    const int node0 = (local / 3) * UPD_NODES;
+    const int node0 = (b - blk[lj]) * UPD_NODES;
     const int lane = threadIdx.x % UPD_NODES;
-    // the velocity group is uniform across the wave
-    const int grp = (local % 3) * UPD_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x / UPD_NODES);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / UPD_NODES);
+    const int c2 = wave - 1;
     const int node = node0 + lane;
-    const bool valid = node < L.N;
-    MechC mc = *as_const(L.mech);
-    const int par = (L.parity0 + t) & 1;
-    const void* src = L.pop[par];
-    void* dst = L.pop[par ^ 1];
+    const int N = (int)L.N;
+    const bool valid = node < N;
     const int s = L.slaved;
-    const size_t N = (size_t)L.N;
-    const double* prm = L.prm;
+    const int par = (L.parity0 + t) & 1;
+    const RLBM_GLOBAL S* src = as_global(static_cast<const S*>(L.pop[par]));
+    RLBM_GLOBAL S* dst = as_global(static_cast<S*>(L.pop[par ^ 1]));
+    const RLBM_GLOBAL S* bc = as_global(static_cast<const S*>(L.bcbuf));
+    const RLBM_GLOBAL double* prm = as_global(L.prm);
+    const int nif = L.n_if;
 
-    const int x = node % L.nx, r = node / L.nx, y = r % L.ny, z = r / L.ny;
-    const int k = (L.n_if && valid) ? L.if_index[node] : -1;
-    PullOff o;
-    pull_offsets(L, x, y, z, o);
-    const int c1 = grp % 3 - 1, c2 = grp / 3 - 1;
-    const int offyz = node + sel3(c1, o.y[0], 0, o.y[2]) + sel3(c2, o.z[0], 0, o.z[2]);
-    // populations of the first of the three velocities, loaded before staging
-    S fin[M + 1];
-    if (valid) {
-        const int i0 = 9 * (c2 + 1) + 3 * (c1 + 1);
-#pragma unroll
-        for (int l = 0; l <= M; ++l) fin[l] = ld_raw<S>(L, src, k, offyz + o.x[0], l, i0);
-    }
+    // stage the record; species rows in slot order
     for (int idx = threadIdx.x; idx < NR * UPD_NODES; idx += UPD_THREADS) {
         const int row = idx / UPD_NODES, j = idx % UPD_NODES;
+        int srow = row;
+        if (row >= PRM_SP && row < prm_grad(M)) {
+            const int slot = (row - PRM_SP) / 6, q = (row - PRM_SP) % 6;
+            const int a = slot < M - 1 ? slot + (slot >= s ? 1 : 0) : s;
+            srow = PRM_SP + 6 * a + q;
+        }
         const int nd = node0 + j;
-        sp[row][j] = nd < L.N ? prm[(size_t)row * N + nd] : 1.0;
+        sp[row][j] = nd < N ? prm[(size_t)srow * L.N + nd] : 1.0;
     }
+
+    int x = 0, y = 0, z = 0;
+    if (valid) { x = node % L.nx; const int r = node / L.nx; y = r % L.ny; z = r / L.ny; }
+    const int k = (nif && valid) ? as_global(L.if_index)[node] : -1;
+    const bool wave_if = __builtin_amdgcn_ballot_w64(k >= 0) != 0;   // uniform
+    PullOff o;
+    pull_offsets(L, x, y, z, o);
+    const int offz = node + sel3(c2, o.z[0], 0, o.z[2]);
+
+    // populations of velocity i at node offset off (after advection and
+    // boundary reconstruction)
+    auto load = [&](int i, int off, S* out) {
+        if (!wave_if) {
+#pragma unroll
+            for (int l = 0; l < NL; ++l) out[l] = ld_at(src + (size_t)(l * Q + i) * L.N, off);
+        } else {
+#pragma unroll
+            for (int l = 0; l < NL; ++l)
+                out[l] = k >= 0 ? bc[(size_t)(l * Q + i) * nif + k] : src[(size_t)(l * Q + i) * L.N + off];
+        }
+    };
+
+    S fin[NL];
+    const int i_first = 9 * (c2 + 1);
+    if (valid) load(i_first, offz + o.y[0] + o.x[0], fin);
     __syncthreads();
     if (!valid) return;
+
     const int GR = prm_grad(M);
+    // per-node values used by every velocity are re-read from LDS where they
+    // are needed; only the few derived ones stay in registers
+    const double exf = [&] {
+        const double w = sp[PRM_OMEGA][lane];
+        return (2.0 - w) / (2.0 * sp[PRM_RHO][lane] * w);
+    }();
+    const double fcm = sp[PRM_COMMON][lane] / sp[PRM_RHO][lane];   // F_ai = common Y_a sum_b K_ab D_bi
+    const PsiCoef pz = psi_coef(c2);
 
 #pragma unroll 1
-    for (int cxi = 0; cxi < 3; ++cxi) {
+    for (int c1 = -1; c1 <= 1; ++c1) {
         reload_barrier();
-        MechC mc = in_loop(*as_const(L.mech));
-        const RLBM_CONST double* ref = as_const(L.ref) + opaque_zero();
-        const int c0 = cxi - 1;
-        const int i = 9 * (c2 + 1) + 3 * (c1 + 1) + cxi;
-        // prefetch the next velocity's populations
-        S fnx[M + 1];
-        if (cxi < 2) {
-            const int off = offyz + (cxi == 0 ? o.x[1] : o.x[2]);
+        const RLBM_CONST double* Ra = as_const(L.slotc) + opaque_zero();   // [M] gas constants, slot order
+        const PsiCoef py = psi_coef(c1);
+        const int offyz = offz + sel3(c1, o.y[0], 0, o.y[2]);
+        const double T = sp[PRM_T][lane], th = sp[PRM_TH][lane];
+        const double uy = sp[PRM_U + 1][lane], uz = sp[PRM_U + 2][lane];
+        // y/z factors of the species equilibria (xi = u) and quasi-equilibria
+        // (xi = u + V_b, eq. xiPstar2)
+        double YZe[M], YZs[M];
 #pragma unroll
-            for (int l = 0; l <= M; ++l) fnx[l] = ld_raw<S>(L, src, k, off, l, i + 1);
+        for (int q = 0; q < M; ++q) {
+            const double tq = Ra[q] * T;
+            const double vy = uy + sp[PRM_SP + 6 * q + 2][lane], vz = uz + sp[PRM_SP + 6 * q + 3][lane];
+            YZe[q] = psi_u(py, uy, fma(uy, uy, tq)) * psi_u(pz, uz, fma(uz, uz, tq));
+            YZs[q] = psi_u(py, vy, fma(vy, vy, tq)) * psi_u(pz, vz, fma(vz, vz, tq));
         }
-        const double rho = sp[PRM_RHO][lane];
-        const double T = sp[PRM_T][lane];
-        const double ux = sp[PRM_U][lane], uy = sp[PRM_U + 1][lane], uz = sp[PRM_U + 2][lane];
-        const double th = sp[PRM_TH][lane];
-        // species equilibria (xi = u) and quasi-equilibria (xi = u + V_b,
-        // eq. xiPstar2): D_b = f_bi^eq - f_bi^*
-        double D[M];
-#pragma unroll
-        for (int a = 0; a < M; ++a) {
-            const int r0 = PRM_SP + 6 * a;
-            const double tha = mc.Ra[a] * T;
-            const double ra = sp[r0][lane];
-            const double vx = ux + sp[r0 + 1][lane], vy = uy + sp[r0 + 2][lane], vz = uz + sp[r0 + 3][lane];
-            const double we = psi_rt(c0, ux, ux * ux + tha) * psi_rt(c1, uy, uy * uy + tha) * psi_rt(c2, uz, uz * uz + tha);
-            const double ws = psi_rt(c0, vx, vx * vx + tha) * psi_rt(c1, vy, vy * vy + tha) * psi_rt(c2, vz, vz * vz + tha);
-            D[a] = ra * (we - ws);
-        }
-        const double fcm = sp[PRM_COMMON][lane] / rho;   // F_ai = common Y_a sum_b K_ab D_bi
-        // species (eq. finalNumericalEquationsReactive with eq. fStar)
-#pragma unroll
-        for (int a = 0; a < M; ++a) {
-            if (a == s) continue;
-            const int r0 = PRM_SP + 6 * a;
-            double F = 0.0;
-#pragma unroll
-            for (int c = 0; c < M; ++c)
-                if (c != a) F += mc.Kab[a][c] * D[c];
-            const double ra = sp[r0][lane], be = sp[r0 + 4][lane], dr = sp[r0 + 5][lane];
-            const double tha = mc.Ra[a] * T;
-            const double W = psi_rt(c0, ux, ux * ux + tha) * psi_rt(c1, uy, uy * uy + tha) * psi_rt(c2, uz, uz * uz + tha);
-            F *= fcm * ra;
-            const int l = lat_of<M>(a, s);
-            double f = 0.0;
-#pragma unroll
-            for (int ll = 0; ll < M - 1; ++ll)
-                if (ll == l) f = (double)fin[ll];
-            const int li = l * Q + i;
-            if constexpr (sizeof(S) == 4) f += ref[li];
-            const double out = f + 2.0 * be * (ra * W - f) + (be - 1.0) * F + W * dr;
-            Codec<S>::st(dst, (size_t)li * N + node, out, ref, li);
-        }
-        const double omega = sp[PRM_OMEGA][lane];
-        const double dx = sp[GR][lane], dy = sp[GR + 1][lane], dz = sp[GR + 2][lane];
-        // momentum lattice, extended equilibrium (eqs. f, feqmix, Pex)
-        {
-            const double exf = (2.0 - omega) / (2.0 * rho * omega);
-            const int li = (M - 1) * Q + i;
-            double f = (double)fin[M - 1];
-            if constexpr (sizeof(S) == 4) f += ref[li];
-            const double fe = rho * psi_rt(c0, ux, th + ux * ux + exf * dx) * psi_rt(c1, uy, th + uy * uy + exf * dy) *
-                              psi_rt(c2, uz, th + uz * uz + exf * dz);
-            Codec<S>::st(dst, (size_t)li * N + node, f + omega * (fe - f), ref, li);
-        }
-        // energy lattice (eqs. g, geq_i, gstar)
-        {
-            GeqAxis gax, gay, gaz;
-            geq_axis(ux, th, gax);
-            geq_axis(uy, th, gay);
-            geq_axis(uz, th, gaz);
-            const double Wx = sel3d(c0, gax.W[0], gax.W[1], gax.W[2]), kx = sel3d(c0, gax.k[0], gax.k[1], gax.k[2]);
-            const double Wy = sel3d(c1, gay.W[0], gay.W[1], gay.W[2]), ky = sel3d(c1, gay.k[0], gay.k[1], gay.k[2]);
-            const double Wz = sel3d(c2, gaz.W[0], gaz.W[1], gaz.W[2]), kz = sel3d(c2, gaz.k[0], gaz.k[1], gaz.k[2]);
-            const double U = sp[PRM_UINT][lane];
-            const double geq = rho * (U * Wx * Wy * Wz + kx * Wy * Wz + Wx * (ky * Wz + Wy * kz));
-            const int li = M * Q + i;
-            double g = (double)fin[M];
-            if constexpr (sizeof(S) == 4) g += ref[li];
-            double out = g + omega * (geq - g);
-            if (c0 * c0 + c1 * c1 + c2 * c2 == 1) {
-                const double wq = sp[PRM_WQ][lane], cc = sp[PRM_CC][lane];
-                const double Qx = sp[PRM_QB][lane] + wq * (-0.5 * ux * dx) + cc * sp[GR + 3][lane];
-                const double Qy = sp[PRM_QB + 1][lane] + wq * (-0.5 * uy * dy) + cc * sp[GR + 4][lane];
-                const double Qz = sp[PRM_QB + 2][lane] + wq * (-0.5 * uz * dz) + cc * sp[GR + 5][lane];
-                out += 0.5 * (c0 * Qx + c1 * Qy + c2 * Qz);
+        // momentum lattice: y/z factors of the extended equilibrium (eq. Pex)
+        const double Fyz = psi_u(py, uy, th + uy * uy + exf * sp[GR + 1][lane]) *
+                           psi_u(pz, uz, th + uz * uz + exf * sp[GR + 2][lane]);
+        // energy lattice: y/z factors of eq. geq_i
+        double Wy, ky, Wz, kz;
+        geq_wk(c1, uy, th, Wy, ky);
+        geq_wk(c2, uz, th, Wz, kz);
+        const double Wyz = Wy * Wz, kyz = ky * Wz + Wy * kz;
+        const int cyz2 = c1 * c1 + c2 * c2;
+
+        auto body = [&](auto c0t) {
+            constexpr int c0 = decltype(c0t)::value;
+            const int i = 9 * (c2 + 1) + 3 * (c1 + 1) + (c0 + 1);
+            // per-velocity re-reads of LDS and constants (cheap) instead of
+            // keeping them live across the three velocities
+            reload_barrier();
+            const RLBM_CONST double* slotc = as_const(L.slotc) + opaque_zero();
+            const RLBM_CONST double* Ra = slotc;
+            const RLBM_CONST double* Ks = slotc + M;
+            const RLBM_CONST double* ref = as_const(L.ref) + opaque_zero();
+            // prefetch the next velocity of this thread
+            S fnx[NL];
+            if constexpr (c0 < 1) {
+                load(i + 1, offyz + o.x[c0 + 2], fnx);
+            } else {
+                if (c1 < 1) load(i + 1, offyz + sel3(c1 + 1, o.y[0], 0, o.y[2]) - sel3(c1, o.y[0], 0, o.y[2]) + o.x[0], fnx);
             }
-            Codec<S>::st(dst, (size_t)li * N + node, out, ref, li);
-        }
+            const double T = sp[PRM_T][lane], ux = sp[PRM_U][lane];
+            double D[M], Xe[M];
 #pragma unroll
-        for (int l = 0; l <= M; ++l) fin[l] = fnx[l];
+            for (int q = 0; q < M; ++q) {
+                const double tq = Ra[q] * T;
+                const double vx = ux + sp[PRM_SP + 6 * q + 1][lane];
+                Xe[q] = psi_c<c0>(ux, fma(ux, ux, tq));
+                const double Xs = psi_c<c0>(vx, fma(vx, vx, tq));
+                D[q] = sp[PRM_SP + 6 * q][lane] * (Xe[q] * YZe[q] - Xs * YZs[q]);
+            }
+            // species (eq. finalNumericalEquationsReactive with eq. fStar)
+#pragma unroll
+            for (int j = 0; j < M - 1; ++j) {
+                double F = 0.0;
+#pragma unroll
+                for (int q = 0; q < M; ++q)
+                    if (q != j) F = fma(Ks[j * M + q], D[q], F);
+                const double ra = sp[PRM_SP + 6 * j][lane], be = sp[PRM_SP + 6 * j + 4][lane],
+                             dr = sp[PRM_SP + 6 * j + 5][lane];
+                const double W = Xe[j] * YZe[j];
+                const int li = j * Q + i;
+                double f = (double)fin[j];
+                if constexpr (sizeof(S) == 4) f += ref[li];
+                const double out = f + 2.0 * be * (ra * W - f) + (be - 1.0) * (fcm * ra * F) + W * dr;
+                if constexpr (sizeof(S) == 4) st_at(dst + (size_t)li * L.N, node, __double2float_rn(out - ref[li]));
+                else st_at(dst + (size_t)li * L.N, node, out);
+            }
+            const double rho = sp[PRM_RHO][lane], th = sp[PRM_TH][lane], omega = sp[PRM_OMEGA][lane];
+            // momentum lattice, extended equilibrium (eqs. f, feqmix, Pex)
+            {
+                const int li = (M - 1) * Q + i;
+                double f = (double)fin[M - 1];
+                if constexpr (sizeof(S) == 4) f += ref[li];
+                const double fe = rho * psi_c<c0>(ux, th + ux * ux + exf * sp[GR][lane]) * Fyz;
+                const double out = f + omega * (fe - f);
+                if constexpr (sizeof(S) == 4) st_at(dst + (size_t)li * L.N, node, __double2float_rn(out - ref[li]));
+                else st_at(dst + (size_t)li * L.N, node, out);
+            }
+            // energy lattice (eqs. g, geq_i, gstar)
+            {
+                const int li = M * Q + i;
+                double g = (double)fin[M];
+                if constexpr (sizeof(S) == 4) g += ref[li];
+                const double ux2 = ux * ux;
+                const double Wx = psi_c<c0>(ux, th + ux2);
+                double kx;
+                if constexpr (c0 == 0) {
+                    kx = 0.5 * ux2 - (th * th + 2.5 * th * ux2 + 0.5 * ux2 * ux2);
+                } else {
+                    const double o1 = th * ux + 0.5 * ux2 * ux;
+                    const double o2 = th * th + 2.5 * th * ux2 + 0.5 * ux2 * ux2;
+                    kx = 0.5 * (o2 + (double)c0 * o1);
+                }
+                const double geq = rho * (Wyz * (sp[PRM_UINT][lane] * Wx + kx) + Wx * kyz);
+                double out = g + omega * (geq - g);
+                // the singularity-free flux term on the six |c| = 1 velocities
+                const double wq = sp[PRM_WQ][lane], cc = sp[PRM_CC][lane];
+                if constexpr (c0 != 0) {
+                    if (cyz2 == 0)
+                        out += 0.5 * (double)c0 *
+                               (sp[PRM_QB][lane] - 0.5 * wq * ux * sp[GR][lane] + cc * sp[GR + 3][lane]);
+                } else {
+                    if (cyz2 == 1) {
+                        const int ax = c1 != 0 ? 1 : 2;   // uniform
+                        const double ua = sp[PRM_U + ax][lane];
+                        const double Qa = sp[PRM_QB + ax][lane] - 0.5 * wq * ua * sp[GR + ax][lane] +
+                                          cc * sp[GR + 3 + ax][lane];
+                        out += 0.5 * (double)(c1 + c2) * Qa;
+                    }
+                }
+                if constexpr (sizeof(S) == 4) st_at(dst + (size_t)li * L.N, node, __double2float_rn(out - ref[li]));
+                else st_at(dst + (size_t)li * L.N, node, out);
+            }
+#pragma unroll
+            for (int l = 0; l < NL; ++l) fin[l] = fnx[l];
+        };
+        body(std::integral_constant<int, -1>{});
+        body(std::integral_constant<int, 0>{});
+        body(std::integral_constant<int, 1>{});
     }
 }
 

@@ -65,6 +65,7 @@ struct LatDev {
     void* bcbuf;                // [L * 27][n_if] post-boundary populations (storage format)
     double* out_state;          // [5 + M][n_out]: rho, ux, uy, uz, T, Y
     const double* ref;          // [L * 27] reference populations (FP32 storage)
+    const double* slotc;        // [M + M * M] R_a and 1/(D_ref m_a m_b) in slot order (slaved species last)
     double rho_in, u_in, T_in, P_inf, sigma;
     double Y_in[MAXM];
     int parity0;                // buffer holding the current populations at t = 0
@@ -92,6 +93,17 @@ __device__ __forceinline__ void reload_barrier() { asm volatile("" ::: "memory")
 // through the constant address space: the compiler may then always use
 // scalar loads for them, also after a reload barrier.
 #define RLBM_CONST __attribute__((address_space(4)))
+// Device buffers reached through generic pointers in a struct are cast to the
+// global address space so loads and stores take the scalar-base form.
+#define RLBM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ RLBM_GLOBAL T* as_global(T* p) {
+    return (RLBM_GLOBAL T*)((unsigned long long)p);
+}
+template <typename T>
+__device__ __forceinline__ const RLBM_GLOBAL T* as_global(const T* p) {
+    return (const RLBM_GLOBAL T*)((unsigned long long)p);
+}
 using MechC = const RLBM_CONST MechDev&;
 template <typename T>
 __device__ __forceinline__ const RLBM_CONST T* as_const(const T* p) {

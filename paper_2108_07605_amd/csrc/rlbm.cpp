@@ -42,7 +42,7 @@ constexpr int NPHASE = 5;   // boundary, local, chemistry, gradients, update
 
 struct Plan {
     size_t off_lat, off_mech, off_blk, off_flag, off_ref, off_pop0, off_pop1, off_aux, off_prm, off_ifindex, off_ifnode,
-        off_ifmask, off_iftype, off_ifT, off_ifout, off_bcbuf, off_out, off_partial, off_invout, total;
+        off_ifmask, off_iftype, off_ifT, off_ifout, off_bcbuf, off_out, off_partial, off_invout, off_slot, total;
 };
 
 struct Geometry {
@@ -171,6 +171,7 @@ Plan make_plan(const rlbm_lattice_desc* d, int M, int E, const Geometry& g) {
     p.off_blk = take(6 * sizeof(int));
     p.off_flag = take(sizeof(int));
     p.off_ref = take((size_t)L * Q * sizeof(double));
+    p.off_slot = take((size_t)(M + M * M) * sizeof(double));
     p.off_pop0 = take((size_t)L * Q * N * s);
     p.off_pop1 = take((size_t)L * Q * N * s);
     p.off_aux = take((size_t)(AUX_Y + M + 6) * N * sizeof(double));
@@ -209,6 +210,7 @@ struct rlbm_lattice {
     Geometry geo;
     Plan plan{};
     char* base = nullptr;
+    MechDev mech{};           // host copy of the mechanism (slot tables at rlbm_set_state)
     LatDev host{};            // mirror of the device entry
     LatDev* d_lat = nullptr;
     int* d_blk = nullptr;     // [0, node blocks] and [0, interface blocks]
@@ -343,6 +345,7 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     if (!lat) return fail(RLBM_EINVAL, "out of host memory");
     lat->desc = *d;
     lat->M = M;
+    lat->mech = mech->dev;
     lat->L = M + 1;
     lat->E = mech->dev.E;
     lat->storage = d->storage;
@@ -373,6 +376,7 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     h.n_if = (int)nif;
     h.n_out = g.n_out;
     h.mech = (const MechDev*)(base + p.off_mech);
+    h.slotc = (const double*)(base + p.off_slot);
     h.pop[0] = base + p.off_pop0;
     h.pop[1] = base + p.off_pop1;
     h.aux = (double*)(base + p.off_aux);
@@ -403,7 +407,7 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     lat->d_invout = (double*)(base + p.off_invout);
     const int nb_nodes = (int)((g.N + 255) / 256);
     const int nb_if = (int)((nif + 63) / 64);
-    const int nb64 = 3 * (int)((g.N + 63) / 64);
+    const int nb64 = (int)((g.N + 63) / 64);
     const int blk[6] = {0, nb_nodes, 0, nb_if, 0, nb64};
     const int zero = 0;
 #define UP(dst, src, n)                                                              \
@@ -501,6 +505,20 @@ int rlbm_set_state(rlbm_lattice* lat, const double* rho, const double* u, const 
     lat->steps_done = 0;
     lat->host.parity0 = 0;
     HIP_TRY(hipMemcpyAsync(lat->d_lat, &lat->host, sizeof(LatDev), hipMemcpyHostToDevice, lat->stream), "upload");
+    // slot order for the collision: stored species in lattice order, then the
+    // slaved one; gas constants R_a and couplings 1/(D_ref m_a m_b) permuted
+    std::vector<double> slot((size_t)M + (size_t)M * M);
+    {
+        const int sl = lat->host.slaved;
+        auto spc = [&](int j) { return j < M - 1 ? j + (j >= sl ? 1 : 0) : sl; };
+        for (int j = 0; j < M; ++j) {
+            slot[j] = lat->mech.Ra[spc(j)];
+            for (int q = 0; q < M; ++q) slot[M + (size_t)j * M + q] = lat->mech.Kab[spc(j)][spc(q)];
+        }
+    }
+    HIP_TRY(hipMemcpyAsync((void*)lat->host.slotc, slot.data(), slot.size() * sizeof(double), hipMemcpyHostToDevice,
+                           lat->stream),
+            "upload");
     // device staging for the fields: the second population buffer is idle now
     double* stage = (double*)lat->host.pop[1];
     HIP_TRY(hipMemcpyAsync(stage, hf.data(), nf * sizeof(double), hipMemcpyHostToDevice, lat->stream), "upload");
@@ -522,7 +540,7 @@ static int step_one(rlbm_lattice* lat, long long t) {
     (void)p;
     const int nb_nodes = (int)((lat->geo.N + 255) / 256);
     const int nb_if = (int)((lat->geo.if_node.size() + 63) / 64);
-    const int nb64 = 3 * (int)((lat->geo.N + 63) / 64);
+    const int nb64 = (int)((lat->geo.N + 63) / 64);
     for (int phase = 0; phase < NPHASE; ++phase) {
         StepLaunch a;
         a.lats = lat->d_lat;
@@ -730,7 +748,7 @@ int rlbm_batch_step(rlbm_batch* b, const int64_t* steps) {
         b->host_table[j] = e;
         const int nbn = steps[j] ? (int)((lat->geo.N + 255) / 256) : 0;
         const int nbi = steps[j] ? (int)((lat->geo.if_node.size() + 63) / 64) : 0;
-        const int nb6 = steps[j] ? 3 * (int)((lat->geo.N + 63) / 64) : 0;
+        const int nb6 = steps[j] ? (int)((lat->geo.N + 63) / 64) : 0;
         b->host_blk[j + 1] = b->host_blk[j] + nbn;
         b->host_blk[(k + 1) + j + 1] = b->host_blk[(k + 1) + j] + nbi;
         b->host_blk[2 * (k + 1) + j + 1] = b->host_blk[2 * (k + 1) + j] + nb6;

@@ -530,7 +530,7 @@ __device__ __forceinline__ void st_at(RLBM_GLOBAL S* base, int idx, S v) {
 }
 
 template <int M, typename S>
-__global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+__global__ __launch_bounds__(UPD_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_update(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                                         int n_lat, long long t, int* __restrict__ flag) {
     constexpr int NR = prm_rows(M);
     constexpr int NL = M + 1;        // stored lattices
@@ -782,34 +782,92 @@ __device__ __forceinline__ double eq_value(MechC mc, const EqState<M, SPV>& e, i
     return e.rho * Ya * psi(c0, w0, w0 * w0 + tha) * psi(c1, w1, w1 * w1 + tha) * psi(c2, w2, w2 * w2 + tha);
 }
 
-// Local state (section 4, steps "local"): moments of the populations with
-// the incoming links D set to the imposed equilibrium A and the outgoing
-// links from advection, temperature by eq. temperature.
-template <int M, bool SPV, typename S, typename Streamed, typename Incoming, bool ASPV>
-__device__ __forceinline__ void bc_local(MechC mc, const EqState<M, ASPV>& A, int s, Streamed streamed,
-                                         Incoming incoming, EqState<M, SPV>& Lc, int* fail) {
-    double rl = 0.0, jl[3] = {0.0, 0.0, 0.0}, El = 0.0, ra[M], ja[M][3];
+// ---------------------------------------------------------------------------
+// k_boundary: reconstruction at interface nodes (section 4).  Lane-parallel:
+// half a wave (32 lanes) takes one interface node, lane v < 27 the discrete
+// velocity i = v, so the node's 27 * L populations are loaded at once and
+// every equilibrium is evaluated by the lane of its velocity; zeroth and
+// first moments are half-wave sums.  The state construction (temperature
+// iteration, LODI) is evaluated redundantly by the lanes of a node.
+// ---------------------------------------------------------------------------
+// Sum over the 32 lanes of a half-wave; every lane receives the first lane's
+// result, so all lanes of a node continue from bit-identical moments.
+__device__ __forceinline__ double hsum32(double v) {
 #pragma unroll
-    for (int a = 0; a < M; ++a) ra[a] = ja[a][0] = ja[a][1] = ja[a][2] = 0.0;
-#pragma unroll 1
-    for (int l = 0; l <= M; ++l) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll 1
-        for (int i = 0; i < Q; ++i) {
-            const double v = incoming(i) ? eq_value<M, ASPV>(mc, A, l, s, i) : streamed(l, i);
-            s0 += v; s1 += v * cx_of(i); s2 += v * cy_of(i); s3 += v * cz_of(i);
-        }
-        if (l == M) {
-            El = s0;
-        } else if (l == M - 1) {
-            rl = s0; jl[0] = s1; jl[1] = s2; jl[2] = s3;
-        } else {
-            const int a = l + (l >= s ? 1 : 0);
+    for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m, 32);
+    return __shfl(v, 0, 32);
+}
+
+// Equilibrium state of section 4.1: density, mass fractions, velocity (with
+// per-species velocities in the wall's local state, eq. locua) and T.
+template <int M, bool SPV>
+struct BcState {
+    double rho, th, U, T;
+    double u[3];
+    double Y[M];
+    double us[SPV ? M : 1][3];
+};
+
+template <int M, bool SPV>
+__device__ __forceinline__ void bc_prepare(MechC mc, BcState<M, SPV>& e, double T) {
+    e.T = T;
+    e.th = mc.R_univ * mix_inv_m<M>(mc, e.Y) * T;
+    e.U = mix_U<M>(mc, e.Y, T);
+}
+
+// Equilibria of every lattice at this lane's velocity (eqs. faEqGeneral,
+// fEqGeneral, gEqGeneral): species a (all M, slaved included) into ea[a],
+// the momentum lattice into ef, the energy lattice into eg.
+template <int M, bool SPV>
+__device__ __forceinline__ void bc_eq(MechC mc, const BcState<M, SPV>& e, int c0, int c1, int c2, double* ea,
+                                      double& ef, double& eg) {
 #pragma unroll
-            for (int c = 0; c < M; ++c)
-                if (c == a) { ra[c] = s0; ja[c][0] = s1; ja[c][1] = s2; ja[c][2] = s3; }
-        }
+    for (int a = 0; a < M; ++a) {
+        const double tha = mc.Ra[a] * e.T;
+        const double w0 = SPV ? e.us[SPV ? a : 0][0] : e.u[0];
+        const double w1 = SPV ? e.us[SPV ? a : 0][1] : e.u[1];
+        const double w2 = SPV ? e.us[SPV ? a : 0][2] : e.u[2];
+        ea[a] = e.rho * e.Y[a] * psi(c0, w0, w0 * w0 + tha) * psi(c1, w1, w1 * w1 + tha) *
+                psi(c2, w2, w2 * w2 + tha);
     }
+    ef = e.rho * psi(c0, e.u[0], e.u[0] * e.u[0] + e.th) * psi(c1, e.u[1], e.u[1] * e.u[1] + e.th) *
+         psi(c2, e.u[2], e.u[2] * e.u[2] + e.th);
+    GeqAxis gx, gy, gz;
+    geq_axis(e.u[0], e.th, gx);
+    geq_axis(e.u[1], e.th, gy);
+    geq_axis(e.u[2], e.th, gz);
+    const double Wx = sel3d(c0, gx.W[0], gx.W[1], gx.W[2]), kx = sel3d(c0, gx.k[0], gx.k[1], gx.k[2]);
+    const double Wy = sel3d(c1, gy.W[0], gy.W[1], gy.W[2]), ky = sel3d(c1, gy.k[0], gy.k[1], gy.k[2]);
+    const double Wz = sel3d(c2, gz.W[0], gz.W[1], gz.W[2]), kz = sel3d(c2, gz.k[0], gz.k[1], gz.k[2]);
+    eg = e.rho * (e.U * Wx * Wy * Wz + kx * Wy * Wz + Wx * (ky * Wz + Wy * kz));
+}
+
+// Local state (eqs. locRho .. locT and their inlet/outlet counterparts): the
+// moments of the populations with the incoming links set to the imposed
+// equilibrium A, outgoing links from advection (pa, pf, pg: this lane's
+// streamed values by species / momentum / energy lattice).
+template <int M, bool SPV, bool ASPV>
+__device__ __forceinline__ void bc_local(MechC mc, const BcState<M, ASPV>& A, int s, bool act, bool in, int c0,
+                                         int c1, int c2, const double* pa, double pf, double pg,
+                                         BcState<M, SPV>& Lc, int* fail) {
+    double ea[M], ef, eg;
+    bc_eq<M, ASPV>(mc, A, c0, c1, c2, ea, ef, eg);
+    double ra[M], ja[M][3];
+    const double cx = c0, cy = c1, cz = c2;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        if (a == s) continue;
+        const double v = act ? (in ? ea[a] : pa[a]) : 0.0;
+        ra[a] = hsum32(v);
+        ja[a][0] = hsum32(v * cx);
+        ja[a][1] = hsum32(v * cy);
+        ja[a][2] = hsum32(v * cz);
+    }
+    const double vf = act ? (in ? ef : pf) : 0.0;
+    const double vg = act ? (in ? eg : pg) : 0.0;
+    const double rl = hsum32(vf);
+    const double jl[3] = {hsum32(vf * cx), hsum32(vf * cy), hsum32(vf * cz)};
+    const double El = hsum32(vg);
     double rs = rl, j0 = jl[0], j1 = jl[1], j2 = jl[2];
 #pragma unroll
     for (int a = 0; a < M; ++a)
@@ -831,122 +889,126 @@ __device__ __forceinline__ void bc_local(MechC mc, const EqState<M, ASPV>& A, in
     }
     const double Ul = El / rl - 0.5 * (Lc.u[0] * Lc.u[0] + Lc.u[1] * Lc.u[1] + Lc.u[2] * Lc.u[2]);
     const double T_l = solve_T<M>(mc, Lc.Y, Ul, A.T, fail);
-    eq_prepare<M, SPV>(mc, Lc, T_l);
+    bc_prepare<M, SPV>(mc, Lc, T_l);
 }
 
+constexpr int BC_THREADS = 32 * BC_NODES;
+
 template <int M, typename S>
-__global__ __launch_bounds__(64) void k_boundary(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                                 int n_lat, long long t, int* __restrict__ flag) {
+__global__ __launch_bounds__(BC_THREADS) void k_boundary(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+                                                         int n_lat, long long t, int* __restrict__ flag) {
     const int b = blockIdx.x;
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
     if (t >= L.t_end) return;
-    const int k = (b - blk[lj]) * 64 + threadIdx.x;
-    if (k >= L.n_if) return;
+    const int k = (b - blk[lj]) * BC_NODES + (int)threadIdx.x / 32;
+    if (k >= L.n_if) return;                       // whole half-waves leave together
+    const int v = threadIdx.x % 32;
+    const bool act = v < Q;
+    const int i = act ? v : 0;
+    const int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);
     MechC mc = *as_const(L.mech);
     const void* src = L.pop[(L.parity0 + t) & 1];
-    const long long node = L.if_node[k];
+    const int node = L.if_node[k];
     const unsigned Dm = L.if_mask[k];
+    const bool in = act && ((Dm >> i) & 1u);      // incoming link (set D)
     const int type = L.if_type[k];
     const int s = L.slaved;
     const size_t N = (size_t)L.N;
-    const int x = (int)(node % L.nx), r = (int)(node / L.nx), y = r % L.ny, z = r / L.ny;
+    const int x = node % L.nx, r = node / L.nx, y = r % L.ny, z = r / L.ny;
     PullOff o;
     pull_offsets(L, x, y, z, o);
-    const int nL = M + 1;
+    const int off = node + sel3(c0, o.x[0], 0, o.x[2]) + sel3(c1, o.y[0], 0, o.y[2]) + sel3(c2, o.z[0], 0, o.z[2]);
     int fail = 0;
 
-    // population (l, i) after advection (outgoing links; the source lies in
-    // the box for every velocity not in D)
-    auto streamed = [&](int l, int i) -> double {
-        const int li = l * Q + i;
-        const int off = (int)node + sel3(cx_of(i), o.x[0], 0, o.x[2]) + sel3(cy_of(i), o.y[0], 0, o.y[2]) +
-                        sel3(cz_of(i), o.z[0], 0, o.z[2]);
-        return Codec<S>::ld(src, (size_t)li * N + off, L.ref, li);
-    };
-    auto incoming = [&](int i) -> bool { return (Dm >> i) & 1u; };
-    auto put = [&](int l, int i, double v) {
-        Codec<S>::st(L.bcbuf, (size_t)(l * Q + i) * L.n_if + k, v, L.ref, l * Q + i);
+    // this lane's populations after advection (outgoing links); on incoming
+    // links at a wall, the bounce-back source f'_{opp(i)}(x) instead
+    const bool wall = type == RLBM_FACE_WALL;
+    const int ld_off = (in && wall) ? node : off;
+    const int ld_i = (in && wall) ? Q - 1 - i : i;
+    const bool need = act && (!in || wall);       // open-face incoming links take no population
+    double pa[M], pf = 0.0, pg = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        pa[a] = 0.0;
+        if (a == s || !need) continue;
+        const int li = lat_of<M>(a, s) * Q + ld_i;
+        pa[a] = Codec<S>::ld(src, (size_t)li * N + ld_off, L.ref, li);
+    }
+    if (need) {
+        const int lf = (M - 1) * Q + ld_i;
+        pf = Codec<S>::ld(src, (size_t)lf * N + ld_off, L.ref, lf);
+        if (!in) {
+            const int lg = M * Q + i;
+            pg = Codec<S>::ld(src, (size_t)lg * N + off, L.ref, lg);
+        }
+    }
+    auto put = [&](int li, double val) {
+        if (act) Codec<S>::st(L.bcbuf, (size_t)li * L.n_if + k, val, L.ref, li);
     };
 
-    if (type == RLBM_FACE_WALL) {
+    if (wall) {
         // Tamm-Mott-Smith wall (section 4.2.2)
-        EqState<M, false> A;   // target: bounce-back rho and Y, u^tgt = 0, T^tgt
+        BcState<M, false> A;   // target: bounce-back rho and Y (eqs. BBrho, BBY), u^tgt = 0, T^tgt
         {
-            // step 1: bounce-back density and mass fractions (eqs. BBrho, BBY)
-            double rb = 0.0, rY[M];
-#pragma unroll
-            for (int a = 0; a < M; ++a) rY[a] = 0.0;
-#pragma unroll 1
-            for (int l = 0; l < nL - 1; ++l) {
-                double sum = 0.0;
-#pragma unroll 1
-                for (int i = 0; i < Q; ++i) {
-                    const int lo = l * Q + (Q - 1 - i);
-                    sum += incoming(i) ? Codec<S>::ld(src, (size_t)lo * N + node, L.ref, lo) : streamed(l, i);
-                }
-                if (l == M - 1) {
-                    rb = sum;
-                } else {
-                    const int a = l + (l >= s ? 1 : 0);
-#pragma unroll
-                    for (int c = 0; c < M; ++c)
-                        if (c == a) rY[c] = sum;
-                }
-            }
+            double rY[M];
+            const double rb = hsum32(act ? pf : 0.0);
             double rs = rb;
 #pragma unroll
-            for (int a = 0; a < M; ++a)
-                if (a != s) rs -= rY[a];
+            for (int a = 0; a < M; ++a) {
+                if (a == s) continue;
+                rY[a] = hsum32(pa[a]);
+                rs -= rY[a];
+            }
 #pragma unroll
             for (int a = 0; a < M; ++a) A.Y[a] = (a == s ? rs : rY[a]) / rb;
             A.rho = rb;
             A.u[0] = A.u[1] = A.u[2] = 0.0;
-            eq_prepare<M, false>(mc, A, L.if_T[k]);
+            bc_prepare<M, false>(mc, A, L.if_T[k]);
         }
-        // step 3: local state with species velocities (eqs. locRho..locT)
-        EqState<M, true> Lc;
-        bc_local<M, true, S>(mc, A, s, streamed, incoming, Lc, &fail);
+        // step 3: local state with species velocities (eqs. locRho .. locT)
+        BcState<M, true> Lc;
+        bc_local<M, true, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
         // step 4 (eqs. ftms, gtms, fatms)
-#pragma unroll 1
-        for (int l = 0; l < nL; ++l)
-#pragma unroll 1
-            for (int i = 0; i < Q; ++i) {
-                const double a_eq = eq_value<M, false>(mc, A, l, s, i);
-                const double l_eq = eq_value<M, true>(mc, Lc, l, s, i);
-                put(l, i, incoming(i) ? 2.0 * a_eq - l_eq : a_eq + streamed(l, i) - l_eq);
-            }
+        double eA[M], fA, gA, eL[M], fL, gL;
+        bc_eq<M, false>(mc, A, c0, c1, c2, eA, fA, gA);
+        bc_eq<M, true>(mc, Lc, c0, c1, c2, eL, fL, gL);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+            if (a != s) put(lat_of<M>(a, s) * Q + i, in ? 2.0 * eA[a] - eL[a] : eA[a] + pa[a] - eL[a]);
+        put((M - 1) * Q + i, in ? 2.0 * fA - fL : fA + pf - fL);
+        put(M * Q + i, in ? 2.0 * gA - gL : gA + pg - gL);
     } else if (type == RLBM_FACE_INLET) {
         // flux inlet (section 4.3)
-        EqState<M, false> A;   // inlet equilibrium (eqs. in_f, in_g, in_fa)
+        BcState<M, false> A;   // inlet equilibrium (eqs. in_f, in_g, in_fa)
         A.rho = L.rho_in;
         A.u[0] = L.u_in; A.u[1] = 0.0; A.u[2] = 0.0;
 #pragma unroll
         for (int a = 0; a < M; ++a) A.Y[a] = L.Y_in[a];
-        eq_prepare<M, false>(mc, A, L.T_in);
-        EqState<M, false> Lc;  // local state (eqs. inletlocRho..inletlocT)
-        bc_local<M, false, S>(mc, A, s, streamed, incoming, Lc, &fail);
+        bc_prepare<M, false>(mc, A, L.T_in);
+        BcState<M, false> Lc;  // local state (eqs. inletlocRho .. inletlocT)
+        bc_local<M, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
         // target: local density and composition at the imposed u, T (eqs. in_tgt_*)
-        EqState<M, false> Tg;
+        BcState<M, false> Tg;
         Tg.rho = Lc.rho;
         Tg.u[0] = L.u_in; Tg.u[1] = 0.0; Tg.u[2] = 0.0;
 #pragma unroll
         for (int a = 0; a < M; ++a) Tg.Y[a] = Lc.Y[a];
-        eq_prepare<M, false>(mc, Tg, L.T_in);
+        bc_prepare<M, false>(mc, Tg, L.T_in);
         // (eqs. f_inlet, g_inlet, fa_inlet)
-#pragma unroll 1
-        for (int l = 0; l < nL; ++l)
-#pragma unroll 1
-            for (int i = 0; i < Q; ++i) {
-                const double t_eq = eq_value<M, false>(mc, Tg, l, s, i);
-                const double l_eq = eq_value<M, false>(mc, Lc, l, s, i);
-                put(l, i, incoming(i) ? t_eq + eq_value<M, false>(mc, A, l, s, i) - l_eq
-                                      : t_eq + streamed(l, i) - l_eq);
-            }
+        double eA[M], fA, gA, eL[M], fL, gL, eT[M], fT, gT;
+        bc_eq<M, false>(mc, A, c0, c1, c2, eA, fA, gA);
+        bc_eq<M, false>(mc, Lc, c0, c1, c2, eL, fL, gL);
+        bc_eq<M, false>(mc, Tg, c0, c1, c2, eT, fT, gT);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+            if (a != s) put(lat_of<M>(a, s) * Q + i, eT[a] + (in ? eA[a] : pa[a]) - eL[a]);
+        put((M - 1) * Q + i, fT + (in ? fA : pf) - fL);
+        put(M * Q + i, gT + (in ? gA : pg) - gL);
     } else {
         // outlet (section 4.4): LODI state from the previous outlet state and
         // the previous post-boundary moments of the first interior node
-        EqState<M, false> A;
+        BcState<M, false> A;
         {
             const int ko = L.if_out[k];
             const size_t No = (size_t)L.n_out;
@@ -955,16 +1017,16 @@ __global__ __launch_bounds__(64) void k_boundary(const LatDev* __restrict__ lats
             const double u0[3] = {os[1 * No + ko], os[2 * No + ko], os[3 * No + ko]};
             const double T0 = os[4 * No + ko];
             double Y0[M], Y1[M];
-            const size_t in = (size_t)node - 1;
+            const size_t inn = (size_t)node - 1;
 #pragma unroll
             for (int a = 0; a < M; ++a) {
                 Y0[a] = os[(5 + a) * No + ko];
-                Y1[a] = L.aux[(AUX_Y + a) * N + in];
+                Y1[a] = L.aux[(AUX_Y + a) * N + inn];
             }
-            const double rho1 = L.aux[AUX_RHO * N + in];
-            const double u1[3] = {L.aux[(AUX_U + 0) * N + in], L.aux[(AUX_U + 1) * N + in],
-                                  L.aux[(AUX_U + 2) * N + in]};
-            const double T1 = L.aux[AUX_T * N + in];
+            const double rho1 = L.aux[AUX_RHO * N + inn];
+            const double u1[3] = {L.aux[(AUX_U + 0) * N + inn], L.aux[(AUX_U + 1) * N + inn],
+                                  L.aux[(AUX_U + 2) * N + inn]};
+            const double T1 = L.aux[AUX_T * N + inn];
             const double R0 = mc.R_univ * mix_inv_m<M>(mc, Y0);
             const double P0 = rho0 * R0 * T0;
             const double P1 = rho1 * mc.R_univ * mix_inv_m<M>(mc, Y1) * T1;
@@ -989,26 +1051,30 @@ __global__ __launch_bounds__(64) void k_boundary(const LatDev* __restrict__ lats
 #pragma unroll
             for (int a = 0; a < M; ++a) A.Y[a] = Y0[a] - un * (Y0[a] - Y1[a]);   // eq. convectiveBC
             const double T_o = P_o / (rho_o * mc.R_univ * mix_inv_m<M>(mc, A.Y));
-            os[0 * No + ko] = A.rho;
-            os[1 * No + ko] = A.u[0]; os[2 * No + ko] = A.u[1]; os[3 * No + ko] = A.u[2];
-            os[4 * No + ko] = T_o;
+            bc_prepare<M, false>(mc, A, T_o);
+            // all lanes of the node have read the previous state above
+            __builtin_amdgcn_wave_barrier();
+            if (v == 0) {
+                os[0 * No + ko] = A.rho;
+                os[1 * No + ko] = A.u[0]; os[2 * No + ko] = A.u[1]; os[3 * No + ko] = A.u[2];
+                os[4 * No + ko] = T_o;
 #pragma unroll
-            for (int a = 0; a < M; ++a) os[(5 + a) * No + ko] = A.Y[a];
-            eq_prepare<M, false>(mc, A, T_o);
-        }
-        EqState<M, false> Lc;  // local state (eqs. outletlocRho..outletlocT)
-        bc_local<M, false, S>(mc, A, s, streamed, incoming, Lc, &fail);
-        // (eqs. f_outlet, g_outlet, fa_outlet)
-#pragma unroll 1
-        for (int l = 0; l < nL; ++l)
-#pragma unroll 1
-            for (int i = 0; i < Q; ++i) {
-                const double a_eq = eq_value<M, false>(mc, A, l, s, i);
-                const double l_eq = eq_value<M, false>(mc, Lc, l, s, i);
-                put(l, i, incoming(i) ? 2.0 * a_eq - l_eq : a_eq + streamed(l, i) - l_eq);
+                for (int a = 0; a < M; ++a) os[(5 + a) * No + ko] = A.Y[a];
             }
+        }
+        BcState<M, false> Lc;  // local state (eqs. outletlocRho .. outletlocT)
+        bc_local<M, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
+        // (eqs. f_outlet, g_outlet, fa_outlet)
+        double eA[M], fA, gA, eL[M], fL, gL;
+        bc_eq<M, false>(mc, A, c0, c1, c2, eA, fA, gA);
+        bc_eq<M, false>(mc, Lc, c0, c1, c2, eL, fL, gL);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+            if (a != s) put(lat_of<M>(a, s) * Q + i, in ? 2.0 * eA[a] - eL[a] : eA[a] + pa[a] - eL[a]);
+        put((M - 1) * Q + i, in ? 2.0 * fA - fL : fA + pf - fL);
+        put(M * Q + i, in ? 2.0 * gA - gL : gA + pg - gL);
     }
-    if (fail) atomicOr(flag, 1);
+    if (fail && v == 0) atomicOr(flag, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1232,7 +1298,7 @@ template <typename S>
 static hipError_t launch_step_phase(int phase, int M, const StepLaunch& a) {
     if (a.blocks <= 0) return hipSuccess;
     if (phase == 0) {
-        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_boundary<MM, S>), dim3(a.blocks), dim3(64), 0, a.stream, a.lats,
+        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_boundary<MM, S>), dim3(a.blocks), dim3(BC_THREADS), 0, a.stream, a.lats,
                                                 a.blk, a.n_lat, a.t, a.flag))
     } else if (phase == 1) {
         RLBM_DISPATCH(M, hipLaunchKernelGGL((k_local<MM, S>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,

@@ -406,7 +406,7 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     lat->d_partial = (double*)(base + p.off_partial);
     lat->d_invout = (double*)(base + p.off_invout);
     const int nb_nodes = (int)((g.N + 255) / 256);
-    const int nb_if = (int)((nif + 63) / 64);
+    const int nb_if = (int)((nif + BC_NODES - 1) / BC_NODES);
     const int nb64 = (int)((g.N + 63) / 64);
     const int blk[6] = {0, nb_nodes, 0, nb_if, 0, nb64};
     const int zero = 0;
@@ -539,7 +539,7 @@ static int step_one(rlbm_lattice* lat, long long t) {
     const Plan& p = lat->plan;
     (void)p;
     const int nb_nodes = (int)((lat->geo.N + 255) / 256);
-    const int nb_if = (int)((lat->geo.if_node.size() + 63) / 64);
+    const int nb_if = (int)((lat->geo.if_node.size() + BC_NODES - 1) / BC_NODES);
     const int nb64 = (int)((lat->geo.N + 63) / 64);
     for (int phase = 0; phase < NPHASE; ++phase) {
         StepLaunch a;
@@ -747,7 +747,7 @@ int rlbm_batch_step(rlbm_batch* b, const int64_t* steps) {
         e.t_end = steps[j];
         b->host_table[j] = e;
         const int nbn = steps[j] ? (int)((lat->geo.N + 255) / 256) : 0;
-        const int nbi = steps[j] ? (int)((lat->geo.if_node.size() + 63) / 64) : 0;
+        const int nbi = steps[j] ? (int)((lat->geo.if_node.size() + BC_NODES - 1) / BC_NODES) : 0;
         const int nb6 = steps[j] ? (int)((lat->geo.N + 63) / 64) : 0;
         b->host_blk[j + 1] = b->host_blk[j] + nbn;
         b->host_blk[(k + 1) + j + 1] = b->host_blk[(k + 1) + j] + nbi;

@@ -100,6 +100,84 @@ def _cpu_baseline(budget_s=20.0):
                       f"{n} steps in {dt:.1f} s, FP64 NumPy, 1 thread"}
 
 
+def _bench_tubes(args):
+    """The uneven flame-tube batch: tubes of U{64..2048} nodes (inlet,
+    outlet, FP32 deviation storage) advanced by one launch per kernel for all
+    tubes, against stepping one lattice at a time."""
+    import torch
+    from paper_2108_07605_amd import rlbm, workloads as wl
+    mech = wl.mechanism_h2air9()
+    cases = wl.tube_batch(args.tubes, mech=mech)
+    m = rlbm.Mechanism(mech)
+    lats = [rlbm.Lattice(c, storage="f32dev", mech=m).set_state() for c in cases]
+    k = len(lats)
+    nodes = sum(c["N"] for c in cases)
+    batch = rlbm.Batch(lats)
+    batch.step([args.warmup] * k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step([args.steps] * k)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    finite = all(l.invariants()[-1] == 0.0 for l in lats)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for l in lats:
+        l.step(args.seq_steps)
+    torch.cuda.synchronize()
+    dt_seq = time.perf_counter() - t1
+    v = nodes * args.steps / dt / 1e6
+    v_seq = nodes * args.seq_steps / dt_seq / 1e6
+    return {"metric": "MLUPS, batched uneven instances", "value": v, "unit": "MLUPS", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"{k} flame tubes, lengths U{{64..2048}} (total {nodes} nodes), "
+                                   "9 species / 21 reactions, flux inlet + LODI outlet, f32dev storage",
+                       "instances": k, "nodes": nodes},
+            "one_at_a_time": {"value": v_seq, "unit": "MLUPS", "steps": args.seq_steps},
+            "batched_over_one_at_a_time": v / v_seq, "finite": finite}
+
+
+def _bench_serve(args):
+    """The continuous-batching server on a seeded Poisson trace (mean 20
+    requests/s) over reactor 16^3, flame tube 1024, channel 512x64x1 and
+    channel 256x64x64 requests; step budgets U{1000..5000} scaled by
+    --step-scale; admission budget 200 GB of device memory.  Latency is
+    arrival to fields read back."""
+    import torch
+    from paper_2108_07605_amd import workloads as wl
+    from paper_2108_07605_amd.serving import GpuBackend, Request, Server, summarize
+    mech = wl.mechanism_h2air9()
+    trace = wl.serving_trace(args.requests)
+    reqs = [Request(k, q["arrival_s"], wl.request_case(q, mech=mech, scale_steps=args.step_scale),
+                    max(1, int(q["steps"] * args.step_scale))) for k, q in enumerate(trace)]
+    backend = GpuBackend(mech, storage="f32dev", keep="fields")
+    # warm up the kernels once on a small request
+    warm = Server(backend, budget_bytes=200e9)
+    warm.run([Request(-1, 0.0, wl.request_case(trace[0], mech=mech, scale_steps=0.01), 3)])
+    torch.cuda.synchronize()
+    srv = Server(backend, budget_bytes=200e9, max_slots=256, round_s=0.05)
+    t0 = time.perf_counter()
+    out = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    summ = summarize(out, wall)
+    kinds = {}
+    for q, r in zip(trace, out):
+        kinds.setdefault(q["kind"], []).append(r.latency)
+    return {"metric": "p50/p99 solve latency + MLUPS, continuous batching", "value": summ["mlups"],
+            "unit": "MLUPS", "n_gpus": 1, "steps": None, "warmup": 1, "ms_per_step": None,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"{len(out)} requests, Poisson 20/s over reactor 16^3 / tube 1024 / "
+                                   f"channel 512x64x1 / channel 256x64x64, steps U{{1000..5000}} x "
+                                   f"{args.step_scale}, 200 GB admission budget, f32dev storage",
+                       "requests": len(out), "step_scale": args.step_scale},
+            "latency_s": {"p50": summ["p50_s"], "p99": summ["p99_s"], "max": summ["max_s"]},
+            "latency_p50_by_kind_s": {k: sorted(v)[len(v) // 2] for k, v in kinds.items()},
+            "rounds": srv.rounds, "wall_s": wall}
+
+
 def _copy_probe(mib):
     """A copy kernel of known size: 5 launches of an out-of-place elementwise
     copy reading and writing mib MiB each."""
@@ -124,6 +202,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--storage", default="both", choices=["both", "f32dev", "f64"])
+    ap.add_argument("--workload", default="channel3d", choices=["channel3d", "tubes", "serve"],
+                    help="channel3d: the 512x64x64 channel (default); tubes: 256 uneven flame "
+                         "tubes in batched launches vs one lattice at a time; serve: the "
+                         "continuous-batching server on a Poisson request trace")
+    ap.add_argument("--tubes", type=int, default=256)
+    ap.add_argument("--seq-steps", type=int, default=20,
+                    help="steps of the one-lattice-at-a-time comparison (tubes)")
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--step-scale", type=float, default=0.05,
+                    help="scale of the trace's step budgets (serve)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -132,12 +220,18 @@ def main():
         _copy_probe(args.copy_probe)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding note in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2108_07605_amd import workloads as wl
     torch.cuda.set_device(0)
+    if args.workload == "tubes":
+        print(json.dumps(_bench_tubes(args)))
+        return
+    if args.workload == "serve":
+        print(json.dumps(_bench_serve(args)))
+        return
     case = wl.make_case("channel3d", nx=args.nx, ny=args.ny, nz=args.nz)
     N = case["nx"] * case["ny"] * case["nz"]
     M = case["mech"]["M"]

@@ -238,9 +238,16 @@ class Lattice:
         return sl.value
 
     def __del__(self):
+        self.close()
+
+    def close(self):
+        """Destroy the lattice and release its device memory (after the
+        work queued on its stream)."""
         if getattr(self, "handle", None) and _lib_handle is not None:
             _lib_handle.rlbm_lattice_destroy(self.handle)
             self.handle = None
+            self.stream.synchronize()
+            self._mem = None
 
     def set_state(self, init=None):
         init = init or self.case["init"]

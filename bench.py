@@ -178,6 +178,83 @@ def _bench_serve(args):
             "rounds": srv.rounds, "wall_s": wall}
 
 
+def _field_errors(a, b, u_floor, dims):
+    """Field-normalised max errors of a against b: max|a-b| / max|b| per
+    mass fraction, for T, and for |u| (normalised by max(max|u|, u_floor));
+    with the node (x, y, z) of the largest mass-fraction error."""
+    import numpy as np
+    nx, ny, _ = dims
+    Y = [float(np.abs(a["Y"][k] - b["Y"][k]).max() / max(np.abs(b["Y"][k]).max(), 1e-300))
+         for k in range(b["Y"].shape[0])]
+    kw = int(np.argmax(Y))
+    n = int(np.argmax(np.abs(a["Y"][kw] - b["Y"][kw])))
+    T = float(np.abs(a["T"] - b["T"]).max() / np.abs(b["T"]).max())
+    nT = int(np.argmax(np.abs(a["T"] - b["T"])))
+    du = np.sqrt(((a["u"] - b["u"]) ** 2).sum(axis=0)).max()
+    um = np.sqrt((b["u"] ** 2).sum(axis=0)).max()
+    xyz = lambda m: [m % nx, (m // nx) % ny, m // (nx * ny)]
+    return {"Y_max": max(Y), "Y": Y, "T": T, "u": float(du / max(um, u_floor)),
+            "Y_abs_max": float(np.abs(a["Y"] - b["Y"]).max()),
+            "T_abs_max_K": float(np.abs(a["T"] - b["T"]).max()),
+            "Y_worst_species": kw, "Y_worst_node": xyz(n), "T_worst_node": xyz(nT)}
+
+
+def _bench_precision(args):
+    """FP32-deviation storage against FP64 storage from the same initial
+    state: the 512x64x64 channel after --steps steps (2000 in the recipe) and
+    the 1024x64x1 channel after 2.5x as many, with the errors at 1/8, 1/4,
+    1/2 and all of the steps."""
+    import math
+    import torch
+    from paper_2108_07605_amd import rlbm, workloads as wl
+    mech = wl.mechanism_h2air9()
+    m = rlbm.Mechanism(mech)
+    out = {"metric": "FP32-deviation vs FP64 storage: field-normalised max error", "unit": "relative",
+           "n_gpus": 1, "dtype": "f64", "data": "synthetic", "higher_is_better": False, "cases": {}}
+    for name, kw, steps in (("channel3d", dict(nx=args.nx, ny=args.ny, nz=args.nz), args.steps),
+                            ("channel2d", dict(nx=1024, ny=64, nz=1), int(2.5 * args.steps))):
+        case = wl.make_case(name, mech=mech, **kw)
+        dims = (case["nx"], case["ny"], case["nz"])
+        th = float(case["init"]["T"].mean()) * mech["R_univ"] / 20.0
+        lats = {st: rlbm.Lattice(case, storage=st, mech=m).set_state() for st in ("f64", "f32dev")}
+        done, rows = 0, []
+        for n in (steps // 8, steps // 4, steps // 2, steps):
+            for lat in lats.values():
+                lat.step(n - done)
+            done = n
+            f = {st: lat.fields() for st, lat in lats.items()}
+            err = _field_errors(f["f32dev"], f["f64"], 1e-3 * math.sqrt(th), dims)
+            rows.append({"steps": n, **err})
+        finite = all(lat.invariants()[-1] == 0.0 for lat in lats.values())
+        for lat in lats.values():
+            lat.close()
+        # sensitivity of the FP64 run itself: the same case with the initial
+        # temperature perturbed by 1e-10 (relative, seeded noise)
+        import numpy as np
+        init = dict(case["init"])
+        rng = np.random.default_rng(11)
+        init["T"] = init["T"] * (1.0 + 1e-10 * rng.uniform(-1.0, 1.0, init["T"].shape))
+        a = rlbm.Lattice(case, storage="f64", mech=m).set_state()
+        bl = rlbm.Lattice(case, storage="f64", mech=m).set_state(init)
+        done, sens = 0, []
+        for n in (steps // 8, steps // 4, steps // 2, steps):
+            a.step(n - done)
+            bl.step(n - done)
+            done = n
+            e = _field_errors(bl.fields(), a.fields(), 1e-3 * math.sqrt(th), dims)
+            sens.append({k: e[k] for k in ("Y_max", "T", "u", "Y_abs_max")} | {"steps": n})
+        a.close()
+        bl.close()
+        err = rows[-1]
+        out["cases"][name] = {"dims": list(dims), "steps": steps, "errors": err,
+                              "history": [{k: r[k] for k in ("steps", "Y_max", "T", "u", "Y_abs_max")}
+                                          for r in rows],
+                              "f64_perturbed_1e-10": sens,
+                              "pass_1e-5_Y_T": err["Y_max"] <= 1e-5 and err["T"] <= 1e-5, "finite": finite}
+    out["value"] = max(c["errors"]["Y_max"] for c in out["cases"].values())
+    return out
+
+
 def _copy_probe(mib):
     """A copy kernel of known size: 5 launches of an out-of-place elementwise
     copy reading and writing mib MiB each."""
@@ -202,10 +279,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--storage", default="both", choices=["both", "f32dev", "f64"])
-    ap.add_argument("--workload", default="channel3d", choices=["channel3d", "tubes", "serve"],
+    ap.add_argument("--workload", default="channel3d", choices=["channel3d", "tubes", "serve", "precision"],
                     help="channel3d: the 512x64x64 channel (default); tubes: 256 uneven flame "
                          "tubes in batched launches vs one lattice at a time; serve: the "
-                         "continuous-batching server on a Poisson request trace")
+                         "continuous-batching server on a Poisson request trace; precision: "
+                         "FP32-deviation vs FP64 storage field errors after --steps steps")
     ap.add_argument("--tubes", type=int, default=256)
     ap.add_argument("--seq-steps", type=int, default=20,
                     help="steps of the one-lattice-at-a-time comparison (tubes)")
@@ -231,6 +309,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(_bench_serve(args)))
+        return
+    if args.workload == "precision":
+        print(json.dumps(_bench_precision(args)))
         return
     case = wl.make_case("channel3d", nx=args.nx, ny=args.ny, nz=args.nz)
     N = case["nx"] * case["ny"] * case["nz"]

@@ -169,6 +169,23 @@ int rlbm_read_fields(rlbm_lattice* lat, double* rho, double* u, double* T, doubl
 int rlbm_read_populations(rlbm_lattice* lat, double* buf, int on_device);
 int rlbm_write_populations(rlbm_lattice* lat, const double* buf, int on_device);
 
+/* Raw state snapshot for bit-exact checkpoint and resume.  The snapshot holds
+ * the current populations in their storage format together with everything
+ * the next steps read besides them: the FP32 references (shapes and per-node
+ * scales), the per-node fields carried between steps (the temperature that
+ * starts the next Newton iteration, the interior moments the outlet reads),
+ * the outlet state and the slaved-species index.  A lattice that loads it
+ * continues bit-identically to the one that saved it.
+ *   rlbm_state_bytes: size of the snapshot of this lattice.
+ *   rlbm_save_state: writes the snapshot to buf (host or device memory of at
+ *     least rlbm_state_bytes bytes); synchronises the lattice's stream.
+ *   rlbm_load_state: replaces the lattice's state with the snapshot; the
+ *     lattice must have the snapshot's dimensions, species count and storage
+ *     (RLBM_EINVAL otherwise).  rlbm_set_state is not needed before it. */
+int rlbm_state_bytes(const rlbm_lattice* lat, size_t* bytes);
+int rlbm_save_state(rlbm_lattice* lat, void* buf, int on_device);
+int rlbm_load_state(rlbm_lattice* lat, const void* buf, int on_device);
+
 /* Global invariants of the current populations into host array out[n_out]:
  * [0] sum rho, [1..3] sum rho u, [4] sum rho E, [5..5+E) element totals
  * (moles), [5+E] 1 if any population is non-finite else 0.  Needs

@@ -31,27 +31,54 @@ struct Codec;
 
 template <>
 struct Codec<double> {
-    template <typename RP>
-    static __device__ __forceinline__ double ld(const void* p, size_t idx, RP, int) {
+    static __device__ __forceinline__ double ld(const void* p, size_t idx, double) {
         return static_cast<const double*>(p)[idx];
     }
-    template <typename RP>
-    static __device__ __forceinline__ void st(void* p, size_t idx, double v, RP, int) {
+    static __device__ __forceinline__ void st(void* p, size_t idx, double v, double) {
         static_cast<double*>(p)[idx] = v;
     }
 };
 
 template <>
 struct Codec<float> {
-    template <typename RP>
-    static __device__ __forceinline__ double ld(const void* p, size_t idx, RP ref, int li) {
-        return (double)static_cast<const float*>(p)[idx] + ref[li];
+    static __device__ __forceinline__ double ld(const void* p, size_t idx, double ref) {
+        return (double)static_cast<const float*>(p)[idx] + ref;
     }
-    template <typename RP>
-    static __device__ __forceinline__ void st(void* p, size_t idx, double v, RP ref, int li) {
-        static_cast<float*>(p)[idx] = __double2float_rn(v - ref[li]);
+    static __device__ __forceinline__ void st(void* p, size_t idx, double v, double ref) {
+        static_cast<float*>(p)[idx] = __double2float_rn(v - ref);
     }
 };
+
+// FP32 deviation storage: population (l, i) is stored as its deviation from
+// s_l(y) G_li, where G_li is the zero-velocity equilibrium shape of lattice l
+// at the domain-mean initial state normalised to unit zeroth moment, and
+// s_l(y) the zeroth moment of lattice l (rho_a, rho or rho E) at the node y
+// that reads the population, as it was when the population was written.
+// Both factors hold FP32 values, so their product is exact in FP64: every
+// writer and reader forms the same reference however the compiler fuses it.
+__device__ __forceinline__ double ref_of(float s, double G) { return (double)s * G; }
+
+// The energy lattice's reference: at zero velocity its equilibrium is
+// rho U W_i(theta) + rho K_i(theta) (eq. geq_i with u = 0: K carries the
+// theta^2 terms and has zero sum), so its reference is s_g W_i + s_f K_i with
+// s_g = rho E and s_f = rho of the reading node (both products exact).
+__device__ __forceinline__ double ref_g(float sg, float sf, double W, double K) {
+    return (double)sg * W + (double)sf * K;
+}
+
+// Layout of the reference table: shapes G[M + 1][Q] (the energy lattice's
+// row is W), the zeroth moments sum_i G_li [M + 1], sum_i G_fi c_ix^2, the
+// energy lattice's K[Q] and sum_i K_i.
+template <int M> constexpr int REF_M0 = (M + 1) * Q;
+template <int M> constexpr int REF_M2 = (M + 1) * Q + M + 1;
+template <int M> constexpr int REF_K = (M + 1) * Q + M + 2;
+template <int M> constexpr int REF_K0 = (M + 1) * Q + M + 2 + Q;
+
+// Scales s_l of node n in buffer q: rss floats per node, lattices in order
+// (stored species, rho, rho E).
+__device__ __forceinline__ const RLBM_GLOBAL float* scale_at(const LatDev& L, int q, long long n) {
+    return as_global(L.rscale[q]) + (size_t)n * L.rss;
+}
 
 // ---------------------------------------------------------------------------
 // work-list helpers
@@ -95,18 +122,10 @@ __device__ __forceinline__ double sel3d(int c, double m, double z, double p) { r
 template <int M>
 __device__ __forceinline__ int lat_of(int a, int slaved) { return a - (a > slaved ? 1 : 0); }
 
-// Load population (lattice l, velocity i) of this node after advection and
-// boundary reconstruction: interface nodes (slot k >= 0) read the boundary
-// buffer, all others pull from node + off in the source buffer.
-template <typename S>
-__device__ __forceinline__ double ldpop(const LatDev& L, const void* src, int k, int node_off, int l, int i) {
-    const int li = l * Q + i;
-    if (k >= 0) return Codec<S>::ld(L.bcbuf, (size_t)li * L.n_if + k, L.ref, li);
-    return Codec<S>::ld(src, (size_t)li * L.N + node_off, L.ref, li);
-}
-
 // Raw stored value (FP64, or FP32 deviation) of population (l, i) at node
-// offset off after advection and boundary reconstruction.
+// offset off after advection and boundary reconstruction: interface nodes
+// (slot k >= 0) read the boundary buffer, all others pull from the source
+// buffer.
 template <typename S>
 __device__ __forceinline__ S ld_raw_off(const LatDev& L, const void* src, int k, int off, int l, int i) {
     const int li = l * Q + i;
@@ -123,10 +142,15 @@ struct Moments {
 // Moments of the node's post-advection, post-boundary populations (eqs.
 // density1, momentum1, fdensity, f1momMomentum, g0momTotalEnergy), the
 // slaved species by difference (eq. strongest).  FULL adds P = sum f c c,
-// q = sum g c and the species momenta.
+// q = sum g c and the species momenta.  In FP32 deviation storage the sums
+// run over the stored deviations and the reference's own moments are added
+// in closed form (zeroth s_l sum_i G_li, second s_f sum_i G_fi c c, first
+// zero by symmetry).  With FP32 storage the stored lattices' zeroth moments
+// (rho_a, rho) are written to s_out, the scales of the references of the
+// populations written this step.
 template <int M, typename S, bool FULL>
 __device__ __forceinline__ void node_moments(const LatDev& L, const void* src, int k, int node, const PullOff& o,
-                                             Moments<M>& m) {
+                                             int par, Moments<M>& m, float* s_out) {
     const int s = L.slaved;
     m.rho = m.rhoE = 0.0;
 #pragma unroll
@@ -140,8 +164,8 @@ __device__ __forceinline__ void node_moments(const LatDev& L, const void* src, i
     for (int i = 0; i < Q; ++i) {
         const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
         const int off = node + o.x[cx + 1] + o.y[cy + 1] + o.z[cz + 1];
-        const double f = ldpop<S>(L, src, k, off, M - 1, i);
-        const double g = ldpop<S>(L, src, k, off, M, i);
+        const double f = (double)ld_raw_off<S>(L, src, k, off, M - 1, i);
+        const double g = (double)ld_raw_off<S>(L, src, k, off, M, i);
         m.rho += f;
         m.rhoE += g;
         if (cx) m.j[0] += cx > 0 ? f : -f;
@@ -156,6 +180,20 @@ __device__ __forceinline__ void node_moments(const LatDev& L, const void* src, i
             if (cy * cz) m.P[5] += cy * cz > 0 ? f : -f;
         }
     }
+    const RLBM_GLOBAL float* sc = nullptr;
+    if constexpr (sizeof(S) == 4) {
+        const RLBM_CONST double* G = as_const(L.ref);
+        sc = scale_at(L, par, node);
+        const double sf = (double)sc[M - 1];
+        m.rho += sf * G[REF_M0<M> + M - 1];
+        m.rhoE += (double)sc[M] * G[REF_M0<M> + M] + sf * G[REF_K0<M>];
+        if (FULL) {
+            const double p2 = sf * G[REF_M2<M>];
+            m.P[0] += p2; m.P[1] += p2; m.P[2] += p2;
+        }
+        s_out[M - 1] = __double2float_rn(m.rho);
+        s_out[M] = __double2float_rn(m.rhoE);
+    }
     // species lattices, one at a time, the next one's loads in flight while
     // the current one is summed
     S cur[Q];
@@ -165,7 +203,6 @@ __device__ __forceinline__ void node_moments(const LatDev& L, const void* src, i
 #pragma unroll 1
     for (int l = 0; l < M - 1; ++l) {
         reload_barrier();
-        const RLBM_CONST double* ref = as_const(L.ref) + opaque_zero();
         S nxt[Q];
         if (l + 1 < M - 1) {
 #pragma unroll
@@ -177,8 +214,7 @@ __device__ __forceinline__ void node_moments(const LatDev& L, const void* src, i
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
-            double v = (double)cur[i];
-            if constexpr (sizeof(S) == 4) v += ref[l * Q + i];
+            const double v = (double)cur[i];
             r += v;
             if (FULL) {
                 if (cx) jx += cx > 0 ? v : -v;
@@ -186,6 +222,11 @@ __device__ __forceinline__ void node_moments(const LatDev& L, const void* src, i
                 if (cz) jz += cz > 0 ? v : -v;
             }
         }
+        if constexpr (sizeof(S) == 4) {
+            const RLBM_CONST double* rm = as_const(L.ref) + REF_M0<M> + opaque_zero();
+            r += (double)sc[l] * rm[l];
+        }
+        if constexpr (sizeof(S) == 4) s_out[l] = __double2float_rn(r);
         const int a = l + (l >= s ? 1 : 0);
 #pragma unroll
         for (int c = 0; c < M; ++c) {
@@ -276,8 +317,10 @@ __global__ __launch_bounds__(256) void k_local(const LatDev* __restrict__ lats, 
     double* prm = L.prm;
     const size_t N = (size_t)L.N;
 
+    const int par = (L.parity0 + t) & 1;
     Moments<M> m;
-    node_moments<M, S, true>(L, src, k, node, o, m);
+    float* so = sizeof(S) == 4 ? L.rscale[par ^ 1] + (size_t)node * L.rss : nullptr;
+    node_moments<M, S, true>(L, src, k, node, o, par, m, so);
     const double rho = m.rho, inv_rho = 1.0 / rho;
     const double u[3] = {m.j[0] * inv_rho, m.j[1] * inv_rho, m.j[2] * inv_rho};
     const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
@@ -530,11 +573,13 @@ __device__ __forceinline__ void st_at(RLBM_GLOBAL S* base, int idx, S v) {
 }
 
 template <int M, typename S>
-__global__ __launch_bounds__(UPD_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_update(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+__global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                                         int n_lat, long long t, int* __restrict__ flag) {
     constexpr int NR = prm_rows(M);
     constexpr int NL = M + 1;        // stored lattices
+    constexpr int NS = sizeof(S) == 4 ? M + 1 : 1;
     __shared__ double sp[NR][UPD_NODES];
+    __shared__ float ssc[NS][UPD_NODES];     // FP32 storage: this node's reference scales
     const int b = blockIdx.x;
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
@@ -566,6 +611,14 @@ __global__ __launch_bounds__(UPD_THREADS) __attribute__((amdgpu_waves_per_eu(3, 
         const int nd = node0 + j;
         sp[row][j] = nd < N ? prm[(size_t)srow * L.N + nd] : 1.0;
     }
+    if constexpr (sizeof(S) == 4) {
+        const int par0 = (L.parity0 + t) & 1;
+        for (int idx = threadIdx.x; idx < NS * UPD_NODES; idx += UPD_THREADS) {
+            const int j = idx / NS, l = idx % NS;
+            const int nd = node0 + j;
+            ssc[l][j] = nd < N ? scale_at(L, par0, nd)[l] : 1.0f;
+        }
+    }
 
     int x = 0, y = 0, z = 0;
     if (valid) { x = node % L.nx; const int r = node / L.nx; y = r % L.ny; z = r / L.ny; }
@@ -586,6 +639,24 @@ __global__ __launch_bounds__(UPD_THREADS) __attribute__((amdgpu_waves_per_eu(3, 
             for (int l = 0; l < NL; ++l)
                 out[l] = k >= 0 ? bc[(size_t)(l * Q + i) * nif + k] : src[(size_t)(l * Q + i) * L.N + off];
         }
+    };
+    // FP32 deviation storage: reference scales of this node (decode) and of
+    // the node that reads what is written for velocity (c0, c1, c2) (encode)
+    constexpr int NS4 = (NS + 3) / 4;
+    auto load_scales = [&](int q, int n, float* out) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const RLBM_GLOBAL f4* p4 = reinterpret_cast<const RLBM_GLOBAL f4*>(scale_at(L, q, n));
+#pragma unroll
+        for (int v = 0; v < NS4; ++v) {
+            const f4 w = p4[v];
+            if (4 * v + 0 < NS) out[4 * v + 0] = w.x;
+            if (4 * v + 1 < NS) out[4 * v + 1] = w.y;
+            if (4 * v + 2 < NS) out[4 * v + 2] = w.z;
+            if (4 * v + 3 < NS) out[4 * v + 3] = w.w;
+        }
+    };
+    auto reader = [&](int c0, int c1, int c2) {
+        return node + sel3(c0, o.x[2], 0, o.x[0]) + sel3(c1, o.y[2], 0, o.y[0]) + sel3(c2, o.z[2], 0, o.z[0]);
     };
 
     S fin[NL];
@@ -649,31 +720,38 @@ __global__ __launch_bounds__(UPD_THREADS) __attribute__((amdgpu_waves_per_eu(3, 
             } else {
                 if (c1 < 1) load(i + 1, offyz + sel3(c1 + 1, o.y[0], 0, o.y[2]) - sel3(c1, o.y[0], 0, o.y[2]) + o.x[0], fnx);
             }
+            // scales of the node that reads what this velocity writes (L2 hits,
+            // consumed after the species work below)
+            float srd[NS];
+            if constexpr (sizeof(S) == 4) load_scales(par ^ 1, reader(c0, c1, c2), srd);
             const double T = sp[PRM_T][lane], ux = sp[PRM_U][lane];
-            double D[M], Xe[M];
+            double D[M];
 #pragma unroll
             for (int q = 0; q < M; ++q) {
+                reload_barrier();   // keep each species' LDS reads next to their use
                 const double tq = Ra[q] * T;
                 const double vx = ux + sp[PRM_SP + 6 * q + 1][lane];
-                Xe[q] = psi_c<c0>(ux, fma(ux, ux, tq));
+                const double Xe = psi_c<c0>(ux, fma(ux, ux, tq));
                 const double Xs = psi_c<c0>(vx, fma(vx, vx, tq));
-                D[q] = sp[PRM_SP + 6 * q][lane] * (Xe[q] * YZe[q] - Xs * YZs[q]);
+                D[q] = sp[PRM_SP + 6 * q][lane] * (Xe * YZe[q] - Xs * YZs[q]);
             }
             // species (eq. finalNumericalEquationsReactive with eq. fStar)
 #pragma unroll
             for (int j = 0; j < M - 1; ++j) {
+                reload_barrier();
                 double F = 0.0;
 #pragma unroll
                 for (int q = 0; q < M; ++q)
                     if (q != j) F = fma(Ks[j * M + q], D[q], F);
                 const double ra = sp[PRM_SP + 6 * j][lane], be = sp[PRM_SP + 6 * j + 4][lane],
                              dr = sp[PRM_SP + 6 * j + 5][lane];
-                const double W = Xe[j] * YZe[j];
+                const double W = psi_c<c0>(ux, fma(ux, ux, Ra[j] * T)) * YZe[j];   // W_ji, recomputed
                 const int li = j * Q + i;
                 double f = (double)fin[j];
-                if constexpr (sizeof(S) == 4) f += ref[li];
+                if constexpr (sizeof(S) == 4) f += ref_of(ssc[j][lane], ref[li]);
                 const double out = f + 2.0 * be * (ra * W - f) + (be - 1.0) * (fcm * ra * F) + W * dr;
-                if constexpr (sizeof(S) == 4) st_at(dst + (size_t)li * L.N, node, __double2float_rn(out - ref[li]));
+                if constexpr (sizeof(S) == 4)
+                    st_at(dst + (size_t)li * L.N, node, __double2float_rn(out - ref_of(srd[j], ref[li])));
                 else st_at(dst + (size_t)li * L.N, node, out);
             }
             const double rho = sp[PRM_RHO][lane], th = sp[PRM_TH][lane], omega = sp[PRM_OMEGA][lane];
@@ -681,17 +759,19 @@ __global__ __launch_bounds__(UPD_THREADS) __attribute__((amdgpu_waves_per_eu(3, 
             {
                 const int li = (M - 1) * Q + i;
                 double f = (double)fin[M - 1];
-                if constexpr (sizeof(S) == 4) f += ref[li];
+                if constexpr (sizeof(S) == 4) f += ref_of(ssc[M - 1][lane], ref[li]);
                 const double fe = rho * psi_c<c0>(ux, th + ux * ux + exf * sp[GR][lane]) * Fyz;
                 const double out = f + omega * (fe - f);
-                if constexpr (sizeof(S) == 4) st_at(dst + (size_t)li * L.N, node, __double2float_rn(out - ref[li]));
+                if constexpr (sizeof(S) == 4)
+                    st_at(dst + (size_t)li * L.N, node, __double2float_rn(out - ref_of(srd[M - 1], ref[li])));
                 else st_at(dst + (size_t)li * L.N, node, out);
             }
             // energy lattice (eqs. g, geq_i, gstar)
             {
                 const int li = M * Q + i;
                 double g = (double)fin[M];
-                if constexpr (sizeof(S) == 4) g += ref[li];
+                if constexpr (sizeof(S) == 4)
+                    g += ref_g(ssc[M][lane], ssc[M - 1][lane], ref[li], ref[REF_K<M> + i]);
                 const double ux2 = ux * ux;
                 const double Wx = psi_c<c0>(ux, th + ux2);
                 double kx;
@@ -719,7 +799,9 @@ __global__ __launch_bounds__(UPD_THREADS) __attribute__((amdgpu_waves_per_eu(3, 
                         out += 0.5 * (double)(c1 + c2) * Qa;
                     }
                 }
-                if constexpr (sizeof(S) == 4) st_at(dst + (size_t)li * L.N, node, __double2float_rn(out - ref[li]));
+                if constexpr (sizeof(S) == 4)
+                    st_at(dst + (size_t)li * L.N, node,
+                          __double2float_rn(out - ref_g(srd[M], srd[M - 1], ref[li], ref[REF_K<M> + i])));
                 else st_at(dst + (size_t)li * L.N, node, out);
             }
 #pragma unroll
@@ -927,24 +1009,43 @@ __global__ __launch_bounds__(BC_THREADS) void k_boundary(const LatDev* __restric
     const int ld_off = (in && wall) ? node : off;
     const int ld_i = (in && wall) ? Q - 1 - i : i;
     const bool need = act && (!in || wall);       // open-face incoming links take no population
+    const int par = (L.parity0 + t) & 1;
+    const RLBM_CONST double* G = as_const(L.ref);
+    // FP32 deviation storage: the advected value's reference belongs to this
+    // node; a bounce-back source f'_{opp(i)}(x) is referred to the node that
+    // would pull it, the pull source x - c_i (wrapped)
+    float s_ld[M + 1], s_own[M + 1];
+    if constexpr (sizeof(S) == 4) {
+        const RLBM_GLOBAL float* a0 = scale_at(L, par, (in && wall) ? off : node);
+        const RLBM_GLOBAL float* a1 = scale_at(L, par, node);
+#pragma unroll
+        for (int l = 0; l <= M; ++l) { s_ld[l] = a0[l]; s_own[l] = a1[l]; }
+    }
+    auto refv = [&](const float* sc, int l, int li) -> double {
+        if constexpr (sizeof(S) == 4)
+            return l < M ? ref_of(sc[l], G[li]) : ref_g(sc[M], sc[M - 1], G[li], G[REF_K<M> + li % Q]);
+        else return 0.0;
+    };
     double pa[M], pf = 0.0, pg = 0.0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
         pa[a] = 0.0;
         if (a == s || !need) continue;
-        const int li = lat_of<M>(a, s) * Q + ld_i;
-        pa[a] = Codec<S>::ld(src, (size_t)li * N + ld_off, L.ref, li);
+        const int l = lat_of<M>(a, s);
+        const int li = l * Q + ld_i;
+        pa[a] = Codec<S>::ld(src, (size_t)li * N + ld_off, refv(s_ld, l, li));
     }
     if (need) {
         const int lf = (M - 1) * Q + ld_i;
-        pf = Codec<S>::ld(src, (size_t)lf * N + ld_off, L.ref, lf);
+        pf = Codec<S>::ld(src, (size_t)lf * N + ld_off, refv(s_ld, M - 1, lf));
         if (!in) {
             const int lg = M * Q + i;
-            pg = Codec<S>::ld(src, (size_t)lg * N + off, L.ref, lg);
+            pg = Codec<S>::ld(src, (size_t)lg * N + off, refv(s_own, M, lg));
         }
     }
-    auto put = [&](int li, double val) {
-        if (act) Codec<S>::st(L.bcbuf, (size_t)li * L.n_if + k, val, L.ref, li);
+    auto put = [&](int l, double val) {
+        const int li = l * Q + i;
+        if (act) Codec<S>::st(L.bcbuf, (size_t)li * L.n_if + k, val, refv(s_own, l, li));
     };
 
     if (wall) {
@@ -975,9 +1076,9 @@ __global__ __launch_bounds__(BC_THREADS) void k_boundary(const LatDev* __restric
         bc_eq<M, true>(mc, Lc, c0, c1, c2, eL, fL, gL);
 #pragma unroll
         for (int a = 0; a < M; ++a)
-            if (a != s) put(lat_of<M>(a, s) * Q + i, in ? 2.0 * eA[a] - eL[a] : eA[a] + pa[a] - eL[a]);
-        put((M - 1) * Q + i, in ? 2.0 * fA - fL : fA + pf - fL);
-        put(M * Q + i, in ? 2.0 * gA - gL : gA + pg - gL);
+            if (a != s) put(lat_of<M>(a, s), in ? 2.0 * eA[a] - eL[a] : eA[a] + pa[a] - eL[a]);
+        put(M - 1, in ? 2.0 * fA - fL : fA + pf - fL);
+        put(M, in ? 2.0 * gA - gL : gA + pg - gL);
     } else if (type == RLBM_FACE_INLET) {
         // flux inlet (section 4.3)
         BcState<M, false> A;   // inlet equilibrium (eqs. in_f, in_g, in_fa)
@@ -1002,9 +1103,9 @@ __global__ __launch_bounds__(BC_THREADS) void k_boundary(const LatDev* __restric
         bc_eq<M, false>(mc, Tg, c0, c1, c2, eT, fT, gT);
 #pragma unroll
         for (int a = 0; a < M; ++a)
-            if (a != s) put(lat_of<M>(a, s) * Q + i, eT[a] + (in ? eA[a] : pa[a]) - eL[a]);
-        put((M - 1) * Q + i, fT + (in ? fA : pf) - fL);
-        put(M * Q + i, gT + (in ? gA : pg) - gL);
+            if (a != s) put(lat_of<M>(a, s), eT[a] + (in ? eA[a] : pa[a]) - eL[a]);
+        put(M - 1, fT + (in ? fA : pf) - fL);
+        put(M, gT + (in ? gA : pg) - gL);
     } else {
         // outlet (section 4.4): LODI state from the previous outlet state and
         // the previous post-boundary moments of the first interior node
@@ -1070,9 +1171,9 @@ __global__ __launch_bounds__(BC_THREADS) void k_boundary(const LatDev* __restric
         bc_eq<M, false>(mc, Lc, c0, c1, c2, eL, fL, gL);
 #pragma unroll
         for (int a = 0; a < M; ++a)
-            if (a != s) put(lat_of<M>(a, s) * Q + i, in ? 2.0 * eA[a] - eL[a] : eA[a] + pa[a] - eL[a]);
-        put((M - 1) * Q + i, in ? 2.0 * fA - fL : fA + pf - fL);
-        put(M * Q + i, in ? 2.0 * gA - gL : gA + pg - gL);
+            if (a != s) put(lat_of<M>(a, s), in ? 2.0 * eA[a] - eL[a] : eA[a] + pa[a] - eL[a]);
+        put(M - 1, in ? 2.0 * fA - fL : fA + pf - fL);
+        put(M, in ? 2.0 * gA - gL : gA + pg - gL);
     }
     if (fail && v == 0) atomicOr(flag, 1);
 }
@@ -1080,6 +1181,58 @@ __global__ __launch_bounds__(BC_THREADS) void k_boundary(const LatDev* __restric
 // ---------------------------------------------------------------------------
 // initial state, read-out, populations I/O, invariants
 // ---------------------------------------------------------------------------
+// Node that pulls the population stored at slot (node, i): node + c_i,
+// wrapped on every axis (the placeholder rule of the pull offsets).
+__device__ __forceinline__ long long reader_of(const LatDev& L, long long node, int i) {
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int x = (int)(node % nx);
+    const long long r = node / nx;
+    const int y = (int)(r % ny), z = (int)(r / ny);
+    const int xr = (x + cx_of(i) + nx) % nx, yr = (y + cy_of(i) + ny) % ny, zr = (z + cz_of(i) + nz) % nz;
+    return ((long long)zr * ny + yr) * nx + xr;
+}
+
+// Reference value of slot (node, i) of lattice l in buffer q (FP32 storage).
+template <int M, typename S>
+__device__ __forceinline__ double slot_ref(const LatDev& L, int q, long long node, int l, int i) {
+    if constexpr (sizeof(S) == 8) {
+        return 0.0;
+    } else {
+        const RLBM_CONST double* G = as_const(L.ref);
+        const RLBM_GLOBAL float* sc = scale_at(L, q, reader_of(L, node, i));
+        if (l == M) return ref_g(sc[M], sc[M - 1], G[l * Q + i], G[REF_K<M> + i]);
+        return ref_of(sc[l], G[l * Q + i]);
+    }
+}
+
+// Reference scales of the initial populations: the zeroth moments rho_a of
+// the stored species, rho and rho E.
+template <int M>
+__global__ __launch_bounds__(256) void k_scale_init(const LatDev* __restrict__ lat, const double* __restrict__ rho_in,
+                                                    const double* __restrict__ u_in, const double* __restrict__ T_in,
+                                                    const double* __restrict__ Y_in) {
+    const LatDev& L = *lat;
+    const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (node >= L.N) return;
+    MechC mc = *as_const(L.mech);
+    const size_t N = (size_t)L.N;
+    const int s = L.slaved;
+    const double rho = rho_in[node];
+    float* so = L.rscale[L.parity0] + (size_t)node * L.rss;
+    double Y[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) Y[a] = Y_in[a * N + node];
+    for (int l = 0; l < M - 1; ++l) {
+        const int a = l + (l >= s ? 1 : 0);
+        so[l] = __double2float_rn(rho * Y_in[a * N + node]);
+    }
+    so[M - 1] = __double2float_rn(rho);
+    double usq = 0.0;
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) usq += u_in[dd * N + node] * u_in[dd * N + node];
+    so[M] = __double2float_rn(rho * (mix_U<M>(mc, Y, T_in[node]) + 0.5 * usq));
+}
+
 template <int M, typename S>
 __global__ __launch_bounds__(256) void k_init(const LatDev* __restrict__ lat, const double* __restrict__ rho_in,
                                               const double* __restrict__ u_in, const double* __restrict__ T_in,
@@ -1101,7 +1254,8 @@ __global__ __launch_bounds__(256) void k_init(const LatDev* __restrict__ lat, co
     for (int l = 0; l <= M; ++l)
         for (int i = 0; i < Q; ++i) {
             const int li = l * Q + i;
-            Codec<S>::st(dst, (size_t)li * N + node, eq_value<M, false>(mc, e, l, L.slaved, i), L.ref, li);
+            Codec<S>::st(dst, (size_t)li * N + node, eq_value<M, false>(mc, e, l, L.slaved, i),
+                         slot_ref<M, S>(L, L.parity0, node, l, i));
         }
     double* aux = L.aux;
     aux[AUX_RHO * N + node] = e.rho;
@@ -1128,22 +1282,48 @@ __global__ __launch_bounds__(256) void k_init(const LatDev* __restrict__ lat, co
     }
 }
 
-// Reference populations for FP32 deviation storage: the zero-velocity
-// equilibria of the domain-mean state.
+// Reference shapes for FP32 deviation storage (one block): for the stored
+// species, the momentum lattice and the energy lattice's internal-energy part
+// the zero-velocity equilibrium shape (unit zeroth moment) at the
+// domain-mean temperature and composition, and the energy lattice's theta^2
+// part K (eq. geq_i at u = 0 with rho = 1, U = 0); then the zeroth moments,
+// the momentum shape's sum_i G c_x^2 and sum_i K_i.
 template <int M>
-__global__ void k_refs(const LatDev* __restrict__ lat, double* __restrict__ ref, double rho, double T,
-                       const double* __restrict__ Y) {
+__global__ __launch_bounds__(512) void k_refs(const LatDev* __restrict__ lat, double* __restrict__ ref, double rho,
+                                              double T, const double* __restrict__ Y) {
+    (void)rho;
     const LatDev& L = *lat;
-    const int li = blockIdx.x * blockDim.x + threadIdx.x;
-    if (li >= (M + 1) * Q) return;
+    const int li = threadIdx.x;
     MechC mc = *as_const(L.mech);
-    EqState<M, false> e;
-    e.rho = rho;
-    e.u[0] = e.u[1] = e.u[2] = 0.0;
-#pragma unroll
-    for (int a = 0; a < M; ++a) e.Y[a] = Y[a];
-    eq_prepare<M, false>(mc, e, T);
-    ref[li] = eq_value<M, false>(mc, e, li / Q, L.slaved, li % Q);
+    const double th_mix = mc.R_univ * mix_inv_m<M>(mc, Y) * T;
+    if (li < (M + 1) * Q) {
+        const int l = li / Q, i = li % Q;
+        const int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);
+        double th = th_mix;
+        if (l < M - 1) th = mc.Ra[l + (l >= L.slaved ? 1 : 0)] * T;
+        // shapes are rounded to FP32 values (see ref_of)
+        ref[li] = (double)(float)(psi(c0, 0.0, th) * psi(c1, 0.0, th) * psi(c2, 0.0, th));
+        if (l == M) {
+            const double Wx = psi(c0, 0.0, th), Wy = psi(c1, 0.0, th), Wz = psi(c2, 0.0, th);
+            const double k0 = -th * th, k1 = 0.5 * th * th;
+            const double kx = c0 ? k1 : k0, ky = c1 ? k1 : k0, kz = c2 ? k1 : k0;
+            ref[REF_K<M> + i] = (double)(float)(kx * Wy * Wz + Wx * (ky * Wz + Wy * kz));
+        }
+    }
+    __syncthreads();
+    if (li <= M) {
+        double m0 = 0.0;
+        for (int i = 0; i < Q; ++i) m0 += ref[li * Q + i];
+        ref[REF_M0<M> + li] = m0;
+    } else if (li == M + 1) {
+        double m2 = 0.0;
+        for (int i = 0; i < Q; ++i) m2 += ref[(M - 1) * Q + i] * (double)(cx_of(i) * cx_of(i));
+        ref[REF_M2<M>] = m2;
+    } else if (li == M + 2) {
+        double k0 = 0.0;
+        for (int i = 0; i < Q; ++i) k0 += ref[REF_K<M> + i];
+        ref[REF_K0<M>] = k0;
+    }
 }
 
 template <int M, typename S>
@@ -1155,13 +1335,14 @@ __global__ __launch_bounds__(256) void k_fields(const LatDev* __restrict__ lat, 
     if (node >= L.N) return;
     MechC mc = *as_const(L.mech);
     const size_t N = (size_t)L.N;
-    const void* src = L.pop[(L.parity0 + t) & 1];
+    const int q = (L.parity0 + t) & 1;
+    const void* src = L.pop[q];
     const int s = L.slaved;
     double rho = 0.0, j[3] = {0.0, 0.0, 0.0}, rE = 0.0, ra[M];
     for (int i = 0; i < Q; ++i) {
-        const double f = Codec<S>::ld(src, (size_t)((M - 1) * Q + i) * N + node, L.ref, (M - 1) * Q + i);
+        const double f = Codec<S>::ld(src, (size_t)((M - 1) * Q + i) * N + node, slot_ref<M, S>(L, q, node, M - 1, i));
         rho += f; j[0] += f * cx_of(i); j[1] += f * cy_of(i); j[2] += f * cz_of(i);
-        rE += Codec<S>::ld(src, (size_t)(M * Q + i) * N + node, L.ref, M * Q + i);
+        rE += Codec<S>::ld(src, (size_t)(M * Q + i) * N + node, slot_ref<M, S>(L, q, node, M, i));
     }
     double rs = rho;
 #pragma unroll
@@ -1169,7 +1350,8 @@ __global__ __launch_bounds__(256) void k_fields(const LatDev* __restrict__ lat, 
         ra[a] = 0.0;
         if (a == s) continue;
         const int l = lat_of<M>(a, s);
-        for (int i = 0; i < Q; ++i) ra[a] += Codec<S>::ld(src, (size_t)(l * Q + i) * N + node, L.ref, l * Q + i);
+        for (int i = 0; i < Q; ++i)
+            ra[a] += Codec<S>::ld(src, (size_t)(l * Q + i) * N + node, slot_ref<M, S>(L, q, node, l, i));
         rs -= ra[a];
     }
 #pragma unroll
@@ -1193,7 +1375,7 @@ __global__ __launch_bounds__(256) void k_fields(const LatDev* __restrict__ lat, 
     if (P_o) P_o[node] = rho * mc.R_univ * mix_inv_m<M>(mc, Y) * T;
 }
 
-template <typename S>
+template <int M, typename S>
 __global__ __launch_bounds__(256) void k_pops(const LatDev* __restrict__ lat, long long t, int nl, double* buf,
                                               int write) {
     const LatDev& L = *lat;
@@ -1201,9 +1383,12 @@ __global__ __launch_bounds__(256) void k_pops(const LatDev* __restrict__ lat, lo
     const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;
     const int li = (int)(idx / L.N);
-    void* p = L.pop[(L.parity0 + t) & 1];
-    if (write) Codec<S>::st(p, idx, buf[idx], L.ref, li);
-    else buf[idx] = Codec<S>::ld(p, idx, L.ref, li);
+    const long long node = (long long)(idx % L.N);
+    const int q = (L.parity0 + t) & 1;
+    void* p = L.pop[q];
+    const double ref = slot_ref<M, S>(L, q, node, li / Q, li % Q);
+    if (write) Codec<S>::st(p, idx, buf[idx], ref);
+    else buf[idx] = Codec<S>::ld(p, idx, ref);
 }
 
 // Per-block partial sums of the invariants; nv = 6 + E values per block.
@@ -1218,12 +1403,14 @@ __global__ __launch_bounds__(256) void k_invariants(const LatDev* __restrict__ l
     double v[6 + MAXE];
     for (int q = 0; q < 6 + MAXE; ++q) v[q] = 0.0;
     if (node < L.N) {
-        const void* src = L.pop[(L.parity0 + t) & 1];
+        const int q = (L.parity0 + t) & 1;
+        const void* src = L.pop[q];
         double bad = 0.0;
         double rho = 0.0;
         for (int i = 0; i < Q; ++i) {
-            const double f = Codec<S>::ld(src, (size_t)((M - 1) * Q + i) * N + node, L.ref, (M - 1) * Q + i);
-            const double g = Codec<S>::ld(src, (size_t)(M * Q + i) * N + node, L.ref, M * Q + i);
+            const double f =
+                Codec<S>::ld(src, (size_t)((M - 1) * Q + i) * N + node, slot_ref<M, S>(L, q, node, M - 1, i));
+            const double g = Codec<S>::ld(src, (size_t)(M * Q + i) * N + node, slot_ref<M, S>(L, q, node, M, i));
             if (!isfinite(f) || !isfinite(g)) bad = 1.0;
             rho += f;
             v[1] += f * cx_of(i); v[2] += f * cy_of(i); v[3] += f * cz_of(i);
@@ -1238,7 +1425,7 @@ __global__ __launch_bounds__(256) void k_invariants(const LatDev* __restrict__ l
             if (a == s) continue;
             const int l = lat_of<M>(a, s);
             for (int i = 0; i < Q; ++i) {
-                const double f = Codec<S>::ld(src, (size_t)(l * Q + i) * N + node, L.ref, l * Q + i);
+                const double f = Codec<S>::ld(src, (size_t)(l * Q + i) * N + node, slot_ref<M, S>(L, q, node, l, i));
                 if (!isfinite(f)) bad = 1.0;
                 ra[a] += f;
             }
@@ -1325,6 +1512,8 @@ template <typename S>
 static hipError_t launch_init_t(int M, const LatDev* lat, long long N, const double* rho, const double* u,
                                 const double* T, const double* Y, hipStream_t st) {
     const int blocks = (int)((N + 255) / 256);
+    if constexpr (sizeof(S) == 4)
+        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_scale_init<MM>), dim3(blocks), dim3(256), 0, st, lat, rho, u, T, Y))
     RLBM_DISPATCH(M, hipLaunchKernelGGL((k_init<MM, S>), dim3(blocks), dim3(256), 0, st, lat, rho, u, T, Y))
     return hipGetLastError();
 }
@@ -1337,9 +1526,7 @@ hipError_t launch_init(int M, int storage, const LatDev* lat, long long N, const
 
 hipError_t launch_refs(int M, const LatDev* lat, double* ref, double rho, double T, const double* Y,
                        hipStream_t st) {
-    const int n = (M + 1) * Q;
-    RLBM_DISPATCH(M, hipLaunchKernelGGL((k_refs<MM>), dim3((n + 63) / 64), dim3(64), 0, st, lat, ref, rho,
-                                                 T, Y))
+    RLBM_DISPATCH(M, hipLaunchKernelGGL((k_refs<MM>), dim3(1), dim3(512), 0, st, lat, ref, rho, T, Y))
     return hipGetLastError();
 }
 
@@ -1358,14 +1545,16 @@ hipError_t launch_fields(int M, int storage, const LatDev* lat, long long N, lon
                                            : launch_fields_t<double>(M, lat, N, t, rho, u, T, Y, P, flag, st);
 }
 
-hipError_t launch_pops(int storage, const LatDev* lat, long long N, int nl, long long t, double* buf, int write,
-                       hipStream_t st) {
+hipError_t launch_pops(int M, int storage, const LatDev* lat, long long N, int nl, long long t, double* buf,
+                       int write, hipStream_t st) {
     const size_t total = (size_t)nl * Q * (size_t)N;
     const int blocks = (int)((total + 255) / 256);
     if (storage == RLBM_STORAGE_F32_DEV)
-        hipLaunchKernelGGL((k_pops<float>), dim3(blocks), dim3(256), 0, st, lat, t, nl, buf, write);
+        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_pops<MM, float>), dim3(blocks), dim3(256), 0, st, lat, t, nl, buf,
+                                                write))
     else
-        hipLaunchKernelGGL((k_pops<double>), dim3(blocks), dim3(256), 0, st, lat, t, nl, buf, write);
+        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_pops<MM, double>), dim3(blocks), dim3(256), 0, st, lat, t, nl, buf,
+                                                write))
     return hipGetLastError();
 }
 

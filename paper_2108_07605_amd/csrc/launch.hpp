@@ -31,8 +31,8 @@ hipError_t launch_refs(int M, const LatDev* lat, double* ref, double rho, double
                        hipStream_t st);
 hipError_t launch_fields(int M, int storage, const LatDev* lat, long long N, long long t, double* rho, double* u,
                          double* T, double* Y, double* P, int* flag, hipStream_t st);
-hipError_t launch_pops(int storage, const LatDev* lat, long long N, int nl, long long t, double* buf, int write,
-                       hipStream_t st);
+hipError_t launch_pops(int M, int storage, const LatDev* lat, long long N, int nl, long long t, double* buf,
+                       int write, hipStream_t st);
 hipError_t launch_invariants(int M, int storage, const LatDev* lat, long long N, long long t, double* partial,
                              int nv, double* out, hipStream_t st);
 bool species_supported(int M);

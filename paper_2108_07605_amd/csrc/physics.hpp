@@ -64,7 +64,9 @@ struct LatDev {
     const int* if_out;          // [n_if] outlet slot or -1
     void* bcbuf;                // [L * 27][n_if] post-boundary populations (storage format)
     double* out_state;          // [5 + M][n_out]: rho, ux, uy, uz, T, Y
-    const double* ref;          // [L * 27] reference populations (FP32 storage)
+    const double* ref;          // [L * 27] reference shapes G_li, then [L] sum_i G_li, then sum_i G_fi c_ix^2 (FP32 storage)
+    float* rscale[2];           // [N][rss] reference scales s_l of the populations in pop[q] (FP32 storage)
+    int rss, pad2;              // floats per node in rscale (L rounded up to 4)
     const double* slotc;        // [M + M * M] R_a and 1/(D_ref m_a m_b) in slot order (slaved species last)
     double rho_in, u_in, T_in, P_inf, sigma;
     double Y_in[MAXM];

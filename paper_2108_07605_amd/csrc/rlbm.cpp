@@ -42,7 +42,8 @@ constexpr int NPHASE = 5;   // boundary, local, chemistry, gradients, update
 
 struct Plan {
     size_t off_lat, off_mech, off_blk, off_flag, off_ref, off_pop0, off_pop1, off_aux, off_prm, off_ifindex, off_ifnode,
-        off_ifmask, off_iftype, off_ifT, off_ifout, off_bcbuf, off_out, off_partial, off_invout, off_slot, total;
+        off_ifmask, off_iftype, off_ifT, off_ifout, off_bcbuf, off_out, off_partial, off_invout, off_slot,
+        off_rscale0, off_rscale1, total;
 };
 
 struct Geometry {
@@ -170,7 +171,7 @@ Plan make_plan(const rlbm_lattice_desc* d, int M, int E, const Geometry& g) {
     p.off_mech = take(sizeof(MechDev));
     p.off_blk = take(6 * sizeof(int));
     p.off_flag = take(sizeof(int));
-    p.off_ref = take((size_t)L * Q * sizeof(double));
+    p.off_ref = take(((size_t)L * Q + L + Q + 2) * sizeof(double));
     p.off_slot = take((size_t)(M + M * M) * sizeof(double));
     p.off_pop0 = take((size_t)L * Q * N * s);
     p.off_pop1 = take((size_t)L * Q * N * s);
@@ -186,6 +187,9 @@ Plan make_plan(const rlbm_lattice_desc* d, int M, int E, const Geometry& g) {
     p.off_out = take((size_t)(5 + M) * g.n_out * sizeof(double));
     p.off_partial = take(nblocks * (6 + E) * sizeof(double));
     p.off_invout = take((6 + E) * sizeof(double));
+    const size_t rss = d->storage == RLBM_STORAGE_F32_DEV ? (size_t)((M + 1 + 3) / 4 * 4) : 0;
+    p.off_rscale0 = take(rss * N * sizeof(float));
+    p.off_rscale1 = take(rss * N * sizeof(float));
     p.total = o;
     return p;
 }
@@ -390,6 +394,9 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     h.bcbuf = base + p.off_bcbuf;
     h.out_state = (double*)(base + p.off_out);
     h.ref = d->storage == RLBM_STORAGE_F32_DEV ? (const double*)(base + p.off_ref) : nullptr;
+    h.rss = d->storage == RLBM_STORAGE_F32_DEV ? (M + 1 + 3) / 4 * 4 : 0;
+    h.rscale[0] = d->storage == RLBM_STORAGE_F32_DEV ? (float*)(base + p.off_rscale0) : nullptr;
+    h.rscale[1] = d->storage == RLBM_STORAGE_F32_DEV ? (float*)(base + p.off_rscale1) : nullptr;
     const rlbm_face& fi = d->faces[0];
     if (fi.type == RLBM_FACE_INLET) {
         h.rho_in = fi.rho_in; h.u_in = fi.u_in; h.T_in = fi.T_in;
@@ -451,6 +458,25 @@ int rlbm_lattice_shape(const rlbm_lattice* lat, int32_t* L, int64_t* N, int64_t*
     return RLBM_OK;
 }
 
+// Slot order for the collision: stored species in lattice order, then the
+// slaved one; gas constants R_a and couplings 1/(D_ref m_a m_b) permuted.
+// The host vector is synchronised before it goes out of scope.
+static int upload_slot_table(rlbm_lattice* lat) {
+    const int M = lat->M;
+    std::vector<double> slot((size_t)M + (size_t)M * M);
+    const int sl = lat->host.slaved;
+    auto spc = [&](int j) { return j < M - 1 ? j + (j >= sl ? 1 : 0) : sl; };
+    for (int j = 0; j < M; ++j) {
+        slot[j] = lat->mech.Ra[spc(j)];
+        for (int q = 0; q < M; ++q) slot[M + (size_t)j * M + q] = lat->mech.Kab[spc(j)][spc(q)];
+    }
+    HIP_TRY(hipMemcpyAsync((void*)lat->host.slotc, slot.data(), slot.size() * sizeof(double), hipMemcpyHostToDevice,
+                           lat->stream),
+            "upload");
+    HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
+    return RLBM_OK;
+}
+
 int rlbm_set_state(rlbm_lattice* lat, const double* rho, const double* u, const double* T, const double* Y,
                    int on_device) {
     if (!lat || !rho || !u || !T || !Y) return fail(RLBM_EINVAL, "null argument");
@@ -505,20 +531,10 @@ int rlbm_set_state(rlbm_lattice* lat, const double* rho, const double* u, const 
     lat->steps_done = 0;
     lat->host.parity0 = 0;
     HIP_TRY(hipMemcpyAsync(lat->d_lat, &lat->host, sizeof(LatDev), hipMemcpyHostToDevice, lat->stream), "upload");
-    // slot order for the collision: stored species in lattice order, then the
-    // slaved one; gas constants R_a and couplings 1/(D_ref m_a m_b) permuted
-    std::vector<double> slot((size_t)M + (size_t)M * M);
     {
-        const int sl = lat->host.slaved;
-        auto spc = [&](int j) { return j < M - 1 ? j + (j >= sl ? 1 : 0) : sl; };
-        for (int j = 0; j < M; ++j) {
-            slot[j] = lat->mech.Ra[spc(j)];
-            for (int q = 0; q < M; ++q) slot[M + (size_t)j * M + q] = lat->mech.Kab[spc(j)][spc(q)];
-        }
+        const int rc = upload_slot_table(lat);
+        if (rc) return rc;
     }
-    HIP_TRY(hipMemcpyAsync((void*)lat->host.slotc, slot.data(), slot.size() * sizeof(double), hipMemcpyHostToDevice,
-                           lat->stream),
-            "upload");
     // device staging for the fields: the second population buffer is idle now
     double* stage = (double*)lat->host.pop[1];
     HIP_TRY(hipMemcpyAsync(stage, hf.data(), nf * sizeof(double), hipMemcpyHostToDevice, lat->stream), "upload");
@@ -630,7 +646,7 @@ static int pops_io(rlbm_lattice* lat, double* buf, int on_device, int write) {
     const size_t N = (size_t)lat->geo.N;
     const size_t n = (size_t)lat->L * Q * N;
     if (on_device) {
-        HIP_TRY(launch_pops(lat->storage, lat->d_lat, (long long)N, lat->L, lat->steps_done, buf, write, lat->stream),
+        HIP_TRY(launch_pops(lat->M, lat->storage, lat->d_lat, (long long)N, lat->L, lat->steps_done, buf, write, lat->stream),
                 "populations kernel");
         HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
         return RLBM_OK;
@@ -640,7 +656,7 @@ static int pops_io(rlbm_lattice* lat, double* buf, int on_device, int write) {
     hipError_t e = hipSuccess;
     if (write) e = hipMemcpy(tmp, buf, n * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = launch_pops(lat->storage, lat->d_lat, (long long)N, lat->L, lat->steps_done, tmp, write, lat->stream);
+        e = launch_pops(lat->M, lat->storage, lat->d_lat, (long long)N, lat->L, lat->steps_done, tmp, write, lat->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(lat->stream);
     if (e == hipSuccess && !write) e = hipMemcpy(buf, tmp, n * sizeof(double), hipMemcpyDeviceToHost);
     (void)hipFree(tmp);
@@ -652,6 +668,95 @@ int rlbm_read_populations(rlbm_lattice* lat, double* buf, int on_device) { retur
 
 int rlbm_write_populations(rlbm_lattice* lat, const double* buf, int on_device) {
     return pops_io(lat, const_cast<double*>(buf), on_device, 1);
+}
+
+// ---------------------------------------------------------------------------
+// raw state snapshots
+// ---------------------------------------------------------------------------
+namespace {
+constexpr uint32_t STATE_MAGIC = 0x4d424c52u;   // "RLBM"
+struct StateHeader {
+    uint32_t magic, version;
+    int32_t M, L, storage, slaved, rss, pad;
+    int64_t N, n_out;
+};
+struct StateLayout {
+    size_t ref, pops, scale, aux, out, total;
+    size_t n_ref, n_pops, n_scale, n_aux, n_out;   // bytes of each section
+};
+StateLayout state_layout(const rlbm_lattice* lat) {
+    StateLayout s{};
+    const size_t N = (size_t)lat->geo.N, L = (size_t)lat->L, M = (size_t)lat->M;
+    const bool f32 = lat->storage == RLBM_STORAGE_F32_DEV;
+    s.n_ref = f32 ? (L * Q + L + Q + 2) * sizeof(double) : 0;
+    s.n_pops = L * Q * N * (f32 ? 4 : 8);
+    s.n_scale = f32 ? (size_t)lat->host.rss * N * sizeof(float) : 0;
+    s.n_aux = ((size_t)AUX_Y + M + 6) * N * sizeof(double);
+    s.n_out = (5 + M) * (size_t)lat->geo.n_out * sizeof(double);
+    size_t o = align256(sizeof(StateHeader));
+    s.ref = o; o = align256(o + s.n_ref);
+    s.pops = o; o = align256(o + s.n_pops);
+    s.scale = o; o = align256(o + s.n_scale);
+    s.aux = o; o = align256(o + s.n_aux);
+    s.out = o; o = align256(o + s.n_out);
+    s.total = o;
+    return s;
+}
+}  // namespace
+
+int rlbm_state_bytes(const rlbm_lattice* lat, size_t* bytes) {
+    if (!lat || !bytes) return fail(RLBM_EINVAL, "null argument");
+    *bytes = state_layout(lat).total;
+    return RLBM_OK;
+}
+
+int rlbm_save_state(rlbm_lattice* lat, void* buf, int on_device) {
+    if (!lat || !buf) return fail(RLBM_EINVAL, "null argument");
+    if (!lat->state_set) return fail(RLBM_EINVAL, "rlbm_set_state has not been called");
+    HIP_TRY(hipSetDevice(lat->device), "hipSetDevice");
+    HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
+    (void)on_device;   // hipMemcpyDefault resolves host or device pointers
+    const StateLayout sl = state_layout(lat);
+    const int q = (int)((lat->host.parity0 + lat->steps_done) & 1);
+    StateHeader h{STATE_MAGIC, 1u, lat->M, lat->L, lat->storage, lat->host.slaved, lat->host.rss, 0,
+                  lat->geo.N, lat->geo.n_out};
+    char* b = (char*)buf;
+    HIP_TRY(hipMemcpy(b, &h, sizeof(h), hipMemcpyDefault), "save state");
+    if (sl.n_ref) HIP_TRY(hipMemcpy(b + sl.ref, lat->d_ref, sl.n_ref, hipMemcpyDefault), "save state");
+    HIP_TRY(hipMemcpy(b + sl.pops, lat->host.pop[q], sl.n_pops, hipMemcpyDefault), "save state");
+    if (sl.n_scale) HIP_TRY(hipMemcpy(b + sl.scale, lat->host.rscale[q], sl.n_scale, hipMemcpyDefault), "save state");
+    HIP_TRY(hipMemcpy(b + sl.aux, lat->host.aux, sl.n_aux, hipMemcpyDefault), "save state");
+    if (sl.n_out) HIP_TRY(hipMemcpy(b + sl.out, lat->host.out_state, sl.n_out, hipMemcpyDefault), "save state");
+    return RLBM_OK;
+}
+
+int rlbm_load_state(rlbm_lattice* lat, const void* buf, int on_device) {
+    if (!lat || !buf) return fail(RLBM_EINVAL, "null argument");
+    HIP_TRY(hipSetDevice(lat->device), "hipSetDevice");
+    HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
+    (void)on_device;
+    const StateLayout sl = state_layout(lat);
+    const char* b = (const char*)buf;
+    StateHeader h{};
+    HIP_TRY(hipMemcpy(&h, b, sizeof(h), hipMemcpyDefault), "load state");
+    if (h.magic != STATE_MAGIC || h.version != 1u) return fail(RLBM_EINVAL, "not a lattice state snapshot");
+    if (h.M != lat->M || h.L != lat->L || h.storage != lat->storage || h.N != lat->geo.N ||
+        h.n_out != lat->geo.n_out || h.rss != lat->host.rss || h.slaved < 0 || h.slaved >= lat->M)
+        return fail(RLBM_EINVAL, "snapshot taken on a lattice of another shape, species count or storage");
+    lat->host.slaved = h.slaved;
+    HIP_TRY(hipMemcpy(lat->d_lat, &lat->host, sizeof(LatDev), hipMemcpyHostToDevice), "load state");
+    {
+        const int rc = upload_slot_table(lat);
+        if (rc) return rc;
+    }
+    const int q = (int)((lat->host.parity0 + lat->steps_done) & 1);
+    if (sl.n_ref) HIP_TRY(hipMemcpy(lat->d_ref, b + sl.ref, sl.n_ref, hipMemcpyDefault), "load state");
+    HIP_TRY(hipMemcpy(lat->host.pop[q], b + sl.pops, sl.n_pops, hipMemcpyDefault), "load state");
+    if (sl.n_scale) HIP_TRY(hipMemcpy(lat->host.rscale[q], b + sl.scale, sl.n_scale, hipMemcpyDefault), "load state");
+    HIP_TRY(hipMemcpy(lat->host.aux, b + sl.aux, sl.n_aux, hipMemcpyDefault), "load state");
+    if (sl.n_out) HIP_TRY(hipMemcpy(lat->host.out_state, b + sl.out, sl.n_out, hipMemcpyDefault), "load state");
+    lat->state_set = true;
+    return RLBM_OK;
 }
 
 int rlbm_invariants(rlbm_lattice* lat, double* out, int n_out) {

@@ -27,6 +27,7 @@ EXPORTS = (
     "rlbm_lattice_destroy", "rlbm_set_state", "rlbm_step", "rlbm_read_fields",
     "rlbm_read_populations", "rlbm_write_populations", "rlbm_invariants",
     "rlbm_lattice_shape", "rlbm_set_timing", "rlbm_kernel_times", "rlbm_batch_bytes",
+    "rlbm_state_bytes", "rlbm_save_state", "rlbm_load_state",
     "rlbm_batch_create", "rlbm_batch_step", "rlbm_batch_destroy", "rlbm_last_error",
 )
 
@@ -99,6 +100,9 @@ def lib():
         "rlbm_set_timing": (c_int, [vp, c_int]),
         "rlbm_kernel_times": (c_int, [vp, POINTER(c_double), POINTER(c_int64), c_int]),
         "rlbm_batch_bytes": (c_int, [c_int32, POINTER(c_size_t)]),
+        "rlbm_state_bytes": (c_int, [vp, POINTER(c_size_t)]),
+        "rlbm_save_state": (c_int, [vp, vp, c_int]),
+        "rlbm_load_state": (c_int, [vp, vp, c_int]),
         "rlbm_batch_create": (c_int, [POINTER(vp), c_int32, vp, c_size_t, POINTER(vp)]),
         "rlbm_batch_step": (c_int, [vp, POINTER(c_int64)]),
         "rlbm_batch_destroy": (None, [vp]),
@@ -280,6 +284,19 @@ class Lattice:
         torch = self.torch
         buf = torch.as_tensor(np.ascontiguousarray(pops, dtype=np.float64).ravel(), device="cuda")
         _check(lib().rlbm_write_populations(self.handle, c_void_p(buf.data_ptr()), 1))
+
+    def save_state(self):
+        """Raw snapshot (host bytes) for bit-exact resume."""
+        n = c_size_t()
+        _check(lib().rlbm_state_bytes(self.handle, ctypes.byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        _check(lib().rlbm_save_state(self.handle, buf.ctypes.data_as(c_void_p), 0))
+        return buf
+
+    def load_state(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib().rlbm_load_state(self.handle, buf.ctypes.data_as(c_void_p), 0))
+        return self
 
     def invariants(self):
         n = 6 + self.mech.E

@@ -68,7 +68,8 @@ def test_lattice_bytes_plan(mech9):
     b32 = rlbm.lattice_bytes(case, m, "f32dev")
     N, L = 64 * 16, 10
     assert b64 >= 2 * L * 27 * N * 8 and b32 >= 2 * L * 27 * N * 4
-    assert b64 - b32 >= 2 * L * 27 * N * 4 - 2048
+    # FP32 storage adds two buffers of per-node reference scales (12 floats)
+    assert b64 - b32 >= 2 * L * 27 * N * 4 - 2 * 12 * N * 4 - 4096
 
 
 @pytest.mark.parametrize("mutate,code", [

@@ -46,6 +46,7 @@ extern "C" {
 
 #define RLBM_MAX_SPECIES 12
 #define RLBM_MAX_REACTIONS 64
+#define RLBM_MAX_ORDER 4        /* molecules on either side of one reaction */
 #define RLBM_MAX_ELEMENTS 8
 
 /* Mechanism: species thermochemistry, reactions and transport, all in
@@ -77,8 +78,8 @@ typedef struct rlbm_mech_desc {
     const int32_t* composition;   /* [M][E] atoms per molecule (invariants); NULL if E = 0 */
     double R_univ;                /* universal gas constant > 0 */
     double ln_cstd;               /* standard concentration c_std(T) = exp(ln_cstd)/T */
-    const int32_t* nu_f;          /* [R][M] reactant coefficients, 0..3 */
-    const int32_t* nu_r;          /* [R][M] product coefficients, 0..3 */
+    const int32_t* nu_f;          /* [R][M] reactant coefficients, 0..3, sum <= RLBM_MAX_ORDER */
+    const int32_t* nu_r;          /* [R][M] product coefficients, 0..3, sum <= RLBM_MAX_ORDER */
     const double* lnA;            /* [R] */
     const double* beta;           /* [R] */
     const double* Ta;             /* [R] activation temperatures Ea/R (K) */
@@ -120,7 +121,7 @@ typedef struct rlbm_face {
 #define RLBM_STORAGE_F32_DEV 1    /* FP32 deviations from a per-(lattice, velocity) reference */
 
 typedef struct rlbm_lattice_desc {
-    int32_t nx, ny, nz;           /* >= 1 each; >= 2 along an axis with an inlet/outlet */
+    int32_t nx, ny, nz;           /* >= 1 each, nx ny nz <= 2^29; >= 2 along an axis with an inlet/outlet */
     rlbm_face faces[6];
     int32_t storage;              /* RLBM_STORAGE_* */
     int32_t substeps;             /* reaction sub-steps l >= 1 (eq. R3) */
@@ -198,7 +199,7 @@ int rlbm_lattice_shape(const rlbm_lattice* lat, int32_t* L, int64_t* N, int64_t*
 
 /* Per-kernel timing with HIP events recorded on the lattice stream around
  * every launch while enabled.  rlbm_kernel_times synchronises and returns,
- * for kernel k in {0: boundary, 1: local physics, 2: chemistry, 3: gradients, 4: update}, the accumulated
+ * for kernel k in {0: boundary, 1: moments, 2: diffusion, 3: chemistry, 4: gradients, 5: update}, the accumulated
  * milliseconds ms[k] and launch counts counts[k] since the last reset. */
 int rlbm_set_timing(rlbm_lattice* lat, int enable);
 int rlbm_kernel_times(rlbm_lattice* lat, double* ms, int64_t* counts, int n);

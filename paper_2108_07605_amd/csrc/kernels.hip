@@ -1,16 +1,17 @@
 // HIP kernels of the reactive-mixture lattice Boltzmann step for gfx950.
 //
-// One time step is three launches over a (possibly batched) work list:
+// One time step is six launches over a (possibly batched) work list:
 //   k_boundary  interface nodes: advection + wall / inlet / outlet
-//               reconstruction (section 4) into an FP64 side buffer;
-//   k_moments   every node: advection, moments, temperature (eq. temperature),
-//               then rho, u, T, Y and Phi_a = rho u_a (1 - 3 R T) - rho u_a^3
-//               are published for the neighbours;
-//   k_collide   every node: advection and moments again, same-time
-//               gradients from the neighbours' published fields, relaxation
-//               parameters, Stefan-Maxwell solve, reaction sub-steps and the
-//               collisions of all stored lattices, written to the other
-//               population buffer.
+//               reconstruction (section 4) into a side buffer;
+//   k_local     every node: advection, moments, temperature (eq. temperature),
+//               relaxation rates; publishes rho, u, T, Y, Phi_a and the
+//               enthalpy moments for the neighbours and starts the per-node
+//               record read by k_update;
+//   k_diff      Stefan-Maxwell diffusion velocities (eq. transform1);
+//   k_chem      reaction increment by l sub-steps (eq. R3);
+//   k_grad      same-time gradients of Phi_a and sum_b H_b Y_b;
+//   k_update    every node: advection again and the collisions of all stored
+//               lattices, written to the other population buffer.
 // Populations are structure-of-arrays [L][27][N] (x fastest), pulled from the
 // source buffer, so every load and store of a wavefront is coalesced.  The
 // storage type S is double (FP64) or float (FP32 deviation from a reference
@@ -80,6 +81,18 @@ __device__ __forceinline__ const RLBM_GLOBAL float* scale_at(const LatDev& L, in
     return as_global(L.rscale[q]) + (size_t)n * L.rss;
 }
 
+// Block index -> work tile, XCD-aware.  Workgroups are dispatched to the
+// eight XCDs round-robin (block b on XCD b mod 8), and each XCD has its own
+// L2.  Remapping gives every XCD one contiguous range of tiles, so tiles that
+// share cache lines (x-neighbours of the pull advection, the rows of a
+// gradient stencil) are processed by the same L2 at about the same time.
+// A bijection on [0, gridDim.x) for any grid size.
+__device__ __forceinline__ int xcd_block() {
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int q = nb >> 3, r = nb & 7, j = b & 7, i = b >> 3;
+    return j * q + (j < r ? j : r) + i;
+}
+
 // ---------------------------------------------------------------------------
 // work-list helpers
 // ---------------------------------------------------------------------------
@@ -122,157 +135,347 @@ __device__ __forceinline__ double sel3d(int c, double m, double z, double p) { r
 template <int M>
 __device__ __forceinline__ int lat_of(int a, int slaved) { return a - (a > slaved ? 1 : 0); }
 
-// Raw stored value (FP64, or FP32 deviation) of population (l, i) at node
-// offset off after advection and boundary reconstruction: interface nodes
-// (slot k >= 0) read the boundary buffer, all others pull from the source
-// buffer.
-template <typename S>
-__device__ __forceinline__ S ld_raw_off(const LatDev& L, const void* src, int k, int off, int l, int i) {
-    const int li = l * Q + i;
-    if (k >= 0) return static_cast<const S*>(L.bcbuf)[(size_t)li * L.n_if + k];
-    return static_cast<const S*>(src)[(size_t)li * L.N + off];
-}
-
-template <int M>
-struct Moments {
-    double rho, j[3], rhoE, q[3], P[6];   // P: xx, yy, zz, xy, xz, yz
-    double rho_a[M], j_a[M][3];
-};
-
+// ---------------------------------------------------------------------------
+// k_local: moments and everything else a node needs from its own populations
+// ---------------------------------------------------------------------------
 // Moments of the node's post-advection, post-boundary populations (eqs.
 // density1, momentum1, fdensity, f1momMomentum, g0momTotalEnergy), the
-// slaved species by difference (eq. strongest).  FULL adds P = sum f c c,
-// q = sum g c and the species momenta.  In FP32 deviation storage the sums
-// run over the stored deviations and the reference's own moments are added
-// in closed form (zeroth s_l sum_i G_li, second s_f sum_i G_fi c c, first
-// zero by symmetry).  With FP32 storage the stored lattices' zeroth moments
-// (rho_a, rho) are written to s_out, the scales of the references of the
-// populations written this step.
-template <int M, typename S, bool FULL>
-__device__ __forceinline__ void node_moments(const LatDev& L, const void* src, int k, int node, const PullOff& o,
-                                             int par, Moments<M>& m, float* s_out) {
+// slaved species by difference (eq. strongest), then the temperature (eq.
+// temperature), the relaxation rates and the local part of the energy flux.
+// The momentum and energy lattices are summed first so the mixture velocity
+// is known when each species lattice is summed: its velocity difference
+// u_a - u is written out at once and only rho_a stays in registers.  In FP32
+// deviation storage the sums run over the stored deviations and the
+// reference's own moments are added in closed form (zeroth s_l sum_i G_li,
+// second s_f sum_i G_fi c c, first zero by symmetry); the stored lattices'
+// zeroth moments (rho_a, rho, rho E) become the scales of the references of
+// the populations written this step.  The Stefan-Maxwell solve is left to
+// k_diff, which keeps this streaming kernel small in registers.
+template <int M>
+struct LocalMoments {
+    double rho, rhoE, j[3], q[3], Pd[3], Po[3];   // Pd: xx yy zz, Po: xy xz yz
+    double u[3];
+    double rho_a[M];
+};
+
+// Byte-offset addressing: a uniform base plus a 32-bit per-lane offset keeps
+// every population access in the scalar-base form (no 64-bit address math).
+template <typename S>
+__device__ __forceinline__ S ld_at(const RLBM_GLOBAL S* base, int idx) {
+    return *(const RLBM_GLOBAL S*)((const RLBM_GLOBAL char*)base + (unsigned)(idx * (int)sizeof(S)));
+}
+template <typename S>
+__device__ __forceinline__ void st_at(RLBM_GLOBAL S* base, int idx, S v) {
+    *(RLBM_GLOBAL S*)((RLBM_GLOBAL char*)base + (unsigned)(idx * (int)sizeof(S))) = v;
+}
+
+// Buffer-resource load: a wave-uniform base (scalar registers) plus a 32-bit
+// per-lane byte offset (node counts are limited so that idx * sizeof(S) fits).
+// An offset at or beyond nbytes reads zero instead of leaving the buffer.
+template <typename S>
+__device__ __forceinline__ S ldb(const RLBM_GLOBAL S* base, unsigned nbytes, int idx) {
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(unsigned long long)base, 0, (int)nbytes, 0x00020000);
+    if constexpr (sizeof(S) == 4)
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (unsigned)idx * 4u, 0, 0));
+    else
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (unsigned)idx * 8u, 0, 0));
+}
+__device__ __forceinline__ unsigned plane_bytes(long long N, int s) {
+    const unsigned long long b = (unsigned long long)N * (unsigned)s;
+    return b > 0xffffffffull ? 0xffffffffu : (unsigned)b;
+}
+
+// The moment sums of k_local.  IF = false: no lane of the wave is an
+// interface node and every population is pulled from the source buffer;
+// IF = true: interface lanes read their reconstructed populations from the
+// boundary buffer instead.
+template <int M, typename S, bool IF>
+__device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, int node, const PullOff& o,
+                                              LocalMoments<M>& m) {
+    const size_t N = (size_t)L.N;
+    const int nif = L.n_if;
     const int s = L.slaved;
-    m.rho = m.rhoE = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) m.j[d] = m.q[d] = 0.0;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) m.P[d] = 0.0;
-#pragma unroll
-    for (int a = 0; a < M; ++a) m.rho_a[a] = m.j_a[a][0] = m.j_a[a][1] = m.j_a[a][2] = 0.0;
+    const RLBM_GLOBAL S* src = as_global(static_cast<const S*>(L.pop[par]));
+    const RLBM_GLOBAL S* bc = as_global(static_cast<const S*>(L.bcbuf));
+    RLBM_GLOBAL double* prm = as_global(L.prm);
+    auto off_of = [&](int i) { return node + o.x[cx_of(i) + 1] + o.y[cy_of(i) + 1] + o.z[cz_of(i) + 1]; };
+    const unsigned nb = plane_bytes(L.N, sizeof(S));
+    auto ld = [&](int l, int i) -> S {
+        const int li = l * Q + i;
+        if constexpr (!IF) {
+            return ldb(src + (size_t)li * N, nb, off_of(i));
+        } else {
+            if (k >= 0) return bc[(size_t)li * nif + k];
+            return src[(size_t)li * N + off_of(i)];
+        }
+    };
+    const RLBM_GLOBAL float* sc = nullptr;
+    RLBM_GLOBAL float* so = nullptr;
+    if constexpr (sizeof(S) == 4) {
+        sc = scale_at(L, par, node);
+        so = as_global(L.rscale[par ^ 1]) + (size_t)node * L.rss;
+    }
+
     // momentum and energy lattices
+    double rho = 0.0, rhoE = 0.0, j[3] = {0.0, 0.0, 0.0}, q[3] = {0.0, 0.0, 0.0};
+    double Pd[3] = {0.0, 0.0, 0.0}, Po[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
-        const int off = node + o.x[cx + 1] + o.y[cy + 1] + o.z[cz + 1];
-        const double f = (double)ld_raw_off<S>(L, src, k, off, M - 1, i);
-        const double g = (double)ld_raw_off<S>(L, src, k, off, M, i);
-        m.rho += f;
-        m.rhoE += g;
-        if (cx) m.j[0] += cx > 0 ? f : -f;
-        if (cy) m.j[1] += cy > 0 ? f : -f;
-        if (cz) m.j[2] += cz > 0 ? f : -f;
-        if (FULL) {
-            if (cx) { m.P[0] += f; m.q[0] += cx > 0 ? g : -g; }
-            if (cy) { m.P[1] += f; m.q[1] += cy > 0 ? g : -g; }
-            if (cz) { m.P[2] += f; m.q[2] += cz > 0 ? g : -g; }
-            if (cx * cy) m.P[3] += cx * cy > 0 ? f : -f;
-            if (cx * cz) m.P[4] += cx * cz > 0 ? f : -f;
-            if (cy * cz) m.P[5] += cy * cz > 0 ? f : -f;
-        }
+        const double f = (double)ld(M - 1, i);
+        const double g = (double)ld(M, i);
+        rho += f;
+        rhoE += g;
+        if (cx) { j[0] += cx > 0 ? f : -f; Pd[0] += f; q[0] += cx > 0 ? g : -g; }
+        if (cy) { j[1] += cy > 0 ? f : -f; Pd[1] += f; q[1] += cy > 0 ? g : -g; }
+        if (cz) { j[2] += cz > 0 ? f : -f; Pd[2] += f; q[2] += cz > 0 ? g : -g; }
+        if (cx * cy) Po[0] += cx * cy > 0 ? f : -f;
+        if (cx * cz) Po[1] += cx * cz > 0 ? f : -f;
+        if (cy * cz) Po[2] += cy * cz > 0 ? f : -f;
     }
-    const RLBM_GLOBAL float* sc = nullptr;
     if constexpr (sizeof(S) == 4) {
         const RLBM_CONST double* G = as_const(L.ref);
-        sc = scale_at(L, par, node);
         const double sf = (double)sc[M - 1];
-        m.rho += sf * G[REF_M0<M> + M - 1];
-        m.rhoE += (double)sc[M] * G[REF_M0<M> + M] + sf * G[REF_K0<M>];
-        if (FULL) {
-            const double p2 = sf * G[REF_M2<M>];
-            m.P[0] += p2; m.P[1] += p2; m.P[2] += p2;
-        }
-        s_out[M - 1] = __double2float_rn(m.rho);
-        s_out[M] = __double2float_rn(m.rhoE);
+        rho += sf * G[REF_M0<M> + M - 1];
+        rhoE += (double)sc[M] * G[REF_M0<M> + M] + sf * G[REF_K0<M>];
+        const double p2 = sf * G[REF_M2<M>];
+        Pd[0] += p2; Pd[1] += p2; Pd[2] += p2;
+        so[M - 1] = __double2float_rn(rho);
+        so[M] = __double2float_rn(rhoE);
     }
+    const double inv_rho = 1.0 / rho;
+    const double u[3] = {j[0] * inv_rho, j[1] * inv_rho, j[2] * inv_rho};
+
     // species lattices, one at a time, the next one's loads in flight while
-    // the current one is summed
+    // the current one is summed; rows PRM_SP + 6 a + {0, 1..3} receive rho_a
+    // and u_a - u (zero for an absent species, u_a := u)
+    double rs = rho, js[3] = {j[0], j[1], j[2]};
+    auto put_species = [&](int a, double ra, double jx, double jy, double jz) {
+        const bool small = ra <= 1e-14 * rho;
+        const double inv = small ? 0.0 : 1.0 / ra;
+        RLBM_GLOBAL double* pr = prm + (size_t)(PRM_SP + 6 * a) * N;
+        st_at(pr, node, ra);
+        st_at(pr + N, node, small ? 0.0 : jx * inv - u[0]);
+        st_at(pr + 2 * N, node, small ? 0.0 : jy * inv - u[1]);
+        st_at(pr + 3 * N, node, small ? 0.0 : jz * inv - u[2]);
+    };
+    // FP32 storage double-buffers the species loads; FP64 has no registers
+    // to spare for it
+    constexpr bool PF = sizeof(S) == 4;
     S cur[Q];
+    if constexpr (PF) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-        cur[i] = ld_raw_off<S>(L, src, k, node + o.x[cx_of(i) + 1] + o.y[cy_of(i) + 1] + o.z[cz_of(i) + 1], 0, i);
+        for (int i = 0; i < Q; ++i) cur[i] = ld(0, i);
+    }
 #pragma unroll 1
     for (int l = 0; l < M - 1; ++l) {
         reload_barrier();
         S nxt[Q];
-        if (l + 1 < M - 1) {
+        if constexpr (PF) {
+            if (l + 1 < M - 1) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i)
-                nxt[i] = ld_raw_off<S>(L, src, k, node + o.x[cx_of(i) + 1] + o.y[cy_of(i) + 1] + o.z[cz_of(i) + 1],
-                                       l + 1, i);
+                for (int i = 0; i < Q; ++i) nxt[i] = ld(l + 1, i);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) cur[i] = ld(l, i);
         }
-        double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        double ra = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
             const double v = (double)cur[i];
-            r += v;
-            if (FULL) {
-                if (cx) jx += cx > 0 ? v : -v;
-                if (cy) jy += cy > 0 ? v : -v;
-                if (cz) jz += cz > 0 ? v : -v;
-            }
+            ra += v;
+            if (cx) jx += cx > 0 ? v : -v;
+            if (cy) jy += cy > 0 ? v : -v;
+            if (cz) jz += cz > 0 ? v : -v;
         }
         if constexpr (sizeof(S) == 4) {
             const RLBM_CONST double* rm = as_const(L.ref) + REF_M0<M> + opaque_zero();
-            r += (double)sc[l] * rm[l];
+            ra += (double)sc[l] * rm[l];
+            so[l] = __double2float_rn(ra);
         }
-        if constexpr (sizeof(S) == 4) s_out[l] = __double2float_rn(r);
         const int a = l + (l >= s ? 1 : 0);
+        put_species(a, ra, jx, jy, jz);
+        rs -= ra; js[0] -= jx; js[1] -= jy; js[2] -= jz;
+        if constexpr (PF) {
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            if (c == a) { m.rho_a[c] = r; m.j_a[c][0] = jx; m.j_a[c][1] = jy; m.j_a[c][2] = jz; }
+            for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
         }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
     }
-    double rs = m.rho, jsx = m.j[0], jsy = m.j[1], jsz = m.j[2];
+    put_species(s, rs, js[0], js[1], js[2]);
+    // the species densities are read back from the record (this thread's own
+    // stores) rather than held in registers through the loop
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-        if (a == s) continue;
-        rs -= m.rho_a[a]; jsx -= m.j_a[a][0]; jsy -= m.j_a[a][1]; jsz -= m.j_a[a][2];
-    }
+    for (int c = 0; c < M; ++c) m.rho_a[c] = ld_at(prm + (size_t)(PRM_SP + 6 * c) * N, node);
+    m.rho = rho;
+    m.rhoE = rhoE;
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-        if (a == s) { m.rho_a[a] = rs; m.j_a[a][0] = jsx; m.j_a[a][1] = jsy; m.j_a[a][2] = jsz; }
+    for (int d = 0; d < 3; ++d) {
+        m.j[d] = j[d]; m.q[d] = q[d]; m.Pd[d] = Pd[d]; m.Po[d] = Po[d]; m.u[d] = u[d];
     }
 }
 
+template <int M, typename S>
+__global__ __launch_bounds__(256) void k_local(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+                                               int n_lat, long long t, int* __restrict__ flag) {
+    const int b = xcd_block();
+    const int lj = find_lattice(blk, n_lat, b);
+    const LatDev& L = lats[lj];
+    if (t >= L.t_end) return;
+    const int node = (b - blk[lj]) * 256 + threadIdx.x;
+    if (node >= L.N) return;
+    MechC mc = *as_const(L.mech);
+    const int par = (L.parity0 + t) & 1;
+    const int x = node % L.nx, r = node / L.nx, y = r % L.ny, z = r / L.ny;
+    PullOff o;
+    pull_offsets(L, x, y, z, o);
+    const int k = L.n_if ? L.if_index[node] : -1;
+    double* aux = L.aux;
+    double* prm = L.prm;
+    const size_t N = (size_t)L.N;
+
+    LocalMoments<M> m;
+    if (__builtin_amdgcn_ballot_w64(k >= 0) != 0) local_moments<M, S, true>(L, par, k, node, o, m);
+    else local_moments<M, S, false>(L, par, k, node, o, m);
+    const double rho = m.rho, inv_rho = 1.0 / rho;
+    const double u[3] = {m.u[0], m.u[1], m.u[2]};
+    const double rhoE = m.rhoE;
+    const double* rho_a = m.rho_a;
+    const double* q = m.q;
+    const double* Pd = m.Pd;
+    const double* Po = m.Po;
+
+    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double Y[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) Y[a] = rho_a[a] * inv_rho;
+    const double U = rhoE * inv_rho - 0.5 * usq;
+    int fail = 0;
+    // temperature (eq. temperature), Newton from the previous step's value
+    const double T = solve_T<M>(mc, Y, U, aux[AUX_T * N + node], &fail);
+    if (fail) atomicOr(flag, 1);
+    const double inv_mix_m = mix_inv_m<M>(mc, Y);
+    const double th = mc.R_univ * inv_mix_m * T;
+    const double P = rho * th;
+
+    // relaxation rates (sections 2.3 and 3.4)
+    const double lnr = log(T * mc.inv_T_ref);
+    const double common = mc.R_univ * T / inv_mix_m * P * mc.inv_P_ref * exp(-mc.D_exp * lnr);
+    const double mu = mc.mu_ref * exp(mc.mu_exp * lnr);
+    const double omega = 1.0 / (mu / P + 0.5);
+    const double omega1 = 1.0 / (mu * mc.inv_Pr / P + 0.5);
+
+    // enthalpy-weighted composition moments sum_a H_a(T') Y_a = sum_kk T'^kk Pk
+    double Pk[6];
+#pragma unroll
+    for (int kk = 0; kk < 6; ++kk) {
+        double pk = 0.0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) pk += mc.hc[a][kk] * Y[a];
+        Pk[kk] = pk;
+    }
+    // local part of the energy-lattice flux
+    //   Qb = (omega - omega1)(q - u.(P - P^eq) - q^eq); k_diff adds
+    //   omega1 rho sum_a H_a Y_a V_a
+    {
+        const double H = Pk[0] + T * (Pk[1] + T * (Pk[2] + T * (Pk[3] + T * (Pk[4] + T * Pk[5]))));
+        const double hq = rho * (H + 0.5 * usq);
+        const double Pt[3][3] = {{Pd[0], Po[0], Po[1]}, {Po[0], Pd[1], Po[2]}, {Po[1], Po[2], Pd[2]}};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double uP = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) uP += u[c] * (Pt[c][a] - rho * ((a == c ? th : 0.0) + u[c] * u[a]));
+            prm[(size_t)(PRM_QB + a) * N + node] = (omega - omega1) * (q[a] - uP - hq * u[a]);
+        }
+    }
+
+    // neighbour-facing fields
+    aux[AUX_RHO * N + node] = rho;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        aux[(AUX_U + d) * N + node] = u[d];
+        aux[(AUX_PHI + d) * N + node] = rho * u[d] * (1.0 - 3.0 * th) - rho * u[d] * u[d] * u[d];
+    }
+    aux[AUX_T * N + node] = T;
+#pragma unroll
+    for (int a = 0; a < M; ++a) aux[(AUX_Y + a) * N + node] = Y[a];
+#pragma unroll
+    for (int kk = 0; kk < 6; ++kk) aux[(AUX_Y + M + kk) * N + node] = Pk[kk];
+
+    prm[PRM_RHO * N + node] = rho;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) prm[(PRM_U + d) * N + node] = u[d];
+    prm[PRM_T * N + node] = T;
+    prm[PRM_UINT * N + node] = U;
+    prm[PRM_TH * N + node] = th;
+    prm[PRM_OMEGA * N + node] = omega;
+    prm[PRM_COMMON * N + node] = common;
+    prm[PRM_WQ * N + node] = omega - omega1;
+    prm[PRM_CC * N + node] = 0.5 * (2.0 - omega1) * P;
+}
+
 // ---------------------------------------------------------------------------
-// k_local: everything a node needs from its own populations
+// k_diff: Stefan-Maxwell diffusion velocities (section 2.3, eq. transform1)
 // ---------------------------------------------------------------------------
-// Stefan-Maxwell system (eq. transform1, dt = 1), Doolittle LU without
-// pivoting, rows generated on the fly:
-//   A_aa = 1 + inv_tau_a / 2,   A_ab = -common K_ab Y_b / 2  (a != b).
-// A is strictly row diagonally dominant (margin 1), so no pivoting is needed.
-// V holds u_a - u on entry and the diffusion velocities on exit.
+// The system (dt = 1)
+//   (1 + 1/(2 tau_a)) V_a - 1/2 sum_{b != a} Y_b V_b / tau_ab = u_a - u
+// with 1/tau_ab = common K_ab and 1/tau_a = sum_{b != a} Y_b / tau_ab, for
+// the three components at once.  Its matrix is strictly row diagonally
+// dominant with margin 1 (the off-diagonal row sums are -1/(2 tau_a)), so
+// Doolittle LU without pivoting is stable.  Rows are generated on the fly
+// from cY_b = -common Y_b / 2 (A_ab = K_ab cY_b), the forward substitution
+// runs with the factorisation, and beta_a = 1/(2 tau_a + 1) is written as
+// soon as row a has its 1/tau_a.  Reads Y (aux), u_a - u, common, T, rho
+// and the rates from the per-node record; writes V_a and beta_a and adds
+// omega1 rho sum_a H_a Y_a V_a to the energy flux base.
 template <int M>
-__device__ __forceinline__ void sm_solve_lu(MechC mc, const double* Y, double common,
-                                            const double* inv_tau, double (*V)[3]) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_diff(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+                                              int n_lat, long long t, int* __restrict__ flag) {
+    (void)flag;
+    const int b = xcd_block();
+    const int lj = find_lattice(blk, n_lat, b);
+    const LatDev& L = lats[lj];
+    if (t >= L.t_end) return;
+    const int node = (b - blk[lj]) * 256 + threadIdx.x;
+    if (node >= L.N) return;
+    MechC mc0 = *as_const(L.mech);
+    const size_t N = (size_t)L.N;
+    const RLBM_GLOBAL double* aux = as_global(L.aux);
+    RLBM_GLOBAL double* prm = as_global(L.prm);
+    const double common = ld_at(prm + PRM_COMMON * N, node);
+    double cY[M], V[M][3];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        cY[a] = -0.5 * common * ld_at(aux + (AUX_Y + a) * N, node);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) V[a][d] = ld_at(prm + (PRM_SP + 6 * a + 1 + d) * N, node);
+    }
     double Uu[M][M];
     double inv_diag[M];
 #pragma unroll
     for (int i = 0; i < M; ++i) {
+        reload_barrier();
+        MechC mc = in_loop(mc0);   // this row's K_ab as scalar loads, not hoisted
+        double st = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+            if (c != i) st += mc.Kab[i][c] * cY[c];
+        const double inv_tau = -2.0 * st;
+        st_at(prm + (PRM_SP + 6 * i + 4) * N, node, inv_tau / (2.0 + inv_tau));   // beta_a = dt/(2 tau_a + dt)
         double lrow[M];
 #pragma unroll
         for (int j = 0; j < i; ++j) {
-            double a = -0.5 * common * mc.Kab[i][j] * Y[j];
+            double a = mc.Kab[i][j] * cY[j];
 #pragma unroll
             for (int kk = 0; kk < j; ++kk) a -= lrow[kk] * Uu[kk][j];
             lrow[j] = a * inv_diag[j];
         }
 #pragma unroll
         for (int j = i; j < M; ++j) {
-            double a = (i == j) ? 1.0 + 0.5 * inv_tau[i] : -0.5 * common * mc.Kab[i][j] * Y[j];
+            double a = (i == j) ? 1.0 + 0.5 * inv_tau : mc.Kab[i][j] * cY[j];
 #pragma unroll
             for (int kk = 0; kk < i; ++kk) a -= lrow[kk] * Uu[kk][j];
             Uu[i][j] = a;
@@ -294,140 +497,24 @@ __device__ __forceinline__ void sm_solve_lu(MechC mc, const double* Y, double co
 #pragma unroll
             for (int j = i + 1; j < M; ++j) sm -= Uu[i][j] * V[j][dd];
             V[i][dd] = sm * inv_diag[i];
+            st_at(prm + (PRM_SP + 6 * i + 1 + dd) * N, node, V[i][dd]);
         }
     }
-}
-
-template <int M, typename S>
-__global__ __launch_bounds__(256) void k_local(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                               int n_lat, long long t, int* __restrict__ flag) {
-    const int b = blockIdx.x;
-    const int lj = find_lattice(blk, n_lat, b);
-    const LatDev& L = lats[lj];
-    if (t >= L.t_end) return;
-    const int node = (b - blk[lj]) * 256 + threadIdx.x;
-    if (node >= L.N) return;
-    MechC mc = *as_const(L.mech);
-    const void* src = L.pop[(L.parity0 + t) & 1];
-    const int x = node % L.nx, r = node / L.nx, y = r % L.ny, z = r / L.ny;
-    PullOff o;
-    pull_offsets(L, x, y, z, o);
-    const int k = L.n_if ? L.if_index[node] : -1;
-    double* aux = L.aux;
-    double* prm = L.prm;
-    const size_t N = (size_t)L.N;
-
-    const int par = (L.parity0 + t) & 1;
-    Moments<M> m;
-    float* so = sizeof(S) == 4 ? L.rscale[par ^ 1] + (size_t)node * L.rss : nullptr;
-    node_moments<M, S, true>(L, src, k, node, o, par, m, so);
-    const double rho = m.rho, inv_rho = 1.0 / rho;
-    const double u[3] = {m.j[0] * inv_rho, m.j[1] * inv_rho, m.j[2] * inv_rho};
-    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    double Y[M];
-#pragma unroll
-    for (int a = 0; a < M; ++a) Y[a] = m.rho_a[a] * inv_rho;
-    const double U = m.rhoE * inv_rho - 0.5 * usq;
-    int fail = 0;
-    // temperature (eq. temperature), Newton from the previous step's value
-    const double T = solve_T<M>(mc, Y, U, aux[AUX_T * N + node], &fail);
-    const double inv_mix_m = mix_inv_m<M>(mc, Y);
-    const double th = mc.R_univ * inv_mix_m * T;
-    const double P = rho * th;
-
-    // relaxation parameters (sections 2.3 and 3.4)
-    const double lnr = log(T * mc.inv_T_ref);
-    const double common = mc.R_univ * T / inv_mix_m * P * mc.inv_P_ref * exp(-mc.D_exp * lnr);
-    const double mu = mc.mu_ref * exp(mc.mu_exp * lnr);
-    const double omega = 1.0 / (mu / P + 0.5);
-    const double omega1 = 1.0 / (mu * mc.inv_Pr / P + 0.5);
-
-    // local part of the energy-lattice flux
-    //   Qb = (omega - omega1)(q - u.(P - P^eq) - q^eq) + omega1 rho sum_a H_a Y_a V_a
-    double Qb[3];
-    {
-        double H = 0.0;
-#pragma unroll
-        for (int a = 0; a < M; ++a) H += Y[a] * (species_U(mc, a, T) + mc.Ra[a] * T);
-        const double hq = rho * (H + 0.5 * usq);
-        const double Pt[3][3] = {{m.P[0], m.P[3], m.P[4]}, {m.P[3], m.P[1], m.P[5]}, {m.P[4], m.P[5], m.P[2]}};
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            double uP = 0.0;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) uP += u[c] * (Pt[c][a] - rho * ((a == c ? th : 0.0) + u[c] * u[a]));
-            Qb[a] = (omega - omega1) * (m.q[a] - uP - hq * u[a]);
-        }
-    }
-
-    // Stefan-Maxwell diffusion velocities; u_a := u for absent species
-    double V[M][3];
-    double inv_tau[M];
+    MechC mc = mc0;
+    const double T = ld_at(prm + PRM_T * N, node);
+    double diff[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-        const bool small = m.rho_a[a] <= 1e-14 * rho;
-        const double inv = small ? 0.0 : 1.0 / m.rho_a[a];
+        const double hy = (species_U(mc, a, T) + mc.Ra[a] * T) * ld_at(aux + (AUX_Y + a) * N, node);
 #pragma unroll
-        for (int dd = 0; dd < 3; ++dd) V[a][dd] = small ? 0.0 : m.j_a[a][dd] * inv - u[dd];
-        double sum = 0.0;
-#pragma unroll
-        for (int c = 0; c < M; ++c)
-            if (c != a) sum += Y[c] * mc.Kab[a][c];
-        inv_tau[a] = common * sum;
+        for (int dd = 0; dd < 3; ++dd) diff[dd] += hy * V[a][dd];
     }
-    sm_solve_lu<M>(mc, Y, common, inv_tau, V);
-    {
-        double diff[3] = {0.0, 0.0, 0.0};
+    const double omega1 = ld_at(prm + PRM_OMEGA * N, node) - ld_at(prm + PRM_WQ * N, node);
+    const double rr = omega1 * ld_at(prm + PRM_RHO * N, node);
 #pragma unroll
-        for (int a = 0; a < M; ++a) {
-            const double hy = (species_U(mc, a, T) + mc.Ra[a] * T) * Y[a];
-#pragma unroll
-            for (int dd = 0; dd < 3; ++dd) diff[dd] += hy * V[a][dd];
-        }
-#pragma unroll
-        for (int dd = 0; dd < 3; ++dd) Qb[dd] += omega1 * rho * diff[dd];
-    }
-
-    // neighbour-facing fields
-    aux[AUX_RHO * N + node] = rho;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        aux[(AUX_U + d) * N + node] = u[d];
-        aux[(AUX_PHI + d) * N + node] = rho * u[d] * (1.0 - 3.0 * th) - rho * u[d] * u[d] * u[d];
-    }
-    aux[AUX_T * N + node] = T;
-#pragma unroll
-    for (int a = 0; a < M; ++a) aux[(AUX_Y + a) * N + node] = Y[a];
-    // enthalpy-weighted composition moments: sum_a H_a(T') Y_a = sum_k T'^k Pk
-#pragma unroll
-    for (int kk = 0; kk < 6; ++kk) {
-        double pk = 0.0;
-#pragma unroll
-        for (int a = 0; a < M; ++a) pk += mc.hc[a][kk] * Y[a];
-        aux[(AUX_Y + M + kk) * N + node] = pk;
-    }
-
-    prm[PRM_RHO * N + node] = rho;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) prm[(PRM_U + d) * N + node] = u[d];
-    prm[PRM_T * N + node] = T;
-    prm[PRM_UINT * N + node] = U;
-    prm[PRM_TH * N + node] = th;
-    prm[PRM_OMEGA * N + node] = omega;
-    prm[PRM_COMMON * N + node] = common;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) prm[(PRM_QB + d) * N + node] = Qb[d];
-    prm[PRM_WQ * N + node] = omega - omega1;
-    prm[PRM_CC * N + node] = 0.5 * (2.0 - omega1) * P;
-
-    if (fail) atomicOr(flag, 1);
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-        const int r0 = PRM_SP + 6 * a;
-        prm[(r0 + 0) * N + node] = m.rho_a[a];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) prm[(r0 + 1 + d) * N + node] = V[a][d];
-        prm[(r0 + 4) * N + node] = inv_tau[a] / (2.0 + inv_tau[a]);   // beta_a = dt / (2 tau_a + dt)
+    for (int dd = 0; dd < 3; ++dd) {
+        RLBM_GLOBAL double* qb = prm + (PRM_QB + dd) * N;
+        st_at(qb, node, ld_at(qb, node) + rr * diff[dd]);
     }
 }
 
@@ -439,7 +526,7 @@ __global__ __launch_bounds__(256) void k_local(const LatDev* __restrict__ lats, 
 template <int M>
 __global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                               int n_lat, long long t, int* __restrict__ flag) {
-    const int b = blockIdx.x;
+    const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
     if (t >= L.t_end) return;
@@ -448,6 +535,8 @@ __global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, c
     MechC mc = *as_const(L.mech);
     double* prm = L.prm;
     const size_t N = (size_t)L.N;
+    __shared__ double s_c[M][256], s_g[M][256];
+    const ChemLds<256> ls{&s_c[0][threadIdx.x], &s_g[0][threadIdx.x]};
     double rho_a[M], drho[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) rho_a[a] = prm[(PRM_SP + 6 * a) * N + node];
@@ -455,7 +544,7 @@ __global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, c
     const double U = prm[PRM_UINT * N + node];
     const double T = prm[PRM_T * N + node];
     int fail = 0;
-    reaction_increment<M>(mc, rho_a, rho, U, T, L.substeps, drho, &fail);
+    reaction_increment<M, 256>(mc, rho_a, rho, U, T, L.substeps, ls, drho, &fail);
     if (fail) atomicOr(flag, 1);
 #pragma unroll
     for (int a = 0; a < M; ++a) prm[(PRM_SP + 6 * a + 5) * N + node] = drho[a];
@@ -472,7 +561,7 @@ __global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, c
 template <int M>
 __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                               int n_lat, long long t, int* __restrict__ flag) {
-    const int b = blockIdx.x;
+    const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
     if (t >= L.t_end) return;
@@ -561,16 +650,6 @@ __device__ __forceinline__ void geq_wk(int c, double u, double th, double& W, do
     k = c == 0 ? 0.5 * u2 - o2 : 0.5 * (o2 + (double)c * o1);
 }
 
-// Byte-offset addressing: a uniform base plus a 32-bit per-lane offset keeps
-// every population access in the scalar-base form (no 64-bit address math).
-template <typename S>
-__device__ __forceinline__ S ld_at(const RLBM_GLOBAL S* base, int idx) {
-    return *(const RLBM_GLOBAL S*)((const RLBM_GLOBAL char*)base + (unsigned)(idx * (int)sizeof(S)));
-}
-template <typename S>
-__device__ __forceinline__ void st_at(RLBM_GLOBAL S* base, int idx, S v) {
-    *(RLBM_GLOBAL S*)((RLBM_GLOBAL char*)base + (unsigned)(idx * (int)sizeof(S))) = v;
-}
 
 template <int M, typename S>
 __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict__ lats, const int* __restrict__ blk,
@@ -580,7 +659,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
     constexpr int NS = sizeof(S) == 4 ? M + 1 : 1;
     __shared__ double sp[NR][UPD_NODES];
     __shared__ float ssc[NS][UPD_NODES];     // FP32 storage: this node's reference scales
-    const int b = blockIdx.x;
+    const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
     if (t >= L.t_end) return;
@@ -599,24 +678,45 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
     const RLBM_GLOBAL double* prm = as_global(L.prm);
     const int nif = L.n_if;
 
-    // stage the record; species rows in slot order
-    for (int idx = threadIdx.x; idx < NR * UPD_NODES; idx += UPD_THREADS) {
-        const int row = idx / UPD_NODES, j = idx % UPD_NODES;
-        int srow = row;
-        if (row >= PRM_SP && row < prm_grad(M)) {
-            const int slot = (row - PRM_SP) / 6, q = (row - PRM_SP) % 6;
-            const int a = slot < M - 1 ? slot + (slot >= s ? 1 : 0) : s;
-            srow = PRM_SP + 6 * a + q;
+    // stage the record, species rows in slot order, and (FP32 storage) this
+    // node's reference scales: wave w takes rows w, w + 3, ..., one node per
+    // lane; every load is in flight before the first LDS write
+    {
+        constexpr int RPW = (NR + UPD_WAVES - 1) / UPD_WAVES;
+        constexpr int LPW = (NS + UPD_WAVES - 1) / UPD_WAVES;
+        const int nd = node0 + lane < N ? node0 + lane : 0;   // beyond the end: a placeholder node
+        double v[RPW];
+        float w[LPW];
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int row = wave + UPD_WAVES * q;
+            int srow = row;
+            if (row >= PRM_SP && row < prm_grad(M)) {
+                const int slot = (row - PRM_SP) / 6, c = (row - PRM_SP) % 6;
+                const int a = slot < M - 1 ? slot + (slot >= s ? 1 : 0) : s;
+                srow = PRM_SP + 6 * a + c;
+            }
+            v[q] = ld_at(prm + (size_t)(row < NR ? srow : 0) * L.N, nd);   // unconditional: no waits between
         }
-        const int nd = node0 + j;
-        sp[row][j] = nd < N ? prm[(size_t)srow * L.N + nd] : 1.0;
-    }
-    if constexpr (sizeof(S) == 4) {
-        const int par0 = (L.parity0 + t) & 1;
-        for (int idx = threadIdx.x; idx < NS * UPD_NODES; idx += UPD_THREADS) {
-            const int j = idx / NS, l = idx % NS;
-            const int nd = node0 + j;
-            ssc[l][j] = nd < N ? scale_at(L, par0, nd)[l] : 1.0f;
+        if constexpr (sizeof(S) == 4) {
+            const RLBM_GLOBAL float* sc = scale_at(L, par, nd);
+#pragma unroll
+            for (int q = 0; q < LPW; ++q) {
+                const int l = wave + UPD_WAVES * q;
+                w[q] = sc[l < NS ? l : 0];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int row = wave + UPD_WAVES * q;
+            if (row < NR) sp[row][lane] = v[q];
+        }
+        if constexpr (sizeof(S) == 4) {
+#pragma unroll
+            for (int q = 0; q < LPW; ++q) {
+                const int l = wave + UPD_WAVES * q;
+                if (l < NS) ssc[l][lane] = w[q];
+            }
         }
     }
 
@@ -872,12 +972,27 @@ __device__ __forceinline__ double eq_value(MechC mc, const EqState<M, SPV>& e, i
 // first moments are half-wave sums.  The state construction (temperature
 // iteration, LODI) is evaluated redundantly by the lanes of a node.
 // ---------------------------------------------------------------------------
-// Sum over the 32 lanes of a half-wave; every lane receives the first lane's
-// result, so all lanes of a node continue from bit-identical moments.
+// Sum over the 32 lanes of a half-wave.  Lane pairs are combined within
+// quads, half-rows and rows of 16 by DPP moves (no LDS round trip), then the
+// two rows by one swizzle.  Every step adds the same two operands on both
+// lanes of a pair (a + b = b + a exactly), so all 32 lanes end with
+// bit-identical sums and the lanes of a node continue from identical moments.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
 __device__ __forceinline__ double hsum32(double v) {
-#pragma unroll
-    for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m, 32);
-    return __shfl(v, 0, 32);
+    v += dpp_f64<0xb1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4e>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)b, 0x401f);          // lane ^ 16 within 32
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401f);
+    return v + __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
 // Equilibrium state of section 4.1: density, mass fractions, velocity (with
@@ -979,7 +1094,7 @@ constexpr int BC_THREADS = 32 * BC_NODES;
 template <int M, typename S>
 __global__ __launch_bounds__(BC_THREADS) void k_boundary(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                                          int n_lat, long long t, int* __restrict__ flag) {
-    const int b = blockIdx.x;
+    const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
     if (t >= L.t_end) return;
@@ -1491,9 +1606,12 @@ static hipError_t launch_step_phase(int phase, int M, const StepLaunch& a) {
         RLBM_DISPATCH(M, hipLaunchKernelGGL((k_local<MM, S>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
                                                 a.blk, a.n_lat, a.t, a.flag))
     } else if (phase == 2) {
-        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
+        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_diff<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
                                                 a.blk, a.n_lat, a.t, a.flag))
     } else if (phase == 3) {
+        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
+                                                a.blk, a.n_lat, a.t, a.flag))
+    } else if (phase == 4) {
         RLBM_DISPATCH(M, hipLaunchKernelGGL((k_grad<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
                                                 a.blk, a.n_lat, a.t, a.flag))
     } else {

@@ -14,6 +14,7 @@ constexpr int Q = 27;
 constexpr int MAXM = RLBM_MAX_SPECIES;
 constexpr int MAXR = RLBM_MAX_REACTIONS;
 constexpr int MAXE = RLBM_MAX_ELEMENTS;
+constexpr int MAXO = RLBM_MAX_ORDER;   // molecules per side of a reaction
 
 // D3Q27 velocity i = 9 (cz + 1) + 3 (cy + 1) + (cx + 1) (section 2.2, eq. d3q27vel).
 __host__ __device__ constexpr int cx_of(int i) { return i % 3 - 1; }
@@ -39,6 +40,10 @@ struct MechDev {
     int rev[MAXR];
     int8_t nu_f[MAXR][MAXM], nu_r[MAXR][MAXM];
     double dnu[MAXR][MAXM];
+    // each side of a reaction as a list of factors: its species in ascending
+    // order, each repeated by its coefficient (mass-action products)
+    int nfac_f[MAXR], nfac_r[MAXR];
+    int fac_f[MAXR][MAXO], fac_r[MAXR][MAXO];
     // transport
     double T_ref, inv_T_ref, P_ref, inv_P_ref, mu_ref, mu_exp, inv_Pr, D_exp;
     double Kab[MAXM][MAXM];     // 1 / (D_ref[a][b] m_a m_b)
@@ -234,61 +239,67 @@ __device__ __forceinline__ double gibbs_RT(MechC mc, int a, double T, double lnT
 // ---------------------------------------------------------------------------
 // chemistry (section 2.3, eq. R3): production rates and sub-steps
 // ---------------------------------------------------------------------------
-template <int M>
-__device__ __forceinline__ void production_rates(MechC mc0, const double* rho_a, double T,
+// Per-thread LDS columns: the concentrations c_a and the Gibbs functions
+// g_a/(R_univ T) of one node, at stride NT doubles between species, so a
+// reaction reads just its own factors at a wave-uniform species index.
+template <int NT>
+struct ChemLds {
+    double* c;   // &c[0][tid]
+    double* g;   // &g[0][tid]
+};
+
+template <int M, int NT>
+__device__ __forceinline__ void production_rates(MechC mc0, const double* rho_a, double T, const ChemLds<NT>& ls,
                                                  double* wdot) {
     MechC mc = mc0;
 #pragma unroll
     for (int a = 0; a < M; ++a) wdot[a] = 0.0;
     const int R = mc.R;
     if (R == 0) return;
-    double conc[M], gRT[M];
     const double lnT = log(T);
     const double invT = 1.0 / T;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-        conc[a] = fmax(rho_a[a], 0.0) * mc.inv_m[a];
-        gRT[a] = gibbs_RT(mc, a, T, lnT, invT);
+        ls.c[a * NT] = fmax(rho_a[a], 0.0) * mc.inv_m[a];
+        ls.g[a * NT] = gibbs_RT(mc, a, T, lnT, invT);
     }
     const double lnc = mc.ln_cstd - lnT;
     for (int r = 0; r < R; ++r) {
         MechC mc = in_loop(mc0);
+        const int nf = mc.nfac_f[r], nr = mc.nfac_r[r];
         const double lnkf = mc.lnA[r] + mc.beta[r] * lnT - mc.Ta[r] * invT;
+        // forward rate k_f prod_b c_b^nu'_b
         double fwd = exp(lnkf);
 #pragma unroll
-        for (int a = 0; a < M; ++a) {
-            const int n = mc.nu_f[r][a];
-            if (n >= 1) fwd *= conc[a];
-            if (n >= 2) fwd *= conc[a];
-            if (n >= 3) fwd *= conc[a];
-        }
+        for (int f = 0; f < MAXO; ++f)
+            if (f < nf) fwd *= ls.c[mc.fac_f[r][f] * NT];
         double q = fwd;
         if (mc.rev[r]) {
+            // k_r = k_f / K_c, ln K_c = -sum_a dnu_a g_a/(R T) + (sum_a dnu_a) ln c_std
             double sg = 0.0;
 #pragma unroll
-            for (int a = 0; a < M; ++a) sg += mc.dnu[r][a] * gRT[a];
-            const double lnKc = -sg + mc.dnu_sum[r] * lnc;
-            double bwd = exp(lnkf - lnKc);
+            for (int f = 0; f < MAXO; ++f)
+                if (f < nr) sg += ls.g[mc.fac_r[r][f] * NT];
 #pragma unroll
-            for (int a = 0; a < M; ++a) {
-                const int n = mc.nu_r[r][a];
-                if (n >= 1) bwd *= conc[a];
-                if (n >= 2) bwd *= conc[a];
-                if (n >= 3) bwd *= conc[a];
-            }
+            for (int f = 0; f < MAXO; ++f)
+                if (f < nf) sg -= ls.g[mc.fac_f[r][f] * NT];
+            double bwd = exp(lnkf + sg - mc.dnu_sum[r] * lnc);
+#pragma unroll
+            for (int f = 0; f < MAXO; ++f)
+                if (f < nr) bwd *= ls.c[mc.fac_r[r][f] * NT];
             q -= bwd;
         }
 #pragma unroll
-        for (int a = 0; a < M; ++a) wdot[a] += mc.dnu[r][a] * q;
+        for (int a = 0; a < M; ++a) wdot[a] = fma(mc.dnu[r][a], q, wdot[a]);
     }
 #pragma unroll
     for (int a = 0; a < M; ++a) wdot[a] *= mc.m[a];
 }
 
 // Delta rho_a over one step by l forward-Euler sub-steps at frozen U.
-template <int M>
-__device__ __forceinline__ void reaction_increment(MechC mc0, const double* rho_a, double rho,
-                                                   double U, double T, int l, double* drho, int* fail) {
+template <int M, int NT>
+__device__ __forceinline__ void reaction_increment(MechC mc0, const double* rho_a, double rho, double U, double T,
+                                                   int l, const ChemLds<NT>& ls, double* drho, int* fail) {
     double cur[M], w[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) cur[a] = rho_a[a];
@@ -308,52 +319,12 @@ __device__ __forceinline__ void reaction_increment(MechC mc0, const double* rho_
             for (int a = 0; a < M; ++a) Y[a] = cur[a] * inv_rho;
             Ts = solve_T<M>(mc, Y, U, Ts, fail);
         }
-        production_rates<M>(mc, cur, Ts, w);
+        production_rates<M, NT>(mc, cur, Ts, ls, w);
 #pragma unroll
         for (int a = 0; a < M; ++a) cur[a] += w[a] * inv_l;
     }
 #pragma unroll
     for (int a = 0; a < M; ++a) drho[a] = cur[a] - rho_a[a];
-}
-
-// ---------------------------------------------------------------------------
-// Stefan-Maxwell system (section 2.3, eq. transform1), dt = 1:
-//   (1 + 1/(2 tau_a)) V_a - 1/2 sum_{b != a} Y_b V_b / tau_ab = u_a - u.
-// The matrix is strictly row diagonally dominant with margin 1 (its
-// off-diagonal row sums are -1/(2 tau_a)), so Gaussian elimination without
-// pivoting is stable.  Three right-hand sides (x, y, z) at once.
-// ---------------------------------------------------------------------------
-template <int M>
-__device__ __forceinline__ void sm_solve(const double* Y, const double (*itab)[M], const double* inv_tau,
-                                         double (*rhs)[3]) {
-    double A[M][M];
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-#pragma unroll
-        for (int b = 0; b < M; ++b) A[a][b] = (a == b) ? 1.0 + 0.5 * inv_tau[a] : -0.5 * Y[b] * itab[a][b];
-    }
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        const double inv = 1.0 / A[k][k];
-#pragma unroll
-        for (int a = k + 1; a < M; ++a) {
-            const double f = A[a][k] * inv;
-#pragma unroll
-            for (int b = k + 1; b < M; ++b) A[a][b] -= f * A[k][b];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) rhs[a][d] -= f * rhs[k][d];
-        }
-    }
-#pragma unroll
-    for (int k = M - 1; k >= 0; --k) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            double s = rhs[k][d];
-#pragma unroll
-            for (int b = k + 1; b < M; ++b) s -= A[k][b] * rhs[b][d];
-            rhs[k][d] = s / A[k][k];
-        }
-    }
 }
 
 }  // namespace rlbm

@@ -38,7 +38,7 @@ int hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-constexpr int NPHASE = 5;   // boundary, local, chemistry, gradients, update
+constexpr int NPHASE = 6;   // boundary, local, diffusion, chemistry, gradients, update
 
 struct Plan {
     size_t off_lat, off_mech, off_blk, off_flag, off_ref, off_pop0, off_pop1, off_aux, off_prm, off_ifindex, off_ifnode,
@@ -59,8 +59,9 @@ bool face_valid(int t) { return t >= RLBM_FACE_PERIODIC && t <= RLBM_FACE_OUTLET
 int validate_desc(const rlbm_lattice_desc* d, int M) {
     if (!d) return fail(RLBM_EINVAL, "null lattice descriptor");
     if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(RLBM_EINVAL, "lattice dimensions must be >= 1");
-    if ((long long)d->nx * d->ny * d->nz > (1LL << 31) - 1)
-        return fail(RLBM_EUNSUP, "more than 2^31 - 1 nodes");
+    // kernels address a population plane with 32-bit byte offsets
+    if ((long long)d->nx * d->ny * d->nz > (1LL << 29))
+        return fail(RLBM_EUNSUP, "more than 2^29 nodes");
     for (int f = 0; f < 6; ++f)
         if (!face_valid(d->faces[f].type)) return fail(RLBM_EINVAL, "unknown face type");
     const int n[3] = {d->nx, d->ny, d->nz};
@@ -226,8 +227,8 @@ struct rlbm_lattice {
     bool state_set = false;
     bool timing = false;
     std::vector<Timing> events;
-    double ms[NPHASE] = {0, 0, 0, 0, 0};
-    long long counts[NPHASE] = {0, 0, 0, 0, 0};
+    double ms[NPHASE] = {0, 0, 0, 0, 0, 0};
+    long long counts[NPHASE] = {0, 0, 0, 0, 0, 0};
 };
 
 struct rlbm_batch {
@@ -310,6 +311,12 @@ int rlbm_mech_create(const rlbm_mech_desc* d, rlbm_mech** out) {
             md.nu_r[r][a] = (int8_t)b;
             md.dnu[r][a] = (double)(b - f);
             s += (double)(b - f);
+            if (md.nfac_f[r] + f > RLBM_MAX_ORDER || md.nfac_r[r] + b > RLBM_MAX_ORDER) {
+                delete m;
+                return fail(RLBM_EUNSUP, "more than RLBM_MAX_ORDER molecules on one side of a reaction");
+            }
+            for (int k = 0; k < f; ++k) md.fac_f[r][md.nfac_f[r]++] = a;
+            for (int k = 0; k < b; ++k) md.fac_r[r][md.nfac_r[r]++] = a;
         }
         md.dnu_sum[r] = s;
     }
@@ -560,9 +567,9 @@ static int step_one(rlbm_lattice* lat, long long t) {
     for (int phase = 0; phase < NPHASE; ++phase) {
         StepLaunch a;
         a.lats = lat->d_lat;
-        a.blk = phase == 0 ? lat->d_blk + 2 : (phase == 4 ? lat->d_blk + 4 : lat->d_blk);
+        a.blk = phase == 0 ? lat->d_blk + 2 : (phase == NPHASE - 1 ? lat->d_blk + 4 : lat->d_blk);
         a.n_lat = 1;
-        a.blocks = phase == 0 ? nb_if : (phase == 4 ? nb64 : nb_nodes);
+        a.blocks = phase == 0 ? nb_if : (phase == NPHASE - 1 ? nb64 : nb_nodes);
         a.t = t;
         a.flag = lat->d_flag;
         a.stream = lat->stream;
@@ -870,9 +877,9 @@ int rlbm_batch_step(rlbm_batch* b, const int64_t* steps) {
         for (int phase = 0; phase < NPHASE; ++phase) {
             StepLaunch a;
             a.lats = b->d_table;
-            a.blk = phase == 0 ? b->d_blk + (k + 1) : (phase == 4 ? b->d_blk + 2 * (k + 1) : b->d_blk);
+            a.blk = phase == 0 ? b->d_blk + (k + 1) : (phase == NPHASE - 1 ? b->d_blk + 2 * (k + 1) : b->d_blk);
             a.n_lat = k;
-            a.blocks = phase == 0 ? nb_if : (phase == 4 ? nb64 : nb_nodes);
+            a.blocks = phase == 0 ? nb_if : (phase == NPHASE - 1 ? nb64 : nb_nodes);
             a.t = t;
             a.flag = l0->d_flag;
             a.stream = l0->stream;

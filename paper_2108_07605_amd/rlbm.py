@@ -21,6 +21,8 @@ STORAGE_F64, STORAGE_F32_DEV = 0, 1
 _FACE_CODES = {"periodic": FACE_PERIODIC, "wall": FACE_WALL, "inlet": FACE_INLET,
                "outlet": FACE_OUTLET}
 _STORAGE = {"f64": STORAGE_F64, "f32dev": STORAGE_F32_DEV}
+# kernels of one step, in launch order (rlbm_kernel_times)
+KERNELS = ("boundary", "local", "diff", "chem", "grad", "update")
 
 EXPORTS = (
     "rlbm_mech_create", "rlbm_mech_destroy", "rlbm_lattice_bytes", "rlbm_lattice_create",
@@ -308,11 +310,11 @@ class Lattice:
         _check(lib().rlbm_set_timing(self.handle, 1 if on else 0))
 
     def kernel_times(self):
-        ms = (c_double * 5)()
-        cnt = (c_int64 * 5)()
-        _check(lib().rlbm_kernel_times(self.handle, ms, cnt, 5))
+        ms = (c_double * len(KERNELS))()
+        cnt = (c_int64 * len(KERNELS))()
+        _check(lib().rlbm_kernel_times(self.handle, ms, cnt, len(KERNELS)))
         return {name: (ms[k], cnt[k])
-                for k, name in enumerate(("boundary", "local", "chem", "grad", "update"))}
+                for k, name in enumerate(KERNELS)}
 
 
 class Batch:

@@ -121,7 +121,8 @@ typedef struct rlbm_face {
 #define RLBM_STORAGE_F32_DEV 1    /* FP32 deviations from a per-(lattice, velocity) reference */
 
 typedef struct rlbm_lattice_desc {
-    int32_t nx, ny, nz;           /* >= 1 each, nx ny nz <= 2^29; >= 2 along an axis with an inlet/outlet */
+    int32_t nx, ny, nz;           /* >= 1 each, >= 2 along an axis with an inlet/outlet; N = nx ny nz
+                                     with 9 N s < 2^32 for s = 4 (FP32) or 8 (FP64) bytes */
     rlbm_face faces[6];
     int32_t storage;              /* RLBM_STORAGE_* */
     int32_t substeps;             /* reaction sub-steps l >= 1 (eq. R3) */
@@ -199,7 +200,7 @@ int rlbm_lattice_shape(const rlbm_lattice* lat, int32_t* L, int64_t* N, int64_t*
 
 /* Per-kernel timing with HIP events recorded on the lattice stream around
  * every launch while enabled.  rlbm_kernel_times synchronises and returns,
- * for kernel k in {0: boundary, 1: moments, 2: diffusion, 3: chemistry, 4: gradients, 5: update}, the accumulated
+ * for kernel k in {0: boundary, 1: moments and diffusion, 2: chemistry and gradients, 3: update}, the accumulated
  * milliseconds ms[k] and launch counts counts[k] since the last reset. */
 int rlbm_set_timing(rlbm_lattice* lat, int enable);
 int rlbm_kernel_times(rlbm_lattice* lat, double* ms, int64_t* counts, int n);

@@ -1,15 +1,15 @@
 // HIP kernels of the reactive-mixture lattice Boltzmann step for gfx950.
 //
-// One time step is six launches over a (possibly batched) work list:
+// One time step is four launches over a (possibly batched) work list:
 //   k_boundary  interface nodes: advection + wall / inlet / outlet
 //               reconstruction (section 4) into a side buffer;
 //   k_local     every node: advection, moments, temperature (eq. temperature),
-//               relaxation rates; publishes rho, u, T, Y, Phi_a and the
-//               enthalpy moments for the neighbours and starts the per-node
-//               record read by k_update;
-//   k_diff      Stefan-Maxwell diffusion velocities (eq. transform1);
-//   k_chem      reaction increment by l sub-steps (eq. R3);
-//   k_grad      same-time gradients of Phi_a and sum_b H_b Y_b;
+//               relaxation rates and Stefan-Maxwell diffusion velocities (eq.
+//               transform1); publishes rho, u, T, Y, Phi_a and the enthalpy
+//               moments for the neighbours and writes the per-node record
+//               read by k_update;
+//   k_chem      reaction increment by l sub-steps (eq. R3), then the
+//               same-time gradients of Phi_a and sum_b H_b Y_b;
 //   k_update    every node: advection again and the collisions of all stored
 //               lattices, written to the other population buffer.
 // Populations are structure-of-arrays [L][27][N] (x fastest), pulled from the
@@ -93,6 +93,17 @@ __device__ __forceinline__ int xcd_block() {
     return j * q + (j < r ? j : r) + i;
 }
 
+// Byte-offset addressing: a uniform base plus a 32-bit per-lane offset keeps
+// every population access in the scalar-base form (no 64-bit address math).
+template <typename S>
+__device__ __forceinline__ S ld_at(const RLBM_GLOBAL S* base, int idx) {
+    return *(const RLBM_GLOBAL S*)((const RLBM_GLOBAL char*)base + (unsigned)(idx * (int)sizeof(S)));
+}
+template <typename S>
+__device__ __forceinline__ void st_at(RLBM_GLOBAL S* base, int idx, S v) {
+    *(RLBM_GLOBAL S*)((RLBM_GLOBAL char*)base + (unsigned)(idx * (int)sizeof(S))) = v;
+}
+
 // ---------------------------------------------------------------------------
 // work-list helpers
 // ---------------------------------------------------------------------------
@@ -136,6 +147,100 @@ template <int M>
 __device__ __forceinline__ int lat_of(int a, int slaved) { return a - (a > slaved ? 1 : 0); }
 
 // ---------------------------------------------------------------------------
+// Stefan-Maxwell diffusion velocities (section 2.3, eq. transform1)
+// ---------------------------------------------------------------------------
+// The system (dt = 1)
+//   (1 + 1/(2 tau_a)) V_a - 1/2 sum_{b != a} Y_b V_b / tau_ab = u_a - u
+// with 1/tau_ab = common K_ab and 1/tau_a = sum_{b != a} Y_b / tau_ab, for
+// the three components at once.  Its matrix is strictly row diagonally
+// dominant with margin 1 (the off-diagonal row sums are -1/(2 tau_a)), so
+// Doolittle LU without pivoting is stable.  Rows are generated on the fly
+// from cY_b = -common Y_b / 2 (A_ab = K_ab cY_b), the forward substitution
+// runs with the factorisation, and beta_a = 1/(2 tau_a + 1) is written as
+// soon as row a has its 1/tau_a.  Reads Y (aux), u_a - u, common, T, rho
+// and the rates back from the node's own record entries (written just before
+// by k_local, so they come from cache); writes V_a and beta_a and adds
+// omega1 rho sum_a H_a Y_a V_a to the energy flux base.
+template <int M>
+__device__ __forceinline__ void stefan_maxwell(const LatDev& L, int node) {
+    MechC mc0 = *as_const(L.mech);
+    const size_t N = (size_t)L.N;
+    const RLBM_GLOBAL double* aux = as_global(L.aux);
+    RLBM_GLOBAL double* prm = as_global(L.prm);
+    const double common = ld_at(prm + PRM_COMMON * N, node);
+    double cY[M], V[M][3];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        cY[a] = -0.5 * common * ld_at(aux + (AUX_Y + a) * N, node);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) V[a][d] = ld_at(prm + (PRM_SP + 6 * a + 1 + d) * N, node);
+    }
+    double Uu[M][M];
+    double inv_diag[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        reload_barrier();
+        MechC mc = in_loop(mc0);   // this row's K_ab as scalar loads, not hoisted
+        double st = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+            if (c != i) st += mc.Kab[i][c] * cY[c];
+        const double inv_tau = -2.0 * st;
+        st_at(prm + (PRM_SP + 6 * i + 4) * N, node, inv_tau / (2.0 + inv_tau));   // beta_a = dt/(2 tau_a + dt)
+        double lrow[M];
+#pragma unroll
+        for (int j = 0; j < i; ++j) {
+            double a = mc.Kab[i][j] * cY[j];
+#pragma unroll
+            for (int kk = 0; kk < j; ++kk) a -= lrow[kk] * Uu[kk][j];
+            lrow[j] = a * inv_diag[j];
+        }
+#pragma unroll
+        for (int j = i; j < M; ++j) {
+            double a = (i == j) ? 1.0 + 0.5 * inv_tau : mc.Kab[i][j] * cY[j];
+#pragma unroll
+            for (int kk = 0; kk < i; ++kk) a -= lrow[kk] * Uu[kk][j];
+            Uu[i][j] = a;
+        }
+        inv_diag[i] = 1.0 / Uu[i][i];
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) {
+            double yv = V[i][dd];
+#pragma unroll
+            for (int kk = 0; kk < i; ++kk) yv -= lrow[kk] * V[kk][dd];
+            V[i][dd] = yv;
+        }
+    }
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) {
+            double sm = V[i][dd];
+#pragma unroll
+            for (int j = i + 1; j < M; ++j) sm -= Uu[i][j] * V[j][dd];
+            V[i][dd] = sm * inv_diag[i];
+            st_at(prm + (PRM_SP + 6 * i + 1 + dd) * N, node, V[i][dd]);
+        }
+    }
+    MechC mc = mc0;
+    const double T = ld_at(prm + PRM_T * N, node);
+    double diff[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        const double hy = (species_U(mc, a, T) + mc.Ra[a] * T) * ld_at(aux + (AUX_Y + a) * N, node);
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) diff[dd] += hy * V[a][dd];
+    }
+    const double omega1 = ld_at(prm + PRM_OMEGA * N, node) - ld_at(prm + PRM_WQ * N, node);
+    const double rr = omega1 * ld_at(prm + PRM_RHO * N, node);
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) {
+        RLBM_GLOBAL double* qb = prm + (PRM_QB + dd) * N;
+        st_at(qb, node, ld_at(qb, node) + rr * diff[dd]);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_local: moments and everything else a node needs from its own populations
 // ---------------------------------------------------------------------------
 // Moments of the node's post-advection, post-boundary populations (eqs.
@@ -149,8 +254,8 @@ __device__ __forceinline__ int lat_of(int a, int slaved) { return a - (a > slave
 // reference's own moments are added in closed form (zeroth s_l sum_i G_li,
 // second s_f sum_i G_fi c c, first zero by symmetry); the stored lattices'
 // zeroth moments (rho_a, rho, rho E) become the scales of the references of
-// the populations written this step.  The Stefan-Maxwell solve is left to
-// k_diff, which keeps this streaming kernel small in registers.
+// the populations written this step.  The Stefan-Maxwell solve comes last,
+// once the streaming part no longer holds registers.
 template <int M>
 struct LocalMoments {
     double rho, rhoE, j[3], q[3], Pd[3], Po[3];   // Pd: xx yy zz, Po: xy xz yz
@@ -158,16 +263,6 @@ struct LocalMoments {
     double rho_a[M];
 };
 
-// Byte-offset addressing: a uniform base plus a 32-bit per-lane offset keeps
-// every population access in the scalar-base form (no 64-bit address math).
-template <typename S>
-__device__ __forceinline__ S ld_at(const RLBM_GLOBAL S* base, int idx) {
-    return *(const RLBM_GLOBAL S*)((const RLBM_GLOBAL char*)base + (unsigned)(idx * (int)sizeof(S)));
-}
-template <typename S>
-__device__ __forceinline__ void st_at(RLBM_GLOBAL S* base, int idx, S v) {
-    *(RLBM_GLOBAL S*)((RLBM_GLOBAL char*)base + (unsigned)(idx * (int)sizeof(S))) = v;
-}
 
 // Buffer-resource load: a wave-uniform base (scalar registers) plus a 32-bit
 // per-lane byte offset (node counts are limited so that idx * sizeof(S) fits).
@@ -184,6 +279,21 @@ __device__ __forceinline__ S ldb(const RLBM_GLOBAL S* base, unsigned nbytes, int
 __device__ __forceinline__ unsigned plane_bytes(long long N, int s) {
     const unsigned long long b = (unsigned long long)N * (unsigned)s;
     return b > 0xffffffffull ? 0xffffffffu : (unsigned)b;
+}
+
+// Population loads through one resource per window of nine planes (the nine
+// velocities of one c_z layer of one lattice): the plane within the window is
+// a scalar offset, the node a per-lane offset.  Few resources stay live, so
+// the scalar registers do not run out.  The host keeps 9 N sizeof(S) below
+// 2^32.
+template <typename S>
+__device__ __forceinline__ S ld_win(const RLBM_GLOBAL S* win, unsigned plane, int iw, int idx) {
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(unsigned long long)win, 0, (int)(9u * plane), 0x00020000);
+    if constexpr (sizeof(S) == 4)
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (unsigned)idx * 4u, iw * plane, 0));
+    else
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (unsigned)idx * 8u, iw * plane, 0));
 }
 
 // The moment sums of k_local.  IF = false: no lane of the wave is an
@@ -204,10 +314,10 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
     auto ld = [&](int l, int i) -> S {
         const int li = l * Q + i;
         if constexpr (!IF) {
-            return ldb(src + (size_t)li * N, nb, off_of(i));
+            return ld_win(src + (size_t)(l * Q + 9 * (i / 9)) * N, nb, i % 9, off_of(i));
         } else {
-            if (k >= 0) return bc[(size_t)li * nif + k];
-            return src[(size_t)li * N + off_of(i)];
+            if (k >= 0) return ld_at(bc + (size_t)li * nif, k);
+            return ld_at(src + (size_t)li * N, off_of(i));
         }
     };
     const RLBM_GLOBAL float* sc = nullptr;
@@ -318,7 +428,7 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
 }
 
 template <int M, typename S>
-__global__ __launch_bounds__(256) void k_local(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_local(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                                int n_lat, long long t, int* __restrict__ flag) {
     const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
@@ -377,7 +487,7 @@ __global__ __launch_bounds__(256) void k_local(const LatDev* __restrict__ lats, 
         Pk[kk] = pk;
     }
     // local part of the energy-lattice flux
-    //   Qb = (omega - omega1)(q - u.(P - P^eq) - q^eq); k_diff adds
+    //   Qb = (omega - omega1)(q - u.(P - P^eq) - q^eq); the Stefan-Maxwell step adds
     //   omega1 rho sum_a H_a Y_a V_a
     {
         const double H = Pk[0] + T * (Pk[1] + T * (Pk[2] + T * (Pk[3] + T * (Pk[4] + T * Pk[5]))));
@@ -415,143 +525,11 @@ __global__ __launch_bounds__(256) void k_local(const LatDev* __restrict__ lats, 
     prm[PRM_COMMON * N + node] = common;
     prm[PRM_WQ * N + node] = omega - omega1;
     prm[PRM_CC * N + node] = 0.5 * (2.0 - omega1) * P;
+    stefan_maxwell<M>(L, node);
 }
 
 // ---------------------------------------------------------------------------
-// k_diff: Stefan-Maxwell diffusion velocities (section 2.3, eq. transform1)
-// ---------------------------------------------------------------------------
-// The system (dt = 1)
-//   (1 + 1/(2 tau_a)) V_a - 1/2 sum_{b != a} Y_b V_b / tau_ab = u_a - u
-// with 1/tau_ab = common K_ab and 1/tau_a = sum_{b != a} Y_b / tau_ab, for
-// the three components at once.  Its matrix is strictly row diagonally
-// dominant with margin 1 (the off-diagonal row sums are -1/(2 tau_a)), so
-// Doolittle LU without pivoting is stable.  Rows are generated on the fly
-// from cY_b = -common Y_b / 2 (A_ab = K_ab cY_b), the forward substitution
-// runs with the factorisation, and beta_a = 1/(2 tau_a + 1) is written as
-// soon as row a has its 1/tau_a.  Reads Y (aux), u_a - u, common, T, rho
-// and the rates from the per-node record; writes V_a and beta_a and adds
-// omega1 rho sum_a H_a Y_a V_a to the energy flux base.
-template <int M>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_diff(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                              int n_lat, long long t, int* __restrict__ flag) {
-    (void)flag;
-    const int b = xcd_block();
-    const int lj = find_lattice(blk, n_lat, b);
-    const LatDev& L = lats[lj];
-    if (t >= L.t_end) return;
-    const int node = (b - blk[lj]) * 256 + threadIdx.x;
-    if (node >= L.N) return;
-    MechC mc0 = *as_const(L.mech);
-    const size_t N = (size_t)L.N;
-    const RLBM_GLOBAL double* aux = as_global(L.aux);
-    RLBM_GLOBAL double* prm = as_global(L.prm);
-    const double common = ld_at(prm + PRM_COMMON * N, node);
-    double cY[M], V[M][3];
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-        cY[a] = -0.5 * common * ld_at(aux + (AUX_Y + a) * N, node);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) V[a][d] = ld_at(prm + (PRM_SP + 6 * a + 1 + d) * N, node);
-    }
-    double Uu[M][M];
-    double inv_diag[M];
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-        reload_barrier();
-        MechC mc = in_loop(mc0);   // this row's K_ab as scalar loads, not hoisted
-        double st = 0.0;
-#pragma unroll
-        for (int c = 0; c < M; ++c)
-            if (c != i) st += mc.Kab[i][c] * cY[c];
-        const double inv_tau = -2.0 * st;
-        st_at(prm + (PRM_SP + 6 * i + 4) * N, node, inv_tau / (2.0 + inv_tau));   // beta_a = dt/(2 tau_a + dt)
-        double lrow[M];
-#pragma unroll
-        for (int j = 0; j < i; ++j) {
-            double a = mc.Kab[i][j] * cY[j];
-#pragma unroll
-            for (int kk = 0; kk < j; ++kk) a -= lrow[kk] * Uu[kk][j];
-            lrow[j] = a * inv_diag[j];
-        }
-#pragma unroll
-        for (int j = i; j < M; ++j) {
-            double a = (i == j) ? 1.0 + 0.5 * inv_tau : mc.Kab[i][j] * cY[j];
-#pragma unroll
-            for (int kk = 0; kk < i; ++kk) a -= lrow[kk] * Uu[kk][j];
-            Uu[i][j] = a;
-        }
-        inv_diag[i] = 1.0 / Uu[i][i];
-#pragma unroll
-        for (int dd = 0; dd < 3; ++dd) {
-            double yv = V[i][dd];
-#pragma unroll
-            for (int kk = 0; kk < i; ++kk) yv -= lrow[kk] * V[kk][dd];
-            V[i][dd] = yv;
-        }
-    }
-#pragma unroll
-    for (int i = M - 1; i >= 0; --i) {
-#pragma unroll
-        for (int dd = 0; dd < 3; ++dd) {
-            double sm = V[i][dd];
-#pragma unroll
-            for (int j = i + 1; j < M; ++j) sm -= Uu[i][j] * V[j][dd];
-            V[i][dd] = sm * inv_diag[i];
-            st_at(prm + (PRM_SP + 6 * i + 1 + dd) * N, node, V[i][dd]);
-        }
-    }
-    MechC mc = mc0;
-    const double T = ld_at(prm + PRM_T * N, node);
-    double diff[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-        const double hy = (species_U(mc, a, T) + mc.Ra[a] * T) * ld_at(aux + (AUX_Y + a) * N, node);
-#pragma unroll
-        for (int dd = 0; dd < 3; ++dd) diff[dd] += hy * V[a][dd];
-    }
-    const double omega1 = ld_at(prm + PRM_OMEGA * N, node) - ld_at(prm + PRM_WQ * N, node);
-    const double rr = omega1 * ld_at(prm + PRM_RHO * N, node);
-#pragma unroll
-    for (int dd = 0; dd < 3; ++dd) {
-        RLBM_GLOBAL double* qb = prm + (PRM_QB + dd) * N;
-        st_at(qb, node, ld_at(qb, node) + rr * diff[dd]);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// k_chem: reaction increment of every node (eq. R3), l forward-Euler
-// sub-steps at frozen specific internal energy; reads rho_a, rho, U, T from
-// the per-node record and writes Delta rho_a into it
-// ---------------------------------------------------------------------------
-template <int M>
-__global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                              int n_lat, long long t, int* __restrict__ flag) {
-    const int b = xcd_block();
-    const int lj = find_lattice(blk, n_lat, b);
-    const LatDev& L = lats[lj];
-    if (t >= L.t_end) return;
-    const int node = (b - blk[lj]) * 256 + threadIdx.x;
-    if (node >= L.N) return;
-    MechC mc = *as_const(L.mech);
-    double* prm = L.prm;
-    const size_t N = (size_t)L.N;
-    __shared__ double s_c[M][256], s_g[M][256];
-    const ChemLds<256> ls{&s_c[0][threadIdx.x], &s_g[0][threadIdx.x]};
-    double rho_a[M], drho[M];
-#pragma unroll
-    for (int a = 0; a < M; ++a) rho_a[a] = prm[(PRM_SP + 6 * a) * N + node];
-    const double rho = prm[PRM_RHO * N + node];
-    const double U = prm[PRM_UINT * N + node];
-    const double T = prm[PRM_T * N + node];
-    int fail = 0;
-    reaction_increment<M, 256>(mc, rho_a, rho, U, T, L.substeps, ls, drho, &fail);
-    if (fail) atomicOr(flag, 1);
-#pragma unroll
-    for (int a = 0; a < M; ++a) prm[(PRM_SP + 6 * a + 5) * N + node] = drho[a];
-}
-
-// ---------------------------------------------------------------------------
-// k_grad: same-time gradients with the isotropic D3Q27 stencil
+// same-time gradients with the isotropic D3Q27 stencil
 //   d phi/dx_a = 3 sum_i w_i c_ia phi(x + c_i)
 // of Phi_a (extension, eqs. Pex, qex) and of sum_b H_b Y_b with H_b at this
 // node's temperature (Fourier correction, eq. corrFourier), from the fields
@@ -559,14 +537,7 @@ __global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, c
 // nearest node.  Writes rows PRM_GRAD..PRM_GRAD+5 of the per-node record.
 // ---------------------------------------------------------------------------
 template <int M>
-__global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                              int n_lat, long long t, int* __restrict__ flag) {
-    const int b = xcd_block();
-    const int lj = find_lattice(blk, n_lat, b);
-    const LatDev& L = lats[lj];
-    if (t >= L.t_end) return;
-    const int node = (b - blk[lj]) * 256 + threadIdx.x;
-    if (node >= L.N) return;
+__device__ __forceinline__ void node_gradients(const LatDev& L, int node) {
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int x = node % nx, r = node / nx, y = r % ny, z = r / ny;
     const size_t N = (size_t)L.N;
@@ -601,6 +572,42 @@ __global__ __launch_bounds__(256) void k_grad(const LatDev* __restrict__ lats, c
 #pragma unroll
     for (int q = 0; q < 6; ++q) prm[(size_t)(prm_grad(M) + q) * N + node] = acc[q];
 }
+
+// ---------------------------------------------------------------------------
+// k_chem: reaction increment of every node (eq. R3), l forward-Euler
+// sub-steps at frozen specific internal energy, reading rho_a, rho, U, T from
+// the per-node record and writing Delta rho_a into it; then the node's
+// same-time gradients.  The stencil's neighbour loads are latency-bound and
+// the chemistry is arithmetic-bound, so the two share one launch.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+                                              int n_lat, long long t, int* __restrict__ flag) {
+    const int b = xcd_block();
+    const int lj = find_lattice(blk, n_lat, b);
+    const LatDev& L = lats[lj];
+    if (t >= L.t_end) return;
+    const int node = (b - blk[lj]) * 256 + threadIdx.x;
+    if (node >= L.N) return;
+    MechC mc = *as_const(L.mech);
+    double* prm = L.prm;
+    const size_t N = (size_t)L.N;
+    __shared__ double s_c[M][256], s_g[M][256];
+    const ChemLds<256> ls{&s_c[0][threadIdx.x], &s_g[0][threadIdx.x]};
+    double rho_a[M], drho[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) rho_a[a] = prm[(PRM_SP + 6 * a) * N + node];
+    const double rho = prm[PRM_RHO * N + node];
+    const double U = prm[PRM_UINT * N + node];
+    const double T = prm[PRM_T * N + node];
+    int fail = 0;
+    reaction_increment<M, 256>(mc, rho_a, rho, U, T, L.substeps, ls, drho, &fail);
+    if (fail) atomicOr(flag, 1);
+#pragma unroll
+    for (int a = 0; a < M; ++a) prm[(PRM_SP + 6 * a + 5) * N + node] = drho[a];
+    node_gradients<M>(L, node);
+}
+
 
 // ---------------------------------------------------------------------------
 // k_update: the collision of every stored lattice (section 2.3 eq.
@@ -1092,7 +1099,7 @@ __device__ __forceinline__ void bc_local(MechC mc, const BcState<M, ASPV>& A, in
 constexpr int BC_THREADS = 32 * BC_NODES;
 
 template <int M, typename S>
-__global__ __launch_bounds__(BC_THREADS) void k_boundary(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+__global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_boundary(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                                          int n_lat, long long t, int* __restrict__ flag) {
     const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
@@ -1606,13 +1613,7 @@ static hipError_t launch_step_phase(int phase, int M, const StepLaunch& a) {
         RLBM_DISPATCH(M, hipLaunchKernelGGL((k_local<MM, S>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
                                                 a.blk, a.n_lat, a.t, a.flag))
     } else if (phase == 2) {
-        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_diff<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
-                                                a.blk, a.n_lat, a.t, a.flag))
-    } else if (phase == 3) {
         RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
-                                                a.blk, a.n_lat, a.t, a.flag))
-    } else if (phase == 4) {
-        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_grad<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
                                                 a.blk, a.n_lat, a.t, a.flag))
     } else {
         RLBM_DISPATCH(M, hipLaunchKernelGGL((k_update<MM, S>), dim3(a.blocks), dim3(UPD_THREADS), 0, a.stream, a.lats,

@@ -21,9 +21,9 @@ struct StepLaunch {
 // Interface nodes per boundary block (half a wave per node).
 constexpr int BC_NODES = 8;
 
-// phase 0: boundary (BC_NODES interface nodes per block); phases 1 to 4:
-// moments, diffusion, chemistry, gradients (256-thread blocks over nodes);
-// phase 5: update (one block per 64 nodes).
+// phase 0: boundary (BC_NODES interface nodes per block); phases 1 and 2:
+// moments and diffusion, chemistry and gradients (256-thread blocks over
+// nodes); phase 3: update (one block per 64 nodes).
 hipError_t launch_phase(int phase, int M, int storage, const StepLaunch& a);
 hipError_t launch_init(int M, int storage, const LatDev* lat, long long N, const double* rho, const double* u,
                        const double* T, const double* Y, hipStream_t st);

@@ -38,7 +38,7 @@ int hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-constexpr int NPHASE = 6;   // boundary, local, diffusion, chemistry, gradients, update
+constexpr int NPHASE = 4;   // boundary, moments + diffusion, chemistry + gradients, update
 
 struct Plan {
     size_t off_lat, off_mech, off_blk, off_flag, off_ref, off_pop0, off_pop1, off_aux, off_prm, off_ifindex, off_ifnode,
@@ -59,9 +59,11 @@ bool face_valid(int t) { return t >= RLBM_FACE_PERIODIC && t <= RLBM_FACE_OUTLET
 int validate_desc(const rlbm_lattice_desc* d, int M) {
     if (!d) return fail(RLBM_EINVAL, "null lattice descriptor");
     if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(RLBM_EINVAL, "lattice dimensions must be >= 1");
-    // kernels address a population plane with 32-bit byte offsets
-    if ((long long)d->nx * d->ny * d->nz > (1LL << 29))
-        return fail(RLBM_EUNSUP, "more than 2^29 nodes");
+    // kernels address nine population planes with 32-bit byte offsets
+    const long long n_nodes = (long long)d->nx * d->ny * d->nz;
+    const long long s_bytes = d->storage == RLBM_STORAGE_F32_DEV ? 4 : 8;
+    if (9 * s_bytes * n_nodes >= (1LL << 32))
+        return fail(RLBM_EUNSUP, "too many nodes: 9 N sizeof(storage) must stay below 2^32");
     for (int f = 0; f < 6; ++f)
         if (!face_valid(d->faces[f].type)) return fail(RLBM_EINVAL, "unknown face type");
     const int n[3] = {d->nx, d->ny, d->nz};
@@ -227,8 +229,8 @@ struct rlbm_lattice {
     bool state_set = false;
     bool timing = false;
     std::vector<Timing> events;
-    double ms[NPHASE] = {0, 0, 0, 0, 0, 0};
-    long long counts[NPHASE] = {0, 0, 0, 0, 0, 0};
+    double ms[NPHASE] = {0, 0, 0, 0};
+    long long counts[NPHASE] = {0, 0, 0, 0};
 };
 
 struct rlbm_batch {

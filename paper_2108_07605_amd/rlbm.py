@@ -22,7 +22,7 @@ _FACE_CODES = {"periodic": FACE_PERIODIC, "wall": FACE_WALL, "inlet": FACE_INLET
                "outlet": FACE_OUTLET}
 _STORAGE = {"f64": STORAGE_F64, "f32dev": STORAGE_F32_DEV}
 # kernels of one step, in launch order (rlbm_kernel_times)
-KERNELS = ("boundary", "local", "diff", "chem", "grad", "update")
+KERNELS = ("boundary", "local", "chem", "update")
 
 EXPORTS = (
     "rlbm_mech_create", "rlbm_mech_destroy", "rlbm_lattice_bytes", "rlbm_lattice_create",

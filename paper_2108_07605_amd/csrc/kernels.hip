@@ -146,6 +146,15 @@ __device__ __forceinline__ double sel3d(int c, double m, double z, double p) { r
 template <int M>
 __device__ __forceinline__ int lat_of(int a, int slaved) { return a - (a > slaved ? 1 : 0); }
 
+// Per-thread LDS columns of k_local (stride 256 doubles between rows): the
+// species densities rho_a [M] and velocity differences u_a - u [3 M], handed
+// from the streaming part to the Stefan-Maxwell step without a trip to memory.
+struct LocalLds {
+    double* ra;   // &rho_a[0][tid]
+    double* dv;   // &(u_a - u)[0][tid], row 3 a + d
+};
+constexpr int LOC_T = 256;   // k_local threads per block
+
 // ---------------------------------------------------------------------------
 // Stefan-Maxwell diffusion velocities (section 2.3, eq. transform1)
 // ---------------------------------------------------------------------------
@@ -157,23 +166,22 @@ __device__ __forceinline__ int lat_of(int a, int slaved) { return a - (a > slave
 // Doolittle LU without pivoting is stable.  Rows are generated on the fly
 // from cY_b = -common Y_b / 2 (A_ab = K_ab cY_b), the forward substitution
 // runs with the factorisation, and beta_a = 1/(2 tau_a + 1) is written as
-// soon as row a has its 1/tau_a.  Reads Y (aux), u_a - u, common, T, rho
-// and the rates back from the node's own record entries (written just before
-// by k_local, so they come from cache); writes V_a and beta_a and adds
-// omega1 rho sum_a H_a Y_a V_a to the energy flux base.
+// soon as row a has its 1/tau_a.  The velocity differences u_a - u and the
+// densities rho_a come from k_local's LDS columns, the node's scalars from
+// its registers; writes V_a, beta_a and the energy flux base Qb plus
+// omega1 sum_a H_a rho_a V_a to the per-node record.
 template <int M>
-__device__ __forceinline__ void stefan_maxwell(const LatDev& L, int node) {
+__device__ __forceinline__ void stefan_maxwell(const LatDev& L, int node, const LocalLds& ls, double T, double rho,
+                                               double common, double omega1, const double* Y, const double* Qb) {
     MechC mc0 = *as_const(L.mech);
     const size_t N = (size_t)L.N;
-    const RLBM_GLOBAL double* aux = as_global(L.aux);
     RLBM_GLOBAL double* prm = as_global(L.prm);
-    const double common = ld_at(prm + PRM_COMMON * N, node);
     double cY[M], V[M][3];
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-        cY[a] = -0.5 * common * ld_at(aux + (AUX_Y + a) * N, node);
+        cY[a] = -0.5 * common * Y[a];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) V[a][d] = ld_at(prm + (PRM_SP + 6 * a + 1 + d) * N, node);
+        for (int d = 0; d < 3; ++d) V[a][d] = ls.dv[(3 * a + d) * LOC_T];
     }
     double Uu[M][M];
     double inv_diag[M];
@@ -222,22 +230,18 @@ __device__ __forceinline__ void stefan_maxwell(const LatDev& L, int node) {
             st_at(prm + (PRM_SP + 6 * i + 1 + dd) * N, node, V[i][dd]);
         }
     }
+    // energy flux: Qb + omega1 sum_a H_a rho_a V_a
     MechC mc = mc0;
-    const double T = ld_at(prm + PRM_T * N, node);
     double diff[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-        const double hy = (species_U(mc, a, T) + mc.Ra[a] * T) * ld_at(aux + (AUX_Y + a) * N, node);
+        const double hy = (species_U(mc, a, T) + mc.Ra[a] * T) * ls.ra[a * LOC_T];
 #pragma unroll
         for (int dd = 0; dd < 3; ++dd) diff[dd] += hy * V[a][dd];
     }
-    const double omega1 = ld_at(prm + PRM_OMEGA * N, node) - ld_at(prm + PRM_WQ * N, node);
-    const double rr = omega1 * ld_at(prm + PRM_RHO * N, node);
+    (void)rho;
 #pragma unroll
-    for (int dd = 0; dd < 3; ++dd) {
-        RLBM_GLOBAL double* qb = prm + (PRM_QB + dd) * N;
-        st_at(qb, node, ld_at(qb, node) + rr * diff[dd]);
-    }
+    for (int dd = 0; dd < 3; ++dd) st_at(prm + (PRM_QB + dd) * N, node, Qb[dd] + omega1 * diff[dd]);
 }
 
 // ---------------------------------------------------------------------------
@@ -302,7 +306,7 @@ __device__ __forceinline__ S ld_win(const RLBM_GLOBAL S* win, unsigned plane, in
 // boundary buffer instead.
 template <int M, typename S, bool IF>
 __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, int node, const PullOff& o,
-                                              LocalMoments<M>& m) {
+                                              const LocalLds& ls, LocalMoments<M>& m) {
     const size_t N = (size_t)L.N;
     const int nif = L.n_if;
     const int s = L.slaved;
@@ -358,17 +362,17 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
     const double u[3] = {j[0] * inv_rho, j[1] * inv_rho, j[2] * inv_rho};
 
     // species lattices, one at a time, the next one's loads in flight while
-    // the current one is summed; rows PRM_SP + 6 a + {0, 1..3} receive rho_a
-    // and u_a - u (zero for an absent species, u_a := u)
+    // the current one is summed; rho_a goes to the record row PRM_SP + 6 a and
+    // with u_a - u (zero for an absent species, u_a := u) to LDS
     double rs = rho, js[3] = {j[0], j[1], j[2]};
     auto put_species = [&](int a, double ra, double jx, double jy, double jz) {
         const bool small = ra <= 1e-14 * rho;
         const double inv = small ? 0.0 : 1.0 / ra;
-        RLBM_GLOBAL double* pr = prm + (size_t)(PRM_SP + 6 * a) * N;
-        st_at(pr, node, ra);
-        st_at(pr + N, node, small ? 0.0 : jx * inv - u[0]);
-        st_at(pr + 2 * N, node, small ? 0.0 : jy * inv - u[1]);
-        st_at(pr + 3 * N, node, small ? 0.0 : jz * inv - u[2]);
+        st_at(prm + (size_t)(PRM_SP + 6 * a) * N, node, ra);
+        ls.ra[a * LOC_T] = ra;
+        ls.dv[(3 * a + 0) * LOC_T] = small ? 0.0 : jx * inv - u[0];
+        ls.dv[(3 * a + 1) * LOC_T] = small ? 0.0 : jy * inv - u[1];
+        ls.dv[(3 * a + 2) * LOC_T] = small ? 0.0 : jz * inv - u[2];
     };
     // FP32 storage double-buffers the species loads; FP64 has no registers
     // to spare for it
@@ -415,10 +419,10 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
         }
     }
     put_species(s, rs, js[0], js[1], js[2]);
-    // the species densities are read back from the record (this thread's own
-    // stores) rather than held in registers through the loop
+    // the species densities come back from LDS rather than being held in
+    // registers through the loop
 #pragma unroll
-    for (int c = 0; c < M; ++c) m.rho_a[c] = ld_at(prm + (size_t)(PRM_SP + 6 * c) * N, node);
+    for (int c = 0; c < M; ++c) m.rho_a[c] = ls.ra[c * LOC_T];
     m.rho = rho;
     m.rhoE = rhoE;
 #pragma unroll
@@ -446,9 +450,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     double* prm = L.prm;
     const size_t N = (size_t)L.N;
 
+    __shared__ double s_ra[M][LOC_T], s_dv[3 * M][LOC_T];
+    const LocalLds ls{&s_ra[0][threadIdx.x], &s_dv[0][threadIdx.x]};
     LocalMoments<M> m;
-    if (__builtin_amdgcn_ballot_w64(k >= 0) != 0) local_moments<M, S, true>(L, par, k, node, o, m);
-    else local_moments<M, S, false>(L, par, k, node, o, m);
+    if (__builtin_amdgcn_ballot_w64(k >= 0) != 0) local_moments<M, S, true>(L, par, k, node, o, ls, m);
+    else local_moments<M, S, false>(L, par, k, node, o, ls, m);
     const double rho = m.rho, inv_rho = 1.0 / rho;
     const double u[3] = {m.u[0], m.u[1], m.u[2]};
     const double rhoE = m.rhoE;
@@ -489,6 +495,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // local part of the energy-lattice flux
     //   Qb = (omega - omega1)(q - u.(P - P^eq) - q^eq); the Stefan-Maxwell step adds
     //   omega1 rho sum_a H_a Y_a V_a
+    double Qb[3];
     {
         const double H = Pk[0] + T * (Pk[1] + T * (Pk[2] + T * (Pk[3] + T * (Pk[4] + T * Pk[5]))));
         const double hq = rho * (H + 0.5 * usq);
@@ -498,7 +505,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             double uP = 0.0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) uP += u[c] * (Pt[c][a] - rho * ((a == c ? th : 0.0) + u[c] * u[a]));
-            prm[(size_t)(PRM_QB + a) * N + node] = (omega - omega1) * (q[a] - uP - hq * u[a]);
+            Qb[a] = (omega - omega1) * (q[a] - uP - hq * u[a]);
         }
     }
 
@@ -525,7 +532,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     prm[PRM_COMMON * N + node] = common;
     prm[PRM_WQ * N + node] = omega - omega1;
     prm[PRM_CC * N + node] = 0.5 * (2.0 - omega1) * P;
-    stefan_maxwell<M>(L, node);
+    stefan_maxwell<M>(L, node, ls, T, rho, common, omega1, Y, Qb);
 }
 
 // ---------------------------------------------------------------------------

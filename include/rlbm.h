@@ -199,9 +199,11 @@ int rlbm_lattice_shape(const rlbm_lattice* lat, int32_t* L, int64_t* N, int64_t*
                        int32_t* slaved);
 
 /* Per-kernel timing with HIP events recorded on the lattice stream around
- * every launch while enabled.  rlbm_kernel_times synchronises and returns,
- * for kernel k in {0: boundary, 1: moments and diffusion, 2: chemistry and gradients, 3: update}, the accumulated
- * milliseconds ms[k] and launch counts counts[k] since the last reset. */
+ * the launches of the kernels selected by `enable`: bit k set times kernel k
+ * in {0: boundary, 1: moments and diffusion, 2: chemistry and gradients,
+ * 3: update}; 0 switches timing off.  Event pairs are pooled and reused.
+ * rlbm_kernel_times synchronises and returns the accumulated milliseconds
+ * ms[k] and launch counts counts[k] since the last reset. */
 int rlbm_set_timing(rlbm_lattice* lat, int enable);
 int rlbm_kernel_times(rlbm_lattice* lat, double* ms, int64_t* counts, int n);
 

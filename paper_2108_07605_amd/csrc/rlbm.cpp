@@ -227,8 +227,9 @@ struct rlbm_lattice {
     double* d_invout = nullptr;
     long long steps_done = 0;
     bool state_set = false;
-    bool timing = false;
-    std::vector<Timing> events;
+    unsigned timing = 0;           // bit k: time kernel k
+    std::vector<Timing> events;    // pool of event pairs; the first n_events are recorded
+    size_t n_events = 0;
     double ms[NPHASE] = {0, 0, 0, 0};
     long long counts[NPHASE] = {0, 0, 0, 0};
 };
@@ -576,18 +577,23 @@ static int step_one(rlbm_lattice* lat, long long t) {
         a.flag = lat->d_flag;
         a.stream = lat->stream;
         if (a.blocks == 0) continue;
-        Timing ev{};
-        if (lat->timing) {
-            ev.kernel = phase;
-            HIP_TRY(hipEventCreate(&ev.a), "hipEventCreate");
-            HIP_TRY(hipEventCreate(&ev.b), "hipEventCreate");
-            HIP_TRY(hipEventRecord(ev.a, lat->stream), "hipEventRecord");
+        Timing* ev = nullptr;
+        if (lat->timing >> phase & 1u) {
+            if (lat->n_events == lat->events.size()) {
+                Timing e{};
+                HIP_TRY(hipEventCreate(&e.a), "hipEventCreate");
+                if (hipEventCreate(&e.b) != hipSuccess) {
+                    (void)hipEventDestroy(e.a);
+                    return fail(RLBM_EHIP, "hipEventCreate failed");
+                }
+                lat->events.push_back(e);
+            }
+            ev = &lat->events[lat->n_events++];
+            ev->kernel = phase;
+            HIP_TRY(hipEventRecord(ev->a, lat->stream), "hipEventRecord");
         }
         HIP_TRY(launch_phase(phase, lat->M, lat->storage, a), "step kernel launch");
-        if (lat->timing) {
-            HIP_TRY(hipEventRecord(ev.b, lat->stream), "hipEventRecord");
-            lat->events.push_back(ev);
-        }
+        if (ev) HIP_TRY(hipEventRecord(ev->b, lat->stream), "hipEventRecord");
     }
     return RLBM_OK;
 }
@@ -784,22 +790,21 @@ int rlbm_invariants(rlbm_lattice* lat, double* out, int n_out) {
 
 int rlbm_set_timing(rlbm_lattice* lat, int enable) {
     if (!lat) return fail(RLBM_EINVAL, "null lattice");
-    lat->timing = enable != 0;
+    lat->timing = (unsigned)enable & ((1u << NPHASE) - 1u);
     return RLBM_OK;
 }
 
 int rlbm_kernel_times(rlbm_lattice* lat, double* ms, int64_t* counts, int n) {
     if (!lat) return fail(RLBM_EINVAL, "null lattice");
     HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
-    for (auto& e : lat->events) {
+    for (size_t j = 0; j < lat->n_events; ++j) {
+        const Timing& e = lat->events[j];
         float t = 0;
         HIP_TRY(hipEventElapsedTime(&t, e.a, e.b), "hipEventElapsedTime");
         lat->ms[e.kernel] += t;
         lat->counts[e.kernel] += 1;
-        (void)hipEventDestroy(e.a);
-        (void)hipEventDestroy(e.b);
     }
-    lat->events.clear();
+    lat->n_events = 0;
     for (int k = 0; k < n && k < NPHASE; ++k) {
         if (ms) ms[k] = lat->ms[k];
         if (counts) counts[k] = lat->counts[k];

@@ -306,8 +306,12 @@ class Lattice:
         _check(lib().rlbm_invariants(self.handle, out, n))
         return np.array(out[:])
 
-    def set_timing(self, on=True):
-        _check(lib().rlbm_set_timing(self.handle, 1 if on else 0))
+    def set_timing(self, on=True, kernels=None):
+        """HIP events around the launches of the named kernels (all when
+        `kernels` is None) while `on`."""
+        names = KERNELS if kernels is None else kernels
+        mask = sum(1 << KERNELS.index(k) for k in names) if on else 0
+        _check(lib().rlbm_set_timing(self.handle, mask))
 
     def kernel_times(self):
         ms = (c_double * len(KERNELS))()

@@ -14,7 +14,11 @@ f - sum_a f_a and is not reconstructed separately.
 Readings where the paper is silent:
   * A node touching several non-periodic faces takes the union of their
     incoming links; a node touching any wall face is a wall node (walls take
-    precedence over the inlet and the outlet).
+    precedence over the inlet and the outlet; Tamm-Mott-Smith walls over
+    bounce-back walls).
+  * The simplified inlet ("apply the local equilibria") sets every
+    population of the inlet node, incoming and outgoing, to the local
+    equilibria.
   * Aligned walls take the target temperature at the node's own x position,
     T^tgt = T_w(x) (the ramp is tanh-shaped, centred at x0, width w), and
     u^tgt = u_a^tgt = 0 (stationary impermeable wall).
@@ -117,6 +121,18 @@ def tms_wall(mech, stored, slaved, D, fa, f, g, fa_prev, f_prev, g_prev, opp,
     return fa_new, f_new, g_new
 
 
+def bounce_back_wall(D, fa, f, g, fa_prev, f_prev, g_prev, opp):
+    """Bounce-back wall (section 4.2.1, eq. bb): every incoming population of
+    every stored lattice takes the pre-advection value of the opposite
+    velocity at the same node.  No slip half-way between the interface node
+    and the wall on the momentum lattice, zero heat flux (adiabatic) on the
+    energy lattice; nothing is imposed."""
+    fa_new = np.where(D[None], fa_prev[:, opp], fa)
+    f_new = np.where(D, f_prev[opp], f)
+    g_new = np.where(D, g_prev[opp], g)
+    return fa_new, f_new, g_new
+
+
 def flux_inlet(mech, stored, slaved, D, fa, f, g, rho_in, u_in, T_in, Y_in):
     """Flux inlet (section 4.3, eqs. in_f..in_fa, inletlocRho..inletlocT,
     in_loc_*, in_tgt_*, f_inlet, g_inlet, fa_inlet)."""
@@ -133,6 +149,23 @@ def flux_inlet(mech, stored, slaved, D, fa, f, g, rho_in, u_in, T_in, Y_in):
     g_new = np.where(D, g_t + g_i - g_l, g_t + g - g_l)
     fa_new = np.where(D[None], fa_t + fa_i - fa_l, fa_t + fa - fa_l)
     return fa_new, f_new, g_new
+
+
+def flux_inlet_local(mech, stored, slaved, D, fa, f, g, rho_in, u_in, T_in, Y_in):
+    """Simplified flux inlet (section 4.3, closing remarks): the construction
+    stops at the local state of step 2 (incoming links at the inlet
+    equilibrium, eqs. inletlocRho..inletlocT) and every population of the
+    node takes the local equilibria (eqs. in_loc_f, in_loc_g, in_loc_fa), so
+    velocity and temperature keep their local values instead of u^in, T^in."""
+    n = f.shape[1]
+    ones = np.ones(n)
+    uin = np.stack([u_in * ones, 0 * ones, 0 * ones])
+    Yin = np.asarray(Y_in, dtype=np.float64)[:, None] * ones
+    f_i, g_i, fa_i = equilibria_set(mech, stored, rho_in * ones, Yin, uin, T_in * ones)
+    loc = mixed_moments(mech, stored, slaved, _mix(D, fa_i, fa), _mix(D, f_i, f),
+                        _mix(D, g_i, g), T_in * ones)
+    f_l, g_l, fa_l = equilibria_set(mech, stored, loc["rho"], loc["Y"], loc["u"], loc["T"])
+    return fa_l, f_l, g_l
 
 
 def lodi_outlet_state(mech, prev, inner, P_inf, sigma, Lx):

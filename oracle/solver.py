@@ -3,8 +3,9 @@
 Per step (dt = dx = 1, lattice units, T in kelvin):
 
  1. Advection of every stored lattice (eq. advection); periodic faces wrap.
- 2. Boundary reconstruction at interface nodes (section 4): walls, inlet,
-    outlet, on disjoint node sets.
+ 2. Boundary reconstruction at interface nodes (section 4): Tamm-Mott-Smith
+    walls, bounce-back walls, inlet (full or simplified), outlet, on
+    disjoint node sets.
  3. Moments: rho, u (f lattice), rho_a, u_a (species; the slaved species by
     difference, eq. strongest), rho E (g lattice), P = sum f c c, q = sum g c;
     T from eq. temperature.
@@ -89,23 +90,28 @@ class Oracle:
                 D[i] |= (src < 0) | (src >= n_ax[ax])
         self.D = D
         wall = np.zeros(self.N, dtype=bool)
+        bb = np.zeros(self.N, dtype=bool)
         inlet = np.zeros(self.N, dtype=bool)
         outlet = np.zeros(self.N, dtype=bool)
         for k, name in enumerate(FACES):
             t = types[k]
             if t == "wall":
                 wall |= on[name]
-            elif t == "inlet":
+            elif t == "bounceback":
+                bb |= on[name]
+            elif t in ("inlet", "inlet_local"):
                 inlet |= on[name]
             elif t == "outlet":
                 outlet |= on[name]
-        inlet &= ~wall
-        outlet &= ~wall
+        bb &= ~wall
+        inlet &= ~(wall | bb)
+        outlet &= ~(wall | bb)
         self.wall_nodes = np.nonzero(wall)[0]
+        self.bb_nodes = np.nonzero(bb)[0]
         self.inlet_nodes = np.nonzero(inlet)[0]
         self.outlet_nodes = np.nonzero(outlet)[0]
         for name, t in zip(FACES, types):
-            if t == "inlet" and name != "x-":
+            if t in ("inlet", "inlet_local") and name != "x-":
                 raise ValueError("inlets are supported on the x- face only")
             if t == "outlet" and name != "x+":
                 raise ValueError("outlets are supported on the x+ face only")
@@ -133,7 +139,7 @@ class Oracle:
             self.nbr[i] = (q[2] * ny + q[1]) * nx + q[0]
         # outlet: first interior neighbour along -x
         self.outlet_inner = self.outlet_nodes - 1
-        self.inlet_face = self.faces[0] if types[0] == "inlet" else None
+        self.inlet_face = self.faces[0] if types[0] in ("inlet", "inlet_local") else None
         self.outlet_face = self.faces[1] if types[1] == "outlet" else None
 
     # ------------------------------------------------------------------
@@ -211,11 +217,17 @@ class Oracle:
                             fa_prev[:, :, w], f_prev[:, w], g_prev[:, w], OPP,
                             self.T_wall)
             fa[:, :, w], f[:, w], g[:, w] = r
+        b = self.bb_nodes
+        if b.size:
+            r = bc.bounce_back_wall(self.D[:, b], fa[:, :, b], f[:, b], g[:, b],
+                                    fa_prev[:, :, b], f_prev[:, b], g_prev[:, b], OPP)
+            fa[:, :, b], f[:, b], g[:, b] = r
         k = self.inlet_nodes
         if k.size:
             fi = self.inlet_face
-            r = bc.flux_inlet(mech, stored, s, self.D[:, k], fa[:, :, k], f[:, k],
-                              g[:, k], fi["rho"], fi["u"], fi["T"], fi["Y"])
+            inlet = bc.flux_inlet_local if fi["type"] == "inlet_local" else bc.flux_inlet
+            r = inlet(mech, stored, s, self.D[:, k], fa[:, :, k], f[:, k],
+                      g[:, k], fi["rho"], fi["u"], fi["T"], fi["Y"])
             fa[:, :, k], f[:, k], g[:, k] = r
         o = self.outlet_nodes
         if o.size:

@@ -429,7 +429,8 @@ def make_case(name: str, seed: int = 0, **kw):
 
     Names: 'abc_box' (32x8x8 periodic, 3 species), 'reactor' (homogeneous
     periodic box), 'channel2d' (1024x64x1), 'channel3d' (512x64x64), 'tube'
-    (Lx1x1 flame tube), 'binary' (two-species periodic box), plus keyword
+    (Lx1x1 flame tube), 'binary' (two-species periodic box), 'bbbox' (duct
+    with bounce-back walls), plus keyword
     overrides nx, ny, nz, storage ('f64' | 'f32dev'), substeps, steps."""
     builders = {
         "abc_box": _case_abc_box,
@@ -438,6 +439,7 @@ def make_case(name: str, seed: int = 0, **kw):
         "channel3d": _case_channel3d,
         "tube": _case_tube,
         "binary": _case_binary,
+        "bbbox": _case_bbbox,
     }
     case = builders[name](seed=seed, **kw)
     case.setdefault("storage", kw.get("storage", "f64"))
@@ -496,7 +498,7 @@ def _premix_Y(mech, X_fuel=0.1, X_inert=0.7):
 
 
 def _channel(mech, nx, ny, nz, u_ms, T_in, T_wall_hi, walls_y, walls_z,
-             perturb, rng, X_fuel=0.1):
+             perturb, rng, X_fuel=0.1, inlet="inlet"):
     N = nx * ny * nz
     units = mech["units"]
     u_in = u_ms / units["c_unit"]
@@ -512,7 +514,7 @@ def _channel(mech, nx, ny, nz, u_ms, T_in, T_wall_hi, walls_y, walls_z,
         u += perturb * u_in * rng.uniform(-1.0, 1.0, size=(3, N))
     rho_in = float(_rho_from_state(mech, mech["P0"], np.array([T_in]), Yin[:, None])[0])
     faces = [
-        {"type": "inlet", "rho": rho_in, "u": u_in, "T": T_in, "Y": Yin.tolist()},
+        {"type": inlet, "rho": rho_in, "u": u_in, "T": T_in, "Y": Yin.tolist()},
         {"type": "outlet", "P_inf": mech["P0"], "sigma": 0.25},
         dict(wall) if walls_y else {"type": "periodic"},
         dict(wall) if walls_y else {"type": "periodic"},
@@ -523,10 +525,12 @@ def _channel(mech, nx, ny, nz, u_ms, T_in, T_wall_hi, walls_y, walls_z,
 
 
 def _case_channel2d(seed=0, nx=1024, ny=64, nz=1, steps=5000, substeps=2, mech=None,
-                    u_ms=0.5, **kw):
+                    u_ms=0.5, inlet="inlet", **kw):
+    """inlet: 'inlet' (velocity and temperature imposed) or 'inlet_local'
+    (the simplified flux inlet that keeps the local values)."""
     mech = mech or mechanism_h2air9(substeps=substeps)
     faces, init = _channel(mech, nx, ny, nz, u_ms, 300.0, 1300.0, True, False, 0.0,
-                           _rng(20, seed))
+                           _rng(20, seed), inlet=inlet)
     return {"mech": mech, "nx": nx, "ny": ny, "nz": nz, "faces": faces,
             "substeps": substeps, "slaved": _slaved_auto(init["Y"]), "steps": steps,
             "init": init}
@@ -540,6 +544,34 @@ def _case_channel3d(seed=0, nx=512, ny=64, nz=64, steps=2000, substeps=2, mech=N
     return {"mech": mech, "nx": nx, "ny": ny, "nz": nz, "faces": faces,
             "substeps": substeps, "slaved": _slaved_auto(init["Y"]), "steps": steps,
             "init": init}
+
+
+def _case_bbbox(seed=0, nx=16, ny=8, nz=6, steps=200, substeps=2, mech=None,
+                perturb=True, **kw):
+    """Closed duct: periodic along x, adiabatic bounce-back walls on the four
+    y and z faces; the lean premix with seeded sinusoidal composition and
+    temperature modes along x and seeded velocity noise (perturb=False: a
+    uniform mixture at rest at 1200 K)."""
+    mech = mech or mechanism_h2air9(substeps=substeps)
+    rng = _rng(60, seed)
+    N = nx * ny * nz
+    x, _, _ = _coords(nx, ny, nz)
+    Y = np.repeat(_premix_Y(mech)[:, None], N, axis=1)
+    T = np.full(N, 1200.0)
+    u = np.zeros((3, N))
+    if perturb:
+        ph = rng.uniform(0, 2 * np.pi, 2)
+        Y[FUEL9] *= 1.0 + 0.2 * np.sin(2 * np.pi * x / nx + ph[0])
+        Y[INERT9] = 0.0
+        Y[INERT9] = 1.0 - Y.sum(axis=0)
+        T = 1200.0 * (1.0 + 0.1 * np.sin(2 * np.pi * x / nx + ph[1]))
+        u = 1e-3 * rng.uniform(-1.0, 1.0, size=(3, N))
+    rho = _rho_from_state(mech, mech["P0"], T, Y)
+    bb = {"type": "bounceback"}
+    faces = [{"type": "periodic"}, {"type": "periodic"}, dict(bb), dict(bb), dict(bb), dict(bb)]
+    return {"mech": mech, "nx": nx, "ny": ny, "nz": nz, "faces": faces,
+            "substeps": substeps, "slaved": _slaved_auto(Y), "steps": steps,
+            "init": {"rho": rho, "u": u, "T": T, "Y": Y}}
 
 
 def _case_tube(seed=0, nx=None, steps=10000, substeps=2, mech=None, **kw):

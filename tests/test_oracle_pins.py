@@ -402,6 +402,76 @@ def test_closed_tms_box_conserves_mass():
         assert abs(inv1[k] - inv0[k]) <= 1e-13 * abs(inv0[k])
 
 
+def test_bounce_back_box_conserves_mass_energy_and_elements(mech9):
+    """Bounce-back (section 4.2.1, eq. bb) hands every post-collision
+    population that would leave the domain back to its own node: a duct
+    closed by bounce-back walls keeps its total mass, its total energy
+    (adiabatic walls) and its element totals while it reacts and diffuses."""
+    case = wl.make_case("bbbox", mech=mech9)
+    o = Oracle(case)
+    inv0 = o.invariants()
+    o.step(40)
+    inv1 = o.invariants()
+    fl = o.fields()
+    assert np.abs(fl["u"]).max() > 0          # the flow is not trivial
+    for k in [0, 4] + list(range(5, 5 + len(mech9["elements"]))):
+        assert abs(inv1[k] - inv0[k]) <= 1e-13 * abs(inv0[k]), k
+    assert inv1[-1] == 0.0
+
+
+def test_bounce_back_box_at_rest_is_a_periodic_reactor(mech9):
+    """At rest the equilibria are symmetric in c, so bounce-back returns
+    exactly what the opposite neighbour of a periodic box would send: a
+    uniform mixture at rest in the bounce-back duct evolves node for node as
+    the same mixture in a periodic box (a homogeneous reactor)."""
+    a = Oracle(wl.make_case("bbbox", mech=mech9, nx=6, ny=5, nz=4, perturb=False))
+    b = Oracle(wl.make_case("reactor", mech=mech9, nx=6, ny=5, nz=4, T0=1200.0))
+    a.step(10)
+    b.step(10)
+    fa, fb = a.fields(), b.fields()
+    assert abs(fa["T"].mean() - 1200.0) > 1e-7   # the mixture reacts
+    np.testing.assert_allclose(fa["T"], fb["T"], rtol=1e-13)
+    np.testing.assert_allclose(fa["Y"], fb["Y"], rtol=1e-12, atol=1e-18)
+    np.testing.assert_allclose(fa["rho"], fb["rho"], rtol=1e-13)
+    assert np.abs(fa["u"]).max() < 1e-15
+
+
+def test_simplified_inlet_keeps_the_local_state(mech9):
+    """The simplified flux inlet (section 4.3, closing remarks) leaves the
+    node at the local equilibria of step 2: its populations are an
+    equilibrium of their own moments, those moments are the local state of
+    the mixed set (incoming links at the inlet equilibrium), and the velocity
+    is not the imposed u^in."""
+    from oracle import boundary as bc
+    from oracle.lattice import C as Cq
+    case = wl.make_case("channel2d", nx=24, ny=8, mech=mech9, inlet="inlet_local")
+    o = Oracle(case)
+    o.step(3)
+    k = o.inlet_nodes
+    D = o.D[:, k]
+    fa, f, g = o.fa[:, :, k], o.f[:, k], o.g[:, k]
+    fi = o.inlet_face
+    fa_n, f_n, g_n = bc.flux_inlet_local(mech9, o.stored, o.s, D, fa, f, g,
+                                         fi["rho"], fi["u"], fi["T"], fi["Y"])
+    mo = bc.mixed_moments(mech9, o.stored, o.s, fa_n, f_n, g_n, np.full(k.size, fi["T"]))
+    f_e, g_e, fa_e = bc.equilibria_set(mech9, o.stored, mo["rho"], mo["Y"], mo["u"], mo["T"])
+    np.testing.assert_allclose(f_n, f_e, rtol=1e-12, atol=1e-16)
+    np.testing.assert_allclose(g_n, g_e, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(fa_n, fa_e, rtol=1e-12, atol=1e-16)
+    # the local state: incoming links at the inlet equilibrium, the rest as given
+    ones = np.ones(k.size)
+    uin = np.stack([fi["u"] * ones, 0 * ones, 0 * ones])
+    Yin = np.asarray(fi["Y"])[:, None] * ones
+    f_i = mixture_eq(fi["rho"] * ones, uin, (Yin / np.asarray(mech9["molar_mass"])[:, None]).sum(axis=0)
+                     * mech9["R_univ"] * fi["T"])
+    f_mix = np.where(D, f_i, f)
+    rho_loc = f_mix.sum(axis=0)
+    u_loc = np.stack([(f_mix * Cq[:, d][:, None]).sum(axis=0) for d in range(3)]) / rho_loc
+    np.testing.assert_allclose(mo["rho"], rho_loc, rtol=1e-13)
+    np.testing.assert_allclose(mo["u"], u_loc, rtol=1e-10, atol=1e-17)
+    assert np.abs(mo["u"][0] - fi["u"]).max() > 1e-3 * abs(fi["u"])
+
+
 def test_boundary_post_conditions(mech9):
     """After the boundary step the interface nodes carry the imposed values:
     TMS walls u = 0 and T = T_w(x) (section 4.2.2), the inlet u = u^in and

@@ -97,6 +97,10 @@ typedef struct rlbm_lattice rlbm_lattice;
 #define RLBM_FACE_WALL 1      /* Tamm-Mott-Smith isothermal no-slip wall (section 4.2.2) */
 #define RLBM_FACE_INLET 2     /* flux inlet (section 4.3); x- face only */
 #define RLBM_FACE_OUTLET 3    /* LODI + convective outlet (section 4.4); x+ face only */
+#define RLBM_FACE_BOUNCEBACK 4   /* bounce-back wall (section 4.2.1, eq. bb): no slip half-way, adiabatic */
+#define RLBM_FACE_INLET_LOCAL 5  /* simplified flux inlet (end of section 4.3): the node takes the local
+                                    equilibria, u and T are not imposed; x- face only, same data as
+                                    RLBM_FACE_INLET */
 
 /* One face of the box.  Faces are ordered x-, x+, y-, y+, z-, z+.  An axis is
  * periodic on both faces or on neither.  A node on several non-periodic faces

@@ -1133,11 +1133,14 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
     int fail = 0;
 
     // this lane's populations after advection (outgoing links); on incoming
-    // links at a wall, the bounce-back source f'_{opp(i)}(x) instead
+    // links at a wall, the bounce-back source f'_{opp(i)}(x) instead (all
+    // lattices at a bounce-back wall, species and momentum at a TMS wall)
     const bool wall = type == RLBM_FACE_WALL;
-    const int ld_off = (in && wall) ? node : off;
-    const int ld_i = (in && wall) ? Q - 1 - i : i;
-    const bool need = act && (!in || wall);       // open-face incoming links take no population
+    const bool bback = type == RLBM_FACE_BOUNCEBACK;
+    const bool bbl = in && (wall || bback);
+    const int ld_off = bbl ? node : off;
+    const int ld_i = bbl ? Q - 1 - i : i;
+    const bool need = act && (!in || wall || bback);   // open-face incoming links take no population
     const int par = (L.parity0 + t) & 1;
     const RLBM_CONST double* G = as_const(L.ref);
     // FP32 deviation storage: the advected value's reference belongs to this
@@ -1145,7 +1148,7 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
     // would pull it, the pull source x - c_i (wrapped)
     float s_ld[M + 1], s_own[M + 1];
     if constexpr (sizeof(S) == 4) {
-        const RLBM_GLOBAL float* a0 = scale_at(L, par, (in && wall) ? off : node);
+        const RLBM_GLOBAL float* a0 = scale_at(L, par, bbl ? off : node);
         const RLBM_GLOBAL float* a1 = scale_at(L, par, node);
 #pragma unroll
         for (int l = 0; l <= M; ++l) { s_ld[l] = a0[l]; s_own[l] = a1[l]; }
@@ -1170,6 +1173,9 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
         if (!in) {
             const int lg = M * Q + i;
             pg = Codec<S>::ld(src, (size_t)lg * N + off, refv(s_own, M, lg));
+        } else if (bback) {
+            const int lg = M * Q + ld_i;
+            pg = Codec<S>::ld(src, (size_t)lg * N + ld_off, refv(s_ld, M, lg));
         }
     }
     auto put = [&](int l, double val) {
@@ -1177,7 +1183,15 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
         if (act) Codec<S>::st(L.bcbuf, (size_t)li * L.n_if + k, val, refv(s_own, l, li));
     };
 
-    if (wall) {
+    if (bback) {
+        // bounce-back wall (section 4.2.1, eq. bb): incoming links take the
+        // opposite population of the same node, outgoing links keep theirs
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+            if (a != s) put(lat_of<M>(a, s), pa[a]);
+        put(M - 1, pf);
+        put(M, pg);
+    } else if (wall) {
         // Tamm-Mott-Smith wall (section 4.2.2)
         BcState<M, false> A;   // target: bounce-back rho and Y (eqs. BBrho, BBY), u^tgt = 0, T^tgt
         {
@@ -1208,6 +1222,25 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
             if (a != s) put(lat_of<M>(a, s), in ? 2.0 * eA[a] - eL[a] : eA[a] + pa[a] - eL[a]);
         put(M - 1, in ? 2.0 * fA - fL : fA + pf - fL);
         put(M, in ? 2.0 * gA - gL : gA + pg - gL);
+    } else if (type == RLBM_FACE_INLET_LOCAL) {
+        // simplified flux inlet (end of section 4.3): the local state of step 2
+        // with the incoming links at the inlet equilibrium, and every
+        // population of the node at the local equilibria (eqs. in_loc_*)
+        BcState<M, false> A;
+        A.rho = L.rho_in;
+        A.u[0] = L.u_in; A.u[1] = 0.0; A.u[2] = 0.0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) A.Y[a] = L.Y_in[a];
+        bc_prepare<M, false>(mc, A, L.T_in);
+        BcState<M, false> Lc;
+        bc_local<M, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
+        double eL[M], fL, gL;
+        bc_eq<M, false>(mc, Lc, c0, c1, c2, eL, fL, gL);
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+            if (a != s) put(lat_of<M>(a, s), eL[a]);
+        put(M - 1, fL);
+        put(M, gL);
     } else if (type == RLBM_FACE_INLET) {
         // flux inlet (section 4.3)
         BcState<M, false> A;   // inlet equilibrium (eqs. in_f, in_g, in_fa)

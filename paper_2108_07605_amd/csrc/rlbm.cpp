@@ -54,7 +54,8 @@ struct Geometry {
     int n_out = 0;
 };
 
-bool face_valid(int t) { return t >= RLBM_FACE_PERIODIC && t <= RLBM_FACE_OUTLET; }
+bool face_valid(int t) { return t >= RLBM_FACE_PERIODIC && t <= RLBM_FACE_INLET_LOCAL; }
+bool is_inlet(int t) { return t == RLBM_FACE_INLET || t == RLBM_FACE_INLET_LOCAL; }
 
 int validate_desc(const rlbm_lattice_desc* d, int M) {
     if (!d) return fail(RLBM_EINVAL, "null lattice descriptor");
@@ -75,7 +76,7 @@ int validate_desc(const rlbm_lattice_desc* d, int M) {
     }
     for (int f = 0; f < 6; ++f) {
         const rlbm_face& fc = d->faces[f];
-        if (fc.type == RLBM_FACE_INLET) {
+        if (is_inlet(fc.type)) {
             if (f != 0) return fail(RLBM_EUNSUP, "inlets are supported on the x- face only");
             if (!(fc.rho_in > 0) || !(fc.T_in > 0) || !fc.Y_in)
                 return fail(RLBM_EINVAL, "inlet needs rho_in > 0, T_in > 0 and Y_in");
@@ -148,7 +149,10 @@ void build_geometry(const rlbm_lattice_desc* d, Geometry& g) {
                         Tw = fc.T_lo + (fc.T_hi - fc.T_lo) * 0.5 * (1.0 + std::tanh((x - fc.x0) / fc.width));
                     }
                 }
-                if (type == 0 && on[0] && d->faces[0].type == RLBM_FACE_INLET) type = RLBM_FACE_INLET;
+                // bounce-back walls after Tamm-Mott-Smith walls, before inlet and outlet
+                for (int q = 0; q < 6 && type == 0; ++q)
+                    if (on[prio[q]] && d->faces[prio[q]].type == RLBM_FACE_BOUNCEBACK) type = RLBM_FACE_BOUNCEBACK;
+                if (type == 0 && on[0] && is_inlet(d->faces[0].type)) type = d->faces[0].type;
                 if (type == 0 && on[1] && d->faces[1].type == RLBM_FACE_OUTLET) type = RLBM_FACE_OUTLET;
                 if (type == 0) continue;   // cannot happen: every non-periodic face has a type
                 const long long node = ((long long)z * ny + y) * nx + x;
@@ -408,7 +412,7 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     h.rscale[0] = d->storage == RLBM_STORAGE_F32_DEV ? (float*)(base + p.off_rscale0) : nullptr;
     h.rscale[1] = d->storage == RLBM_STORAGE_F32_DEV ? (float*)(base + p.off_rscale1) : nullptr;
     const rlbm_face& fi = d->faces[0];
-    if (fi.type == RLBM_FACE_INLET) {
+    if (is_inlet(fi.type)) {
         h.rho_in = fi.rho_in; h.u_in = fi.u_in; h.T_in = fi.T_in;
         for (int a = 0; a < M; ++a) h.Y_in[a] = fi.Y_in[a];
     }
@@ -445,7 +449,7 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
         UP(base + p.off_ifout, g.if_out.data(), nif * sizeof(int));
     }
 #undef UP
-    if (fi.type == RLBM_FACE_INLET) lat->Y_in.assign(fi.Y_in, fi.Y_in + M);
+    if (is_inlet(fi.type)) lat->Y_in.assign(fi.Y_in, fi.Y_in + M);
     *out = lat;
     return RLBM_OK;
 }

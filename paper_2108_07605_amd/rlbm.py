@@ -16,10 +16,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librlbm.so")
 
-FACE_PERIODIC, FACE_WALL, FACE_INLET, FACE_OUTLET = 0, 1, 2, 3
+FACE_PERIODIC, FACE_WALL, FACE_INLET, FACE_OUTLET, FACE_BOUNCEBACK, FACE_INLET_LOCAL = 0, 1, 2, 3, 4, 5
 STORAGE_F64, STORAGE_F32_DEV = 0, 1
 _FACE_CODES = {"periodic": FACE_PERIODIC, "wall": FACE_WALL, "inlet": FACE_INLET,
-               "outlet": FACE_OUTLET}
+               "outlet": FACE_OUTLET, "bounceback": FACE_BOUNCEBACK, "inlet_local": FACE_INLET_LOCAL}
 _STORAGE = {"f64": STORAGE_F64, "f32dev": STORAGE_F32_DEV}
 # kernels of one step, in launch order (rlbm_kernel_times)
 KERNELS = ("boundary", "local", "chem", "update")
@@ -187,7 +187,7 @@ def lattice_desc(case, storage="f64"):
         fc.type = _FACE_CODES[f["type"]]
         if f["type"] == "wall":
             fc.T_lo, fc.T_hi, fc.x0, fc.width = f["T_lo"], f["T_hi"], f["x0"], f["width"]
-        elif f["type"] == "inlet":
+        elif f["type"] in ("inlet", "inlet_local"):
             y = np.ascontiguousarray(f["Y"], dtype=np.float64)
             keep.append(y)
             fc.rho_in, fc.u_in, fc.T_in = f["rho"], f["u"], f["T"]

@@ -207,6 +207,34 @@ def _field_errors(a, b, u_floor, dims):
             "Y_worst_species": kw, "Y_worst_node": xyz(n), "T_worst_node": xyz(nT)}
 
 
+def _bench_substeps(args):
+    """Cost of the reaction sub-steps (eq. R3): the 512x64x64 channel in
+    FP32-deviation storage with l = 1, 2, 4 forward-Euler sub-steps and one
+    mechanism (screened for l = 1), step time relative to l = 1.  The paper
+    reports about +6 % (l = 2) and +15 % (l = 4) for its CPU solver."""
+    from paper_2108_07605_amd import workloads as wl
+    mech = wl.mechanism_h2air9(substeps=1)
+    rows = {}
+    for l in (1, 2, 4):
+        case = wl.make_case("channel3d", nx=args.nx, ny=args.ny, nz=args.nz, mech=mech, substeps=l)
+        r = _time_storage(case, "f32dev", args.steps, args.warmup)
+        ms = r["ms_total"] / args.steps
+        rows[l] = {"ms_per_step": ms,
+                   "chem_ms": r["kernels"]["chem"][0] / max(r["kernels"]["chem"][1], 1),
+                   "finite": r["finite"]}
+    N = args.nx * args.ny * args.nz
+    for l in rows:
+        rows[l]["increase_vs_l1"] = rows[l]["ms_per_step"] / rows[1]["ms_per_step"] - 1.0
+        rows[l]["mlups"] = N / (rows[l]["ms_per_step"] * 1e-3) / 1e6
+    return {"metric": "step time vs reaction sub-steps l", "value": rows[4]["increase_vs_l1"],
+            "unit": "fraction (l=4 over l=1)", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": False, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"channel3d {args.nx}x{args.ny}x{args.nz}, 9 species, f32dev storage"},
+            "substeps": rows,
+            "paper_cpu_increase": {"2": 0.06, "4": 0.15}}
+
+
 def _bench_precision(args):
     """FP32-deviation storage against FP64 storage from the same initial
     state: the 512x64x64 channel after --steps steps (2000 in the recipe) and
@@ -287,11 +315,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--storage", default="both", choices=["both", "f32dev", "f64"])
-    ap.add_argument("--workload", default="channel3d", choices=["channel3d", "tubes", "serve", "precision"],
+    ap.add_argument("--workload", default="channel3d",
+                    choices=["channel3d", "tubes", "serve", "precision", "substeps"],
                     help="channel3d: the 512x64x64 channel (default); tubes: 256 uneven flame "
                          "tubes in batched launches vs one lattice at a time; serve: the "
                          "continuous-batching server on a Poisson request trace; precision: "
-                         "FP32-deviation vs FP64 storage field errors after --steps steps")
+                         "FP32-deviation vs FP64 storage field errors after --steps steps; "
+                         "substeps: step time with l = 1, 2, 4 reaction sub-steps")
     ap.add_argument("--tubes", type=int, default=256)
     ap.add_argument("--seq-steps", type=int, default=20,
                     help="steps of the one-lattice-at-a-time comparison (tubes)")
@@ -320,6 +350,9 @@ def main():
         return
     if args.workload == "precision":
         print(json.dumps(_bench_precision(args)))
+        return
+    if args.workload == "substeps":
+        print(json.dumps(_bench_substeps(args)))
         return
     case = wl.make_case("channel3d", nx=args.nx, ny=args.ny, nz=args.nz)
     N = case["nx"] * case["ny"] * case["nz"]

@@ -163,6 +163,25 @@ void build_geometry(const rlbm_lattice_desc* d, Geometry& g) {
                 g.if_T.push_back(Tw);
                 g.if_out.push_back(type == RLBM_FACE_OUTLET ? g.n_out++ : -1);
             }
+    // group the interface nodes by boundary type (stable): the boundary
+    // kernel's waves then hold nodes of one type and take one branch
+    const size_t nif = g.if_node.size();
+    std::vector<size_t> ord(nif);
+    for (size_t j = 0; j < nif; ++j) ord[j] = j;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return g.if_type[a] < g.if_type[b]; });
+    Geometry s;
+    s.N = g.N;
+    s.if_index.assign(g.if_index.size(), -1);
+    for (size_t j = 0; j < nif; ++j) {
+        const size_t o = ord[j];
+        s.if_index[g.if_node[o]] = (int)j;
+        s.if_node.push_back(g.if_node[o]);
+        s.if_mask.push_back(g.if_mask[o]);
+        s.if_type.push_back(g.if_type[o]);
+        s.if_T.push_back(g.if_T[o]);
+        s.if_out.push_back(g.if_type[o] == RLBM_FACE_OUTLET ? s.n_out++ : -1);
+    }
+    g = std::move(s);
 }
 
 Plan make_plan(const rlbm_lattice_desc* d, int M, int E, const Geometry& g) {

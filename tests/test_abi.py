@@ -76,6 +76,8 @@ def test_lattice_bytes_plan(mech9):
     (lambda c: c["faces"].__setitem__(3, {"type": "periodic"}), -1),   # y axis half periodic
     (lambda c: c["faces"].__setitem__(0, {"type": "outlet", "P_inf": 1.0, "sigma": 0.25}), -4),
     (lambda c: c.__setitem__("substeps", 0), -1),
+    (lambda c: c["faces"].__setitem__(1, dict(c["faces"][0], type="inlet_local")), -4),   # inlet on x+
+    (lambda c: c.__setitem__("nx", 2 ** 27), -4),                         # 9 N s beyond 2^32
     (lambda c: c.__setitem__("nx", 0), -1),
 ])
 def test_lattice_descriptor_validation(mech9, mutate, code):
@@ -85,6 +87,18 @@ def test_lattice_descriptor_validation(mech9, mutate, code):
     with pytest.raises(rlbm.RlbmError) as e:
         rlbm.lattice_bytes(case, m, "f64")
     assert e.value.code == code
+
+
+def test_boundary_variants_accepted(mech9):
+    """Bounce-back walls and the simplified inlet are valid descriptors; a
+    bounce-back x- face with an outlet on x+ is a valid channel end."""
+    m = rlbm.Mechanism(mech9)
+    for case in (wl.make_case("bbbox", mech=mech9),
+                 wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9, inlet="inlet_local")):
+        assert rlbm.lattice_bytes(case, m, "f64") > 0
+    case = wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9)
+    case["faces"][0] = {"type": "bounceback"}
+    assert rlbm.lattice_bytes(case, m, "f32dev") > 0
 
 
 def test_inlet_composition_must_sum_to_one(mech9):

@@ -24,6 +24,16 @@ __host__ __device__ constexpr int c2_of(int i) {
     return cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_of(i) * cz_of(i);
 }
 
+// One reaction: Arrhenius parameters, reversibility, each side as a list of
+// factors (its species in ascending order, each repeated by its coefficient:
+// the mass-action product) and the net coefficients nu'' - nu'.
+struct RxnDev {
+    double lnA, beta, Ta, dnu_sum;
+    int rev, nf, nr, pad_;
+    int fac_f[MAXO], fac_r[MAXO];
+    double dnu[MAXM];
+};
+
 // Mechanism in the layout the kernels read (uniform addresses: scalar loads).
 struct MechDev {
     int M, R, E, pad_;
@@ -35,15 +45,8 @@ struct MechDev {
     double hc[MAXM][6];         // H_a(T) = sum_k hc[a][k] T^k
     double nasa[MAXM][7];       // raw NASA-7 coefficients (Gibbs functions)
     double R_univ, ln_cstd;
-    // reactions
-    double lnA[MAXR], beta[MAXR], Ta[MAXR], dnu_sum[MAXR];
-    int rev[MAXR];
-    int8_t nu_f[MAXR][MAXM], nu_r[MAXR][MAXM];
-    double dnu[MAXR][MAXM];
-    // each side of a reaction as a list of factors: its species in ascending
-    // order, each repeated by its coefficient (mass-action products)
-    int nfac_f[MAXR], nfac_r[MAXR];
-    int fac_f[MAXR][MAXO], fac_r[MAXR][MAXO];
+    // reactions, one contiguous record each (one scalar base per reaction)
+    RxnDev rx[MAXR];
     // transport
     double T_ref, inv_T_ref, P_ref, inv_P_ref, mu_ref, mu_exp, inv_Pr, D_exp;
     double Kab[MAXM][MAXM];     // 1 / (D_ref[a][b] m_a m_b)
@@ -266,31 +269,32 @@ __device__ __forceinline__ void production_rates(MechC mc0, const double* rho_a,
     const double lnc = mc.ln_cstd - lnT;
     for (int r = 0; r < R; ++r) {
         MechC mc = in_loop(mc0);
-        const int nf = mc.nfac_f[r], nr = mc.nfac_r[r];
-        const double lnkf = mc.lnA[r] + mc.beta[r] * lnT - mc.Ta[r] * invT;
+        const RLBM_CONST RxnDev& x = mc.rx[r];
+        const int nf = x.nf, nr = x.nr;
+        const double lnkf = x.lnA + x.beta * lnT - x.Ta * invT;
         // forward rate k_f prod_b c_b^nu'_b
         double fwd = exp(lnkf);
 #pragma unroll
         for (int f = 0; f < MAXO; ++f)
-            if (f < nf) fwd *= ls.c[mc.fac_f[r][f] * NT];
+            if (f < nf) fwd *= ls.c[x.fac_f[f] * NT];
         double q = fwd;
-        if (mc.rev[r]) {
+        if (x.rev) {
             // k_r = k_f / K_c, ln K_c = -sum_a dnu_a g_a/(R T) + (sum_a dnu_a) ln c_std
             double sg = 0.0;
 #pragma unroll
             for (int f = 0; f < MAXO; ++f)
-                if (f < nr) sg += ls.g[mc.fac_r[r][f] * NT];
+                if (f < nr) sg += ls.g[x.fac_r[f] * NT];
 #pragma unroll
             for (int f = 0; f < MAXO; ++f)
-                if (f < nf) sg -= ls.g[mc.fac_f[r][f] * NT];
-            double bwd = exp(lnkf + sg - mc.dnu_sum[r] * lnc);
+                if (f < nf) sg -= ls.g[x.fac_f[f] * NT];
+            double bwd = exp(lnkf + sg - x.dnu_sum * lnc);
 #pragma unroll
             for (int f = 0; f < MAXO; ++f)
-                if (f < nr) bwd *= ls.c[mc.fac_r[r][f] * NT];
+                if (f < nr) bwd *= ls.c[x.fac_r[f] * NT];
             q -= bwd;
         }
 #pragma unroll
-        for (int a = 0; a < M; ++a) wdot[a] = fma(mc.dnu[r][a], q, wdot[a]);
+        for (int a = 0; a < M; ++a) wdot[a] = fma(x.dnu[a], q, wdot[a]);
     }
 #pragma unroll
     for (int a = 0; a < M; ++a) wdot[a] *= mc.m[a];

@@ -322,10 +322,11 @@ int rlbm_mech_create(const rlbm_mech_desc* d, rlbm_mech** out) {
         for (int e = 0; e < E; ++e) md.comp[a][e] = (double)d->composition[a * E + e];
     }
     for (int r = 0; r < R; ++r) {
-        md.lnA[r] = d->lnA[r];
-        md.beta[r] = d->beta[r];
-        md.Ta[r] = d->Ta[r];
-        md.rev[r] = d->reversible[r] ? 1 : 0;
+        RxnDev& x = md.rx[r];
+        x.lnA = d->lnA[r];
+        x.beta = d->beta[r];
+        x.Ta = d->Ta[r];
+        x.rev = d->reversible[r] ? 1 : 0;
         double s = 0;
         for (int a = 0; a < M; ++a) {
             const int f = d->nu_f[r * M + a], b = d->nu_r[r * M + a];
@@ -333,18 +334,16 @@ int rlbm_mech_create(const rlbm_mech_desc* d, rlbm_mech** out) {
                 delete m;
                 return fail(RLBM_EUNSUP, "stoichiometric coefficients must be 0..3");
             }
-            md.nu_f[r][a] = (int8_t)f;
-            md.nu_r[r][a] = (int8_t)b;
-            md.dnu[r][a] = (double)(b - f);
+            x.dnu[a] = (double)(b - f);
             s += (double)(b - f);
-            if (md.nfac_f[r] + f > RLBM_MAX_ORDER || md.nfac_r[r] + b > RLBM_MAX_ORDER) {
+            if (x.nf + f > RLBM_MAX_ORDER || x.nr + b > RLBM_MAX_ORDER) {
                 delete m;
                 return fail(RLBM_EUNSUP, "more than RLBM_MAX_ORDER molecules on one side of a reaction");
             }
-            for (int k = 0; k < f; ++k) md.fac_f[r][md.nfac_f[r]++] = a;
-            for (int k = 0; k < b; ++k) md.fac_r[r][md.nfac_r[r]++] = a;
+            for (int k = 0; k < f; ++k) x.fac_f[x.nf++] = a;
+            for (int k = 0; k < b; ++k) x.fac_r[x.nr++] = a;
         }
-        md.dnu_sum[r] = s;
+        x.dnu_sum = s;
     }
     md.T_ref = d->T_ref;
     md.inv_T_ref = 1.0 / d->T_ref;

@@ -16,7 +16,8 @@ Per step (dt = dx = 1, lattice units, T in kelvin):
     beyond a non-periodic face repeat the nearest in-domain node).
  5. Relaxation parameters and the Stefan-Maxwell system (eq. transform1),
     solved for each Cartesian component.
- 6. Reaction increment by l explicit sub-steps (eq. R3).
+ 6. Reaction increment by l sub-steps (eq. R3), forward Euler or the
+    linearly implicit variant.
  7. Species collision (eq. finalNumericalEquationsReactive with eqs. fStar,
     xiPstar2, and eq. R3 read with rho_a^{-1} f_ai^eq, since with the printed
     rho^{-1} the source would not carry mass rho_dot_a as eq. Dotfr requires).
@@ -55,6 +56,7 @@ class Oracle:
         self.N = self.nx * self.ny * self.nz
         self.faces = case["faces"]
         self.l = int(case.get("substeps", 2))
+        self.reaction = case.get("reaction", "explicit")
         self.s = int(case["slaved"])
         self.stored = [a for a in range(self.M) if a != self.s]
         self._geometry()
@@ -262,7 +264,7 @@ class Oracle:
         omega, omega1 = mixture_omegas(mech, T, P)
         V = stefan_maxwell(Y, itab, inv_tau, u_a, u)
         # 6. reactions
-        drho = reaction_increment(mech, rho_a, rho, U, T, l)
+        drho = reaction_increment(mech, rho_a, rho, U, T, l, self.reaction)
         # 7. species collision
         Wsp = [species_W(u, Ra[b] * T) for b in range(M)]
         feq_b = [rho_a[b] * Wsp[b] for b in range(M)]

@@ -10,9 +10,10 @@ import math
 import numpy as np
 import pytest
 from scipy import integrate
+from scipy.integrate import solve_ivp
 
 from oracle import Oracle
-from oracle.chemistry import production_rates
+from oracle.chemistry import production_rates, rate_jacobian, reaction_increment
 from oracle.equilibria import (energy_eq, energy_quasi_eq, extended_eq,
                                mixture_eq, species_W, species_eq)
 from oracle.lattice import C, OPP, Q, W
@@ -295,6 +296,147 @@ def test_homogeneous_reactor_second_order_kinetics(l):
     assert errs[0] < 0.05
     # first order in the sub-step size
     assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3, errs
+
+
+# --------------------------------------------------------------------------
+# linearly implicit reaction sub-steps (stiff-stable variant of eq. R3)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["abc", "h2air9"])
+def test_rate_jacobian_matches_central_differences(which, mech_abc, mech9):
+    mech = mech_abc if which == "abc" else mech9
+    rho_a, T = _random_state(mech, 6)
+    J = rate_jacobian(mech, rho_a, T)
+    M = mech["M"]
+    for b in range(M):
+        h = 1e-5 * rho_a[b]
+        up, dn = rho_a.copy(), rho_a.copy()
+        up[b] += h
+        dn[b] -= h
+        fd = (production_rates(mech, up, T) - production_rates(mech, dn, T)) / (2 * h)
+        scale = np.abs(J).max(axis=(0, 1)) + 1e-300
+        assert (np.abs(fd - J[:, b]) <= 1e-6 * scale).all(), (b, np.abs(fd - J[:, b]).max(), scale)
+    # columns sum to zero (mass) and carry no element change
+    assert (np.abs(J.sum(axis=0)) <= 1e-12 * np.abs(J).max(axis=(0, 1))).all()
+    comp = np.asarray(mech["composition"], dtype=float)
+    m = np.asarray(mech["molar_mass"])
+    elem = np.einsum("abn,ae->ben", J, comp / m[:, None])
+    assert (np.abs(elem) <= 1e-12 * (np.abs(J).max(axis=(0, 1)) / m.min())).all()
+
+
+def _iso_pair(nu_f, nu_r, masses, k, reversible):
+    """Three species with identical per-mass thermo (so T never moves), one
+    reaction with the given stoichiometry, constant k (beta = Ta = 0)."""
+    mech = copy.deepcopy(_iso_abc(k, 1))
+    mech["molar_mass"] = list(masses)
+    mech["nu_f"], mech["nu_r"] = [list(nu_f)], [list(nu_r)]
+    mech["reversible"] = [int(reversible)]
+    return mech
+
+
+def _reactor_state(mech, rho_a, T=1000.0):
+    rho_a = np.asarray(rho_a, dtype=float)[:, None]
+    rho = rho_a.sum(axis=0)
+    T = np.array([T])
+    U = ((rho_a / rho) * U_species(mech, T)).sum(axis=0)
+    return rho_a, rho, U, T
+
+
+@pytest.mark.parametrize("l", [1, 2, 3])
+def test_linearly_implicit_first_order_is_backward_euler(l):
+    """A -> B with k dt^r = 40 (far beyond forward Euler's stability limit):
+    for a linear network the linearly implicit step is backward Euler, so
+    rho_A ends at rho_A0 / (1 + k/l)^l."""
+    k = 40.0
+    mech = _iso_pair([1, 0, 0], [0, 1, 0], [2.0, 2.0, 32.0], k, False)
+    rho_a, rho, U, T = _reactor_state(mech, [0.3, 0.1, 0.6])
+    d = reaction_increment(mech, rho_a, rho, U, T, l, "implicit")
+    exact_A = 0.3 / (1.0 + k / l) ** l
+    # rho_A0 + Delta cancels to ~3e-4 of rho_A0: a few ulp of rho_A0 in relative terms
+    assert math.isclose(rho_a[0, 0] + d[0, 0], exact_A, rel_tol=1e-11)
+    assert math.isclose(d[1, 0], -d[0, 0], rel_tol=1e-14) and d[2, 0] == 0.0
+    de = reaction_increment(mech, rho_a, rho, U, T, l, "explicit")
+    assert abs(rho_a[0, 0] + de[0, 0]) > 1.0          # forward Euler blows past zero
+
+
+def test_linearly_implicit_reversible_isomerisation_relaxes_to_equilibrium():
+    """A <-> B between isomers with identical thermo: K_c = 1, so k_r = k_f and
+    rho_A - rho_B decays by 1/(1 + 2 k dt^r) per sub-step (backward Euler of
+    a linear system); a very stiff step lands on the equilibrium."""
+    mech = _iso_pair([1, 0, 0], [0, 1, 0], [2.0, 2.0, 32.0], 3.0, True)
+    mech["nasa"] = [list(mech["nasa"][0])] * 3
+    rho_a, rho, U, T = _reactor_state(mech, [0.35, 0.05, 0.6])
+    for l in (1, 2, 5):
+        d = reaction_increment(mech, rho_a, rho, U, T, l, "implicit")
+        diff = (rho_a[0, 0] + d[0, 0]) - (rho_a[1, 0] + d[1, 0])
+        assert math.isclose(diff, 0.3 / (1.0 + 2 * 3.0 / l) ** l, rel_tol=1e-12)
+        assert abs(d[0, 0] + d[1, 0]) <= 1e-16
+    mech["lnA"] = [math.log(1e9)]
+    d = reaction_increment(mech, rho_a, rho, U, T, 1, "implicit")
+    assert abs((rho_a[0, 0] + d[0, 0]) - (rho_a[1, 0] + d[1, 0])) < 1e-9
+
+
+def test_linearly_implicit_second_order_is_rosenbrock_euler():
+    """2A -> B (m_B = 2 m_A): the rate does not depend on B, so the system is
+    triangular and the A component is the scalar linearly implicit Euler step
+    c' = c + h f(c) / (1 - h f'(c)) of dc/dt = f(c) = -2 k c^2."""
+    k, l = 7.0, 2
+    mech = _iso_pair([2, 0, 0], [0, 1, 0], [2.0, 4.0, 32.0], k, False)
+    rho_a, rho, U, T = _reactor_state(mech, [0.4, 0.0, 0.6])
+    d = reaction_increment(mech, rho_a, rho, U, T, l, "implicit")
+    c, h = 0.4 / 2.0, 1.0 / l
+    for _ in range(l):
+        c = c + h * (-2 * k * c * c) / (1.0 + h * 4 * k * c)
+    assert math.isclose((rho_a[0, 0] + d[0, 0]) / 2.0, c, rel_tol=1e-13)
+    assert math.isclose(d[1, 0], -d[0, 0], rel_tol=1e-13)
+
+
+def test_linearly_implicit_conserves_mass_and_elements(mech9):
+    rho_a, T = _random_state(mech9, 16)
+    rho = rho_a.sum(axis=0)
+    U = ((rho_a / rho) * U_species(mech9, T)).sum(axis=0)
+    d = reaction_increment(mech9, rho_a, rho, U, T, 2, "implicit")
+    assert (np.abs(d).max(axis=0) > 1e-6 * rho).all()               # reactions do run
+    # Delta = rho^(l) - rho^(0): rounding is a few ulp of rho, not of Delta
+    assert (np.abs(d.sum(axis=0)) <= 1e-15 * rho).all()
+    m = np.asarray(mech9["molar_mass"])[:, None]
+    comp = np.asarray(mech9["composition"], dtype=float)
+    assert (np.abs((d / m).T @ comp) <= 1e-15 * (rho / m.min())[:, None]).all()
+
+
+def test_linearly_implicit_converges_to_the_reactor_ode(mech9):
+    """One lattice step of a zero-dimensional reactor at frozen U: the
+    linearly implicit sub-steps converge at first order in dt^r to the ODE
+    d rho_a/dt = rho_dot_a(rho, T(U, Y)) integrated by a stiff solver
+    (Radau, tight tolerances) over dt = 1, from the same start as forward
+    Euler, at 20x the seeded rates."""
+    mech = copy.deepcopy(mech9)
+    mech["lnA"] = [a + math.log(20.0) for a in mech["lnA"]]
+    rho_a, T = _random_state(mech, 2, T_lo=1200.0, T_hi=2200.0)
+    rho = rho_a.sum(axis=0)
+    U = ((rho_a / rho) * U_species(mech, T)).sum(axis=0)
+    for n in range(rho_a.shape[1]):
+        Tn = [T[n]]
+
+        def rhs(_, y):
+            Tn[0] = solve_temperature(mech, y[:, None] / rho[n], U[n:n + 1], np.array([Tn[0]]))[0]
+            return production_rates(mech, y[:, None], np.array([Tn[0]]))[:, 0]
+
+        sol = solve_ivp(rhs, (0.0, 1.0), rho_a[:, n], method="Radau", rtol=1e-11,
+                        atol=1e-14 * rho[n])
+        ref = sol.y[:, -1] - rho_a[:, n]
+        errs = []
+        for l in (8, 16, 32):
+            d = reaction_increment(mech, rho_a[:, n:n + 1], rho[n:n + 1], U[n:n + 1], T[n:n + 1], l,
+                                   "implicit")[:, 0]
+            errs.append(np.abs(d - ref).max() / np.abs(ref).max())
+        assert errs[2] < 0.05, errs
+        assert 1.6 < errs[0] / errs[1] < 2.4 and 1.6 < errs[1] / errs[2] < 2.4, errs
+
+
+def test_unknown_reaction_scheme_is_rejected(mech_abc):
+    rho_a, T = _random_state(mech_abc, 2)
+    with pytest.raises(ValueError):
+        reaction_increment(mech_abc, rho_a, rho_a.sum(axis=0), T * 0 + 1.0, T, 1, "rk4")
 
 
 # --------------------------------------------------------------------------

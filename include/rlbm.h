@@ -121,6 +121,16 @@ typedef struct rlbm_face {
     double P_inf, sigma;
 } rlbm_face;
 
+/* Reaction sub-step scheme (section 2.3, eq. R3).  EXPLICIT is the paper's
+ * forward Euler.  LINEARLY_IMPLICIT solves (I - dt^r J) Delta = dt^r rho_dot
+ * per sub-step, J = d rho_dot / d rho at the sub-step's temperature (T held
+ * fixed in J, re-solved at frozen U between sub-steps; max(c, 0) in the rates
+ * differentiated as the identity), by Gaussian elimination with partial
+ * pivoting.  It conserves mass and elements like EXPLICIT and is backward
+ * Euler for a linear network, so stiff mechanisms need fewer sub-steps. */
+#define RLBM_REACTION_EXPLICIT 0
+#define RLBM_REACTION_LINEARLY_IMPLICIT 1
+
 #define RLBM_STORAGE_F64 0        /* populations stored in FP64 */
 #define RLBM_STORAGE_F32_DEV 1    /* FP32 deviations from a per-(lattice, velocity) reference */
 
@@ -132,6 +142,7 @@ typedef struct rlbm_lattice_desc {
     int32_t substeps;             /* reaction sub-steps l >= 1 (eq. R3) */
     int32_t slaved;               /* slaved species index, or -1: chosen at rlbm_set_state as
                                      the largest domain-mean mass fraction (lowest index on ties) */
+    int32_t reaction;             /* RLBM_REACTION_* */
 } rlbm_lattice_desc;
 
 /* Create / destroy a mechanism (host object; uploaded per lattice). */

@@ -582,25 +582,28 @@ __device__ __forceinline__ void node_gradients(const LatDev& L, int node) {
 
 // ---------------------------------------------------------------------------
 // k_chem: reaction increment of every node (eq. R3), l forward-Euler
-// sub-steps at frozen specific internal energy, reading rho_a, rho, U, T from
-// the per-node record and writing Delta rho_a into it; then the node's
-// same-time gradients.  The stencil's neighbour loads are latency-bound and
-// the chemistry is arithmetic-bound, so the two share one launch.
+// sub-steps at frozen specific internal energy (IMPL: linearly implicit
+// sub-steps), reading rho_a, rho, U, T from the per-node record and writing
+// Delta rho_a into it; then the node's same-time gradients.  The stencil's
+// neighbour loads are latency-bound and the chemistry is arithmetic-bound, so
+// the two share one launch.  A launch serves the lattices of its scheme; the
+// blocks of the others return at once.
 // ---------------------------------------------------------------------------
-template <int M>
+template <int M, bool IMPL>
 __global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                               int n_lat, long long t, int* __restrict__ flag) {
     const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
     if (t >= L.t_end) return;
+    if ((L.reaction == RLBM_REACTION_LINEARLY_IMPLICIT) != IMPL) return;
     const int node = (b - blk[lj]) * 256 + threadIdx.x;
     if (node >= L.N) return;
     MechC mc = *as_const(L.mech);
     double* prm = L.prm;
     const size_t N = (size_t)L.N;
-    __shared__ double s_c[M][256], s_g[M][256];
-    const ChemLds<256> ls{&s_c[0][threadIdx.x], &s_g[0][threadIdx.x]};
+    __shared__ double s_c[M][256], s_g[M][256], s_q[IMPL ? M : 1][256];
+    const ChemLds<256> ls{&s_c[0][threadIdx.x], &s_g[0][threadIdx.x], IMPL ? &s_q[0][threadIdx.x] : nullptr};
     double rho_a[M], drho[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) rho_a[a] = prm[(PRM_SP + 6 * a) * N + node];
@@ -608,7 +611,7 @@ __global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, c
     const double U = prm[PRM_UINT * N + node];
     const double T = prm[PRM_T * N + node];
     int fail = 0;
-    reaction_increment<M, 256>(mc, rho_a, rho, U, T, L.substeps, ls, drho, &fail);
+    reaction_increment<M, 256, IMPL>(mc, rho_a, rho, U, T, L.substeps, ls, drho, &fail);
     if (fail) atomicOr(flag, 1);
 #pragma unroll
     for (int a = 0; a < M; ++a) prm[(PRM_SP + 6 * a + 5) * N + node] = drho[a];
@@ -1653,8 +1656,12 @@ static hipError_t launch_step_phase(int phase, int M, const StepLaunch& a) {
         RLBM_DISPATCH(M, hipLaunchKernelGGL((k_local<MM, S>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
                                                 a.blk, a.n_lat, a.t, a.flag))
     } else if (phase == 2) {
-        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
-                                                a.blk, a.n_lat, a.t, a.flag))
+        if (a.schemes & (1u << RLBM_REACTION_EXPLICIT))
+            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem<MM, false>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
+                                                    a.blk, a.n_lat, a.t, a.flag))
+        if (a.schemes & (1u << RLBM_REACTION_LINEARLY_IMPLICIT))
+            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem<MM, true>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
+                                                    a.blk, a.n_lat, a.t, a.flag))
     } else {
         RLBM_DISPATCH(M, hipLaunchKernelGGL((k_update<MM, S>), dim3(a.blocks), dim3(UPD_THREADS), 0, a.stream, a.lats,
                                                 a.blk, a.n_lat, a.t, a.flag))

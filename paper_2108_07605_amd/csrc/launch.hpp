@@ -16,6 +16,7 @@ struct StepLaunch {
     long long t;          // step counter of this launch series
     int* flag;            // device failure flag (temperature iteration)
     hipStream_t stream;
+    unsigned schemes;     // bit r set if a lattice uses RLBM_REACTION r (phase 2 launches one kernel per scheme)
 };
 
 // Interface nodes per boundary block (half a wave per node).

@@ -57,7 +57,7 @@ struct MechDev {
 struct LatDev {
     int nx, ny, nz, pad0;
     int per[3];                 // periodic flags per axis
-    int slaved, substeps, storage;
+    int slaved, substeps, storage, reaction;
     long long N;
     int n_if, n_out;
     const MechDev* mech;
@@ -244,19 +244,55 @@ __device__ __forceinline__ double gibbs_RT(MechC mc, int a, double T, double lnT
 // ---------------------------------------------------------------------------
 // Per-thread LDS columns: the concentrations c_a and the Gibbs functions
 // g_a/(R_univ T) of one node, at stride NT doubles between species, so a
-// reaction reads just its own factors at a wave-uniform species index.
+// reaction reads just its own factors at a wave-uniform species index.  The
+// linearly implicit update adds a third column, dq_b = d q_r / d c_b of the
+// current reaction, scattered by factor and gathered at compile-time indices.
 template <int NT>
 struct ChemLds {
     double* c;   // &c[0][tid]
     double* g;   // &g[0][tid]
+    double* dq;  // &dq[0][tid], or nullptr without the Jacobian
 };
 
-template <int M, int NT>
-__device__ __forceinline__ void production_rates(MechC mc0, const double* rho_a, double T, const ChemLds<NT>& ls,
-                                                 double* wdot) {
+// Adds k prod_{g != f} c_{fac[g]} to dq[fac[f]] for every factor f < n.
+template <int NT>
+__device__ __forceinline__ void scatter_factor_derivs(const ChemLds<NT>& ls, const RLBM_CONST int* fac, int n,
+                                                      double k) {
+    double c[MAXO];
+#pragma unroll
+    for (int f = 0; f < MAXO; ++f) c[f] = f < n ? ls.c[fac[f] * NT] : 1.0;
+    // prefix and suffix products of the factor list
+    double pre[MAXO], suf[MAXO];
+    pre[0] = k;
+#pragma unroll
+    for (int f = 1; f < MAXO; ++f) pre[f] = pre[f - 1] * c[f - 1];
+    suf[MAXO - 1] = 1.0;
+#pragma unroll
+    for (int f = MAXO - 2; f >= 0; --f) suf[f] = suf[f + 1] * c[f + 1];
+#pragma unroll
+    for (int f = 0; f < MAXO; ++f)
+        if (f < n) ls.dq[fac[f] * NT] += pre[f] * suf[f];
+}
+
+// Production rates rho_dot_a and, with JAC, the Jacobian J[a][b] =
+// d rho_dot_a / d rho_b at fixed T.  Each mass-action product is a list of
+// factors (one per molecule), so d/dc_b of the product is the sum, over the
+// factors that are species b, of the product of the other factors; the clip
+// max(c, 0) is differentiated as the identity.
+template <int M, int NT, bool JAC>
+__device__ __forceinline__ void rates_jac(MechC mc0, const double* rho_a, double T, const ChemLds<NT>& ls,
+                                          double* wdot, double (*J)[M]) {
     MechC mc = mc0;
 #pragma unroll
     for (int a = 0; a < M; ++a) wdot[a] = 0.0;
+    if constexpr (JAC) {
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            ls.dq[a * NT] = 0.0;
+#pragma unroll
+            for (int b = 0; b < M; ++b) J[a][b] = 0.0;
+        }
+    }
     const int R = mc.R;
     if (R == 0) return;
     const double lnT = log(T);
@@ -273,10 +309,12 @@ __device__ __forceinline__ void production_rates(MechC mc0, const double* rho_a,
         const int nf = x.nf, nr = x.nr;
         const double lnkf = x.lnA + x.beta * lnT - x.Ta * invT;
         // forward rate k_f prod_b c_b^nu'_b
-        double fwd = exp(lnkf);
+        const double kf = exp(lnkf);
+        double fwd = kf;
 #pragma unroll
         for (int f = 0; f < MAXO; ++f)
             if (f < nf) fwd *= ls.c[x.fac_f[f] * NT];
+        if constexpr (JAC) scatter_factor_derivs<NT>(ls, x.fac_f, nf, kf);
         double q = fwd;
         if (x.rev) {
             // k_r = k_f / K_c, ln K_c = -sum_a dnu_a g_a/(R T) + (sum_a dnu_a) ln c_std
@@ -287,21 +325,87 @@ __device__ __forceinline__ void production_rates(MechC mc0, const double* rho_a,
 #pragma unroll
             for (int f = 0; f < MAXO; ++f)
                 if (f < nf) sg -= ls.g[x.fac_f[f] * NT];
-            double bwd = exp(lnkf + sg - x.dnu_sum * lnc);
+            const double kr = exp(lnkf + sg - x.dnu_sum * lnc);
+            double bwd = kr;
 #pragma unroll
             for (int f = 0; f < MAXO; ++f)
                 if (f < nr) bwd *= ls.c[x.fac_r[f] * NT];
+            if constexpr (JAC) scatter_factor_derivs<NT>(ls, x.fac_r, nr, -kr);
             q -= bwd;
         }
 #pragma unroll
         for (int a = 0; a < M; ++a) wdot[a] = fma(x.dnu[a], q, wdot[a]);
+        if constexpr (JAC) {
+            // J[a][b] += dnu_a dq_b (in concentrations; scaled below)
+#pragma unroll
+            for (int b = 0; b < M; ++b) {
+                const double d = ls.dq[b * NT];
+                ls.dq[b * NT] = 0.0;
+#pragma unroll
+                for (int a = 0; a < M; ++a) J[a][b] = fma(x.dnu[a], d, J[a][b]);
+            }
+        }
     }
 #pragma unroll
     for (int a = 0; a < M; ++a) wdot[a] *= mc.m[a];
+    if constexpr (JAC) {
+        // d rho_dot_a / d rho_b = m_a (d/dc_b) / m_b
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int b = 0; b < M; ++b) J[a][b] *= mc.m[a] * mc.inv_m[b];
+    }
 }
 
-// Delta rho_a over one step by l forward-Euler sub-steps at frozen U.
 template <int M, int NT>
+__device__ __forceinline__ void production_rates(MechC mc, const double* rho_a, double T, const ChemLds<NT>& ls,
+                                                 double* wdot) {
+    rates_jac<M, NT, false>(mc, rho_a, T, ls, wdot, nullptr);
+}
+
+// Solves A x = b in place (x returned in b) by Gaussian elimination with
+// partial pivoting.  Every index is a compile-time constant, so A stays in
+// registers: the pivot search is a chain of compare-and-swap steps that
+// leaves the largest |A[i][k]|, i >= k, in row k (the first one on ties).
+template <int M>
+__device__ __forceinline__ void solve_pivoted(double (*A)[M], double* b) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+#pragma unroll
+        for (int i = k + 1; i < M; ++i) {
+            const bool sw = fabs(A[i][k]) > fabs(A[k][k]);
+#pragma unroll
+            for (int j = k; j < M; ++j) {
+                const double t = A[k][j];
+                A[k][j] = sw ? A[i][j] : t;
+                A[i][j] = sw ? t : A[i][j];
+            }
+            const double t = b[k];
+            b[k] = sw ? b[i] : t;
+            b[i] = sw ? t : b[i];
+        }
+        const double inv = 1.0 / A[k][k];
+#pragma unroll
+        for (int i = k + 1; i < M; ++i) {
+            const double f = A[i][k] * inv;
+#pragma unroll
+            for (int j = k + 1; j < M; ++j) A[i][j] = fma(-f, A[k][j], A[i][j]);
+            b[i] = fma(-f, b[k], b[i]);
+        }
+    }
+#pragma unroll
+    for (int k = M - 1; k >= 0; --k) {
+        double s = b[k];
+#pragma unroll
+        for (int j = k + 1; j < M; ++j) s = fma(-A[k][j], b[j], s);
+        b[k] = s / A[k][k];
+    }
+}
+
+// Delta rho_a over one step by l sub-steps at frozen U: forward Euler
+// (eq. R3) or, with IMPL, linearly implicit sub-steps
+// (I - dt^r J) Delta = dt^r rho_dot.
+template <int M, int NT, bool IMPL>
 __device__ __forceinline__ void reaction_increment(MechC mc0, const double* rho_a, double rho, double U, double T,
                                                    int l, const ChemLds<NT>& ls, double* drho, int* fail) {
     double cur[M], w[M];
@@ -323,9 +427,23 @@ __device__ __forceinline__ void reaction_increment(MechC mc0, const double* rho_
             for (int a = 0; a < M; ++a) Y[a] = cur[a] * inv_rho;
             Ts = solve_T<M>(mc, Y, U, Ts, fail);
         }
-        production_rates<M, NT>(mc, cur, Ts, ls, w);
+        if constexpr (IMPL) {
+            double A[M][M];
+            rates_jac<M, NT, true>(mc, cur, Ts, ls, w, A);
 #pragma unroll
-        for (int a = 0; a < M; ++a) cur[a] += w[a] * inv_l;
+            for (int a = 0; a < M; ++a) {
+#pragma unroll
+                for (int b = 0; b < M; ++b) A[a][b] = (a == b ? 1.0 : 0.0) - inv_l * A[a][b];
+                w[a] *= inv_l;
+            }
+            solve_pivoted<M>(A, w);
+#pragma unroll
+            for (int a = 0; a < M; ++a) cur[a] += w[a];
+        } else {
+            production_rates<M, NT>(mc, cur, Ts, ls, w);
+#pragma unroll
+            for (int a = 0; a < M; ++a) cur[a] += w[a] * inv_l;
+        }
     }
 #pragma unroll
     for (int a = 0; a < M; ++a) drho[a] = cur[a] - rho_a[a];

@@ -99,6 +99,8 @@ int validate_desc(const rlbm_lattice_desc* d, int M) {
     if (d->storage != RLBM_STORAGE_F64 && d->storage != RLBM_STORAGE_F32_DEV)
         return fail(RLBM_EINVAL, "unknown storage format");
     if (d->substeps < 1) return fail(RLBM_EINVAL, "substeps must be >= 1");
+    if (d->reaction != RLBM_REACTION_EXPLICIT && d->reaction != RLBM_REACTION_LINEARLY_IMPLICIT)
+        return fail(RLBM_EINVAL, "unknown reaction scheme");
     if (d->slaved < -1 || d->slaved >= M) return fail(RLBM_EINVAL, "slaved species index out of range");
     return RLBM_OK;
 }
@@ -408,6 +410,7 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     h.slaved = d->slaved < 0 ? M - 1 : d->slaved;
     h.substeps = d->substeps;
     h.storage = d->storage;
+    h.reaction = d->reaction;
     h.N = g.N;
     h.n_if = (int)nif;
     h.n_out = g.n_out;
@@ -598,6 +601,7 @@ static int step_one(rlbm_lattice* lat, long long t) {
         a.t = t;
         a.flag = lat->d_flag;
         a.stream = lat->stream;
+        a.schemes = 1u << lat->host.reaction;
         if (a.blocks == 0) continue;
         Timing* ev = nullptr;
         if (lat->timing >> phase & 1u) {
@@ -881,8 +885,10 @@ int rlbm_batch_step(rlbm_batch* b, const int64_t* steps) {
     HIP_TRY(hipSetDevice(l0->device), "hipSetDevice");
     b->host_table.resize(k);
     b->host_blk.assign(3 * (k + 1), 0);
+    unsigned schemes = 0;
     for (int j = 0; j < k; ++j) {
         rlbm_lattice* lat = b->lats[j];
+        if (steps[j]) schemes |= 1u << lat->host.reaction;
         LatDev e = lat->host;
         e.parity0 = (int)(lat->steps_done & 1);
         e.t_end = steps[j];
@@ -912,6 +918,7 @@ int rlbm_batch_step(rlbm_batch* b, const int64_t* steps) {
             a.t = t;
             a.flag = l0->d_flag;
             a.stream = l0->stream;
+            a.schemes = schemes;
             if (a.blocks == 0) continue;
             HIP_TRY(launch_phase(phase, l0->M, l0->storage, a), "batch kernel launch");
         }

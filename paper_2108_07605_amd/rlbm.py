@@ -18,9 +18,11 @@ LIB_PATH = os.path.join(_HERE, "librlbm.so")
 
 FACE_PERIODIC, FACE_WALL, FACE_INLET, FACE_OUTLET, FACE_BOUNCEBACK, FACE_INLET_LOCAL = 0, 1, 2, 3, 4, 5
 STORAGE_F64, STORAGE_F32_DEV = 0, 1
+REACTION_EXPLICIT, REACTION_LINEARLY_IMPLICIT = 0, 1
 _FACE_CODES = {"periodic": FACE_PERIODIC, "wall": FACE_WALL, "inlet": FACE_INLET,
                "outlet": FACE_OUTLET, "bounceback": FACE_BOUNCEBACK, "inlet_local": FACE_INLET_LOCAL}
 _STORAGE = {"f64": STORAGE_F64, "f32dev": STORAGE_F32_DEV}
+_REACTION = {"explicit": REACTION_EXPLICIT, "implicit": REACTION_LINEARLY_IMPLICIT}
 # kernels of one step, in launch order (rlbm_kernel_times)
 KERNELS = ("boundary", "local", "chem", "update")
 
@@ -69,6 +71,7 @@ class LatticeDesc(ctypes.Structure):
         ("nx", c_int32), ("ny", c_int32), ("nz", c_int32),
         ("faces", Face * 6),
         ("storage", c_int32), ("substeps", c_int32), ("slaved", c_int32),
+        ("reaction", c_int32),
     ]
 
 
@@ -197,6 +200,7 @@ def lattice_desc(case, storage="f64"):
     d.storage = _STORAGE[storage]
     d.substeps = int(case.get("substeps", 2))
     d.slaved = int(case.get("slaved", -1))
+    d.reaction = _REACTION[case.get("reaction", "explicit")]
     return d, keep
 
 

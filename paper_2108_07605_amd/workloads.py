@@ -35,6 +35,7 @@ transport of section 3.5):
 """
 from __future__ import annotations
 
+import copy
 import itertools
 import math
 from dataclasses import dataclass
@@ -431,7 +432,8 @@ def make_case(name: str, seed: int = 0, **kw):
     periodic box), 'channel2d' (1024x64x1), 'channel3d' (512x64x64), 'tube'
     (Lx1x1 flame tube), 'binary' (two-species periodic box), 'bbbox' (duct
     with bounce-back walls), plus keyword
-    overrides nx, ny, nz, storage ('f64' | 'f32dev'), substeps, steps."""
+    overrides nx, ny, nz, storage ('f64' | 'f32dev'), substeps, reaction
+    ('explicit' | 'implicit'), steps."""
     builders = {
         "abc_box": _case_abc_box,
         "reactor": _case_reactor,
@@ -444,6 +446,7 @@ def make_case(name: str, seed: int = 0, **kw):
     case = builders[name](seed=seed, **kw)
     case.setdefault("storage", kw.get("storage", "f64"))
     case.setdefault("substeps", kw.get("substeps", 2))
+    case.setdefault("reaction", kw.get("reaction", "explicit"))
     case["name"] = name
     case["N"] = case["nx"] * case["ny"] * case["nz"]
     return case
@@ -471,13 +474,17 @@ def _case_abc_box(seed=0, nx=32, ny=8, nz=8, steps=200, substeps=2, perturb=True
 
 
 def _case_reactor(seed=0, nx=16, ny=16, nz=16, steps=1000, substeps=2, mech=None,
-                  T0=1200.0, X_fuel=0.1, **kw):
+                  T0=1200.0, X_fuel=0.1, X_radical=0.0, **kw):
+    """Homogeneous periodic box of fuel, oxidiser and inert; X_radical > 0
+    adds that mole fraction of every other species (a radical pool, so the
+    fast reactions run from the first step)."""
     mech = mech or mechanism_h2air9(substeps=substeps)
     M = mech["M"]
     N = nx * ny * nz
     X = np.zeros(M)
     if M == 9:
-        X[FUEL9], X[INERT9] = X_fuel, 0.7
+        X[:] = X_radical
+        X[FUEL9], X[INERT9], X[OXID9] = X_fuel, 0.7 - 6 * X_radical, 0.0
         X[OXID9] = 1.0 - X.sum()
     else:
         X[:] = 1.0 / M
@@ -647,6 +654,16 @@ def _binary_mech(masses=(2.0, 28.0)):
     _transport(mech, T_ref=T_ref, rho_ref=1.0, P_ref=P0, pair_ref=(0, 1))
     mech["capped"] = []
     return mech
+
+
+def scaled_rates(mech, factor: float):
+    """Copy of a mechanism with every pre-exponential factor multiplied by
+    `factor` (after the stiffness screen): a stiff variant for the linearly
+    implicit reaction update."""
+    out = copy.deepcopy(mech)
+    out["lnA"] = [a + math.log(factor) for a in mech["lnA"]]
+    out["name"] = "%s, rates x%g" % (mech["name"], factor)
+    return out
 
 
 def tube_batch(n: int = 256, seed: int = 0, mech=None, substeps: int = 2):

@@ -101,6 +101,19 @@ def test_boundary_variants_accepted(mech9):
     assert rlbm.lattice_bytes(case, m, "f32dev") > 0
 
 
+def test_reaction_scheme_validation(mech9):
+    m = rlbm.Mechanism(mech9)
+    case = wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9, reaction="implicit")
+    assert rlbm.lattice_bytes(case, m, "f64") > 0
+    d, _keep = rlbm.lattice_desc(case, "f64")
+    assert d.reaction == rlbm.REACTION_LINEARLY_IMPLICIT
+    d.reaction = 2
+    n = ctypes.c_size_t()
+    assert rlbm.lib().rlbm_lattice_bytes(ctypes.byref(d), m.handle, ctypes.byref(n)) == -1
+    with pytest.raises(KeyError):
+        rlbm.lattice_desc(dict(case, reaction="rk4"), "f64")
+
+
 def test_inlet_composition_must_sum_to_one(mech9):
     m = rlbm.Mechanism(mech9)
     case = wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9)

@@ -97,6 +97,8 @@ def test_abc_box_initial_state_exact():
     ("bbbox", dict(nx=12, ny=8, nz=6), [1, 30]),
     ("channel2d", dict(nx=48, ny=12, nz=1, inlet="inlet_local"), [1, 30]),
     ("channel2d", dict(nx=40, ny=10, nz=1, substeps=4), [1, 20]),
+    ("channel2d", dict(nx=48, ny=12, nz=1, reaction="implicit"), [1, 30]),
+    ("reactor", dict(nx=4, ny=4, nz=4, T0=1500.0, X_radical=0.01, reaction="implicit", substeps=1), [1, 40]),
 ])
 def test_nine_species_parity(mech9, name, kw, steps):
     print(f"case {name} {kw} M=9 f64", flush=True)
@@ -105,6 +107,26 @@ def test_nine_species_parity(mech9, name, kw, steps):
     for gp, op, gf, of in out:
         _compare_pops(gp, op, TOL64)
         _compare_fields(gf, of, TOL64, _u_floor(case))
+
+
+@pytest.mark.parametrize("l", [1, 3])
+def test_stiff_reactor_linearly_implicit(mech9, l):
+    """Rates x1e4 (one forward-Euler sub-step overshoots to negative mass
+    fractions here): the linearly implicit update with partial pivoting
+    matches the oracle in a perturbed radical-seeded box, so every node
+    differs, while the mixture burns."""
+    mech = wl.scaled_rates(mech9, 1e4)
+    case = wl.make_case("reactor", nx=6, ny=4, nz=3, mech=mech, T0=1500.0, X_radical=0.01,
+                        reaction="implicit", substeps=l)
+    rng = np.random.default_rng(70 + l)
+    case["init"]["T"] = case["init"]["T"] * (1.0 + 0.02 * rng.standard_normal(case["N"]))
+    case["init"]["u"] = 0.01 * rng.standard_normal((3, case["N"]))
+    print(f"case stiff reactor 6x4x3 x1e4 implicit l={l} f64", flush=True)
+    lat, ora, out = _run_pair(case, [1, 5, 20])
+    for gp, op, gf, of in out:
+        _compare_pops(gp, op, TOL64)
+        _compare_fields(gf, of, TOL64, _u_floor(case))
+    assert out[-1][3]["T"].min() > 1800.0
 
 
 def test_bounce_back_box_conservation():
@@ -254,9 +276,11 @@ def test_determinism(mech9):
 
 def test_batch_equals_alone(mech9):
     """Uneven lattices in one batched launch give bit-identical results to
-    stepping each alone, including different step counts."""
+    stepping each alone, including different step counts and a lattice with
+    the linearly implicit reaction update among explicit ones."""
     rlbm = _gpu()
-    cases = [wl.make_case("tube", seed=s, nx=n, mech=mech9) for s, n in ((1, 64), (2, 300), (3, 129))]
+    cases = [wl.make_case("tube", seed=s, nx=n, mech=mech9, reaction=r)
+             for s, n, r in ((1, 64, "explicit"), (2, 300, "implicit"), (3, 129, "explicit"))]
     steps = [20, 7, 13]
     alone = []
     for c, n in zip(cases, steps):

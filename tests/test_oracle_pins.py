@@ -433,6 +433,32 @@ def test_linearly_implicit_converges_to_the_reactor_ode(mech9):
         assert 1.6 < errs[0] / errs[1] < 2.4 and 1.6 < errs[1] / errs[2] < 2.4, errs
 
 
+def test_stiff_reactor_needs_the_implicit_update(mech9):
+    """With every rate x1e4 a radical-seeded reactor overshoots under one
+    forward-Euler sub-step (negative mass fractions, a wrong temperature
+    history), while one linearly implicit sub-step stays non-negative and
+    within 2% in T of eight sub-steps."""
+    mech = wl.scaled_rates(mech9, 1e4)
+    hist = {}
+    for scheme, l in (("explicit", 1), ("implicit", 1), ("implicit", 8)):
+        o = Oracle(wl.make_case("reactor", nx=2, ny=2, nz=2, mech=mech, T0=1500.0, X_radical=0.01,
+                                substeps=l, reaction=scheme))
+        T, ymin = [], []
+        for _ in range(6):
+            o.step(4)
+            f = o.fields()
+            T.append(f["T"][0])
+            ymin.append(f["Y"].min())
+        hist[scheme, l] = (np.array(T), min(ymin))
+    T8, y8 = hist["implicit", 8]
+    T1, y1 = hist["implicit", 1]
+    Te, ye = hist["explicit", 1]
+    assert T8[-1] > 1900.0                       # the mixture does burn
+    assert y1 >= 0.0 and y8 >= 0.0
+    assert np.abs(T1 - T8).max() < 0.02 * T8.max()
+    assert ye < -1e-3 or np.abs(Te - T8).max() > 0.03 * T8.max()
+
+
 def test_unknown_reaction_scheme_is_rejected(mech_abc):
     rho_a, T = _random_state(mech_abc, 2)
     with pytest.raises(ValueError):

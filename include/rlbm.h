@@ -63,6 +63,8 @@ extern "C" {
  *   K_c = exp(-sum_a dnu_a g_a/(R_univ T)) (exp(ln_cstd)/T)^(sum_a dnu_a),
  *   q = k_f prod c^nu_f - reversible * k_f/K_c prod c^nu_r,
  *   rho_dot_a = m_a sum_r (nu_r - nu_f)_ar q_r.
+ * Every reaction must conserve mass, sum_a m_a (nu_r - nu_f)_a = 0 to 1e-12
+ * relative (eq. sumRhoDot), else RLBM_EINVAL.
  * Transport (synthetic laws standing in for mixture-averaged transport):
  *   mu = mu_ref (T/T_ref)^mu_exp, lambda = mu C_p / Pr,
  *   D_ab = D_ref[a][b] (T/T_ref)^D_exp (P_ref/P),
@@ -125,9 +127,12 @@ typedef struct rlbm_face {
  * forward Euler.  LINEARLY_IMPLICIT solves (I - dt^r J) Delta = dt^r rho_dot
  * per sub-step, J = d rho_dot / d rho at the sub-step's temperature (T held
  * fixed in J, re-solved at frozen U between sub-steps; max(c, 0) in the rates
- * differentiated as the identity), by Gaussian elimination with partial
- * pivoting.  It conserves mass and elements like EXPLICIT and is backward
- * Euler for a linear network, so stiff mechanisms need fewer sub-steps. */
+ * differentiated as the identity).  Mass conservation makes the last row of
+ * the system the negative sum of the others, so the library solves the
+ * (M-1)-species system that remains, by Gaussian elimination with partial
+ * pivoting, and sets Delta of the last species to minus the sum of the rest.
+ * It conserves mass and elements like EXPLICIT and is backward Euler for a
+ * linear network, so stiff mechanisms need fewer sub-steps. */
 #define RLBM_REACTION_EXPLICIT 0
 #define RLBM_REACTION_LINEARLY_IMPLICIT 1
 

@@ -590,8 +590,8 @@ __device__ __forceinline__ void node_gradients(const LatDev& L, int node) {
 // blocks of the others return at once.
 // ---------------------------------------------------------------------------
 template <int M, bool IMPL>
-__global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                              int n_lat, long long t, int* __restrict__ flag) {
+__device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const int* __restrict__ blk, int n_lat,
+                                          long long t, int* __restrict__ flag) {
     const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
@@ -604,18 +604,34 @@ __global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, c
     const size_t N = (size_t)L.N;
     __shared__ double s_c[M][256], s_g[M][256], s_q[IMPL ? M : 1][256];
     const ChemLds<256> ls{&s_c[0][threadIdx.x], &s_g[0][threadIdx.x], IMPL ? &s_q[0][threadIdx.x] : nullptr};
-    double rho_a[M], drho[M];
+    double rho_a[M], fin[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) rho_a[a] = prm[(PRM_SP + 6 * a) * N + node];
     const double rho = prm[PRM_RHO * N + node];
     const double U = prm[PRM_UINT * N + node];
     const double T = prm[PRM_T * N + node];
     int fail = 0;
-    reaction_increment<M, 256, IMPL>(mc, rho_a, rho, U, T, L.substeps, ls, drho, &fail);
+    reaction_increment<M, 256, IMPL>(mc, rho_a, rho, U, T, L.substeps, ls, fin, &fail);
     if (fail) atomicOr(flag, 1);
+    // Delta rho_a against the densities read again, so that they need not
+    // stay in registers through the sub-steps
+    reload_barrier();
 #pragma unroll
-    for (int a = 0; a < M; ++a) prm[(PRM_SP + 6 * a + 5) * N + node] = drho[a];
+    for (int a = 0; a < M; ++a) prm[(PRM_SP + 6 * a + 5) * N + node] = fin[a] - prm[(PRM_SP + 6 * a) * N + node];
     node_gradients<M>(L, node);
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+                                              int n_lat, long long t, int* __restrict__ flag) {
+    chem_body<M, false>(lats, blk, n_lat, t, flag);
+}
+
+// The linearly implicit variant holds an (M-1)^2 matrix in registers.
+template <int M>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_chem_implicit(
+    const LatDev* __restrict__ lats, const int* __restrict__ blk, int n_lat, long long t, int* __restrict__ flag) {
+    chem_body<M, true>(lats, blk, n_lat, t, flag);
 }
 
 
@@ -1657,10 +1673,10 @@ static hipError_t launch_step_phase(int phase, int M, const StepLaunch& a) {
                                                 a.blk, a.n_lat, a.t, a.flag))
     } else if (phase == 2) {
         if (a.schemes & (1u << RLBM_REACTION_EXPLICIT))
-            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem<MM, false>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
+            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
                                                     a.blk, a.n_lat, a.t, a.flag))
         if (a.schemes & (1u << RLBM_REACTION_LINEARLY_IMPLICIT))
-            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem<MM, true>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
+            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem_implicit<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
                                                     a.blk, a.n_lat, a.t, a.flag))
     } else {
         RLBM_DISPATCH(M, hipLaunchKernelGGL((k_update<MM, S>), dim3(a.blocks), dim3(UPD_THREADS), 0, a.stream, a.lats,

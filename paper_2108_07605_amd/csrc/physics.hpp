@@ -30,7 +30,7 @@ __host__ __device__ constexpr int c2_of(int i) {
 struct RxnDev {
     double lnA, beta, Ta, dnu_sum;
     int rev, nf, nr, pad_;
-    int fac_f[MAXO], fac_r[MAXO];
+    int fac_f[MAXO], fac_r[MAXO];   // species per molecule; entries past nf / nr hold 0
     double dnu[MAXM];
 };
 
@@ -254,13 +254,11 @@ struct ChemLds {
     double* dq;  // &dq[0][tid], or nullptr without the Jacobian
 };
 
-// Adds k prod_{g != f} c_{fac[g]} to dq[fac[f]] for every factor f < n.
+// Adds k prod_{g != f} c[g] to dq[fac[f]] for every factor f < n (c[f] = 1
+// and nothing added for f >= n).
 template <int NT>
 __device__ __forceinline__ void scatter_factor_derivs(const ChemLds<NT>& ls, const RLBM_CONST int* fac, int n,
-                                                      double k) {
-    double c[MAXO];
-#pragma unroll
-    for (int f = 0; f < MAXO; ++f) c[f] = f < n ? ls.c[fac[f] * NT] : 1.0;
+                                                      const double* c, double k) {
     // prefix and suffix products of the factor list
     double pre[MAXO], suf[MAXO];
     pre[0] = k;
@@ -270,28 +268,31 @@ __device__ __forceinline__ void scatter_factor_derivs(const ChemLds<NT>& ls, con
 #pragma unroll
     for (int f = MAXO - 2; f >= 0; --f) suf[f] = suf[f + 1] * c[f + 1];
 #pragma unroll
-    for (int f = 0; f < MAXO; ++f)
-        if (f < n) ls.dq[fac[f] * NT] += pre[f] * suf[f];
+    for (int f = 0; f < MAXO; ++f) ls.dq[fac[f] * NT] += f < n ? pre[f] * suf[f] : 0.0;
 }
 
 // Production rates rho_dot_a and, with JAC, the Jacobian J[a][b] =
-// d rho_dot_a / d rho_b at fixed T.  Each mass-action product is a list of
-// factors (one per molecule), so d/dc_b of the product is the sum, over the
-// factors that are species b, of the product of the other factors; the clip
-// max(c, 0) is differentiated as the identity.
+// d rho_dot_a / d rho_b at fixed T in the reduced form used by the linearly
+// implicit step (K = M - 1 is the last species):
+//   Jr[a][b] = J[a][b] - J[a][K],   a, b < K.
+// Each mass-action product is a list of factors (one per molecule), so d/dc_b
+// of the product is the sum, over the factors that are species b, of the
+// product of the other factors; the clip max(c, 0) is differentiated as the
+// identity.
 template <int M, int NT, bool JAC>
 __device__ __forceinline__ void rates_jac(MechC mc0, const double* rho_a, double T, const ChemLds<NT>& ls,
-                                          double* wdot, double (*J)[M]) {
+                                          double* wdot, double (*Jr)[M - 1]) {
+    constexpr int K = M - 1;
     MechC mc = mc0;
 #pragma unroll
     for (int a = 0; a < M; ++a) wdot[a] = 0.0;
     if constexpr (JAC) {
 #pragma unroll
-        for (int a = 0; a < M; ++a) {
-            ls.dq[a * NT] = 0.0;
+        for (int a = 0; a < M; ++a) ls.dq[a * NT] = 0.0;
 #pragma unroll
-            for (int b = 0; b < M; ++b) J[a][b] = 0.0;
-        }
+        for (int a = 0; a < K; ++a)
+#pragma unroll
+            for (int b = 0; b < K; ++b) Jr[a][b] = 0.0;
     }
     const int R = mc.R;
     if (R == 0) return;
@@ -309,51 +310,68 @@ __device__ __forceinline__ void rates_jac(MechC mc0, const double* rho_a, double
         const int nf = x.nf, nr = x.nr;
         const double lnkf = x.lnA + x.beta * lnT - x.Ta * invT;
         // forward rate k_f prod_b c_b^nu'_b
+        // Every factor slot is read (unused slots name species 0) and masked
+        // to 1 or 0, so the factor loops have no branches: the index loads
+        // merge into wide scalar loads and the LDS reads issue together.
+        double cf[MAXO];
+#pragma unroll
+        for (int f = 0; f < MAXO; ++f) {
+            const double v = ls.c[x.fac_f[f] * NT];
+            cf[f] = f < nf ? v : 1.0;
+        }
         const double kf = exp(lnkf);
         double fwd = kf;
 #pragma unroll
-        for (int f = 0; f < MAXO; ++f)
-            if (f < nf) fwd *= ls.c[x.fac_f[f] * NT];
-        if constexpr (JAC) scatter_factor_derivs<NT>(ls, x.fac_f, nf, kf);
+        for (int f = 0; f < MAXO; ++f) fwd *= cf[f];
+        if constexpr (JAC) scatter_factor_derivs<NT>(ls, x.fac_f, nf, cf, kf);
         double q = fwd;
         if (x.rev) {
             // k_r = k_f / K_c, ln K_c = -sum_a dnu_a g_a/(R T) + (sum_a dnu_a) ln c_std
+            double cr[MAXO], gr[MAXO], gf[MAXO];
+#pragma unroll
+            for (int f = 0; f < MAXO; ++f) {
+                const double v = ls.c[x.fac_r[f] * NT];
+                const double w = ls.g[x.fac_r[f] * NT];
+                const double u = ls.g[x.fac_f[f] * NT];
+                cr[f] = f < nr ? v : 1.0;
+                gr[f] = f < nr ? w : 0.0;
+                gf[f] = f < nf ? u : 0.0;
+            }
             double sg = 0.0;
 #pragma unroll
-            for (int f = 0; f < MAXO; ++f)
-                if (f < nr) sg += ls.g[x.fac_r[f] * NT];
+            for (int f = 0; f < MAXO; ++f) sg += gr[f];
 #pragma unroll
-            for (int f = 0; f < MAXO; ++f)
-                if (f < nf) sg -= ls.g[x.fac_f[f] * NT];
+            for (int f = 0; f < MAXO; ++f) sg -= gf[f];
             const double kr = exp(lnkf + sg - x.dnu_sum * lnc);
             double bwd = kr;
 #pragma unroll
-            for (int f = 0; f < MAXO; ++f)
-                if (f < nr) bwd *= ls.c[x.fac_r[f] * NT];
-            if constexpr (JAC) scatter_factor_derivs<NT>(ls, x.fac_r, nr, -kr);
+            for (int f = 0; f < MAXO; ++f) bwd *= cr[f];
+            if constexpr (JAC) scatter_factor_derivs<NT>(ls, x.fac_r, nr, cr, -kr);
             q -= bwd;
         }
 #pragma unroll
         for (int a = 0; a < M; ++a) wdot[a] = fma(x.dnu[a], q, wdot[a]);
         if constexpr (JAC) {
-            // J[a][b] += dnu_a dq_b (in concentrations; scaled below)
+            // d rho_dot_a / d rho_b = m_a dnu_a dq_b / m_b summed over the
+            // reactions; Jr[a][b] += dnu_a (dq_b / m_b - dq_K / m_K), m_a below
+            const double dK = ls.dq[K * NT] * mc.inv_m[K];
+            ls.dq[K * NT] = 0.0;
 #pragma unroll
-            for (int b = 0; b < M; ++b) {
-                const double d = ls.dq[b * NT];
+            for (int b = 0; b < K; ++b) {
+                const double d = fma(ls.dq[b * NT], mc.inv_m[b], -dK);
                 ls.dq[b * NT] = 0.0;
 #pragma unroll
-                for (int a = 0; a < M; ++a) J[a][b] = fma(x.dnu[a], d, J[a][b]);
+                for (int a = 0; a < K; ++a) Jr[a][b] = fma(x.dnu[a], d, Jr[a][b]);
             }
         }
     }
 #pragma unroll
     for (int a = 0; a < M; ++a) wdot[a] *= mc.m[a];
     if constexpr (JAC) {
-        // d rho_dot_a / d rho_b = m_a (d/dc_b) / m_b
 #pragma unroll
-        for (int a = 0; a < M; ++a)
+        for (int a = 0; a < K; ++a)
 #pragma unroll
-            for (int b = 0; b < M; ++b) J[a][b] *= mc.m[a] * mc.inv_m[b];
+            for (int b = 0; b < K; ++b) Jr[a][b] *= mc.m[a];
     }
 }
 
@@ -402,18 +420,23 @@ __device__ __forceinline__ void solve_pivoted(double (*A)[M], double* b) {
     }
 }
 
-// Delta rho_a over one step by l sub-steps at frozen U: forward Euler
+// Densities after one step of l sub-steps at frozen U: forward Euler
 // (eq. R3) or, with IMPL, linearly implicit sub-steps
-// (I - dt^r J) Delta = dt^r rho_dot.
+// (I - dt^r J) Delta = dt^r rho_dot.  Every reaction conserves mass (checked
+// when the mechanism is created), so the columns of J sum to zero, and so do
+// rho_dot and Delta: the last row of the system is the negative sum of the
+// others.  It is dropped, with Delta_K = -sum_{a<K} Delta_a substituted, which
+// leaves (I - dt^r Jr) Delta_{<K} = dt^r rho_dot_{<K} of size M - 1.
 template <int M, int NT, bool IMPL>
 __device__ __forceinline__ void reaction_increment(MechC mc0, const double* rho_a, double rho, double U, double T,
-                                                   int l, const ChemLds<NT>& ls, double* drho, int* fail) {
+                                                   int l, const ChemLds<NT>& ls, double* out, int* fail) {
+    constexpr int K = M - 1;
     double cur[M], w[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) cur[a] = rho_a[a];
     if (mc0.R == 0) {
 #pragma unroll
-        for (int a = 0; a < M; ++a) drho[a] = 0.0;
+        for (int a = 0; a < M; ++a) out[a] = cur[a];
         return;
     }
     const double inv_l = 1.0 / (double)l;
@@ -428,17 +451,22 @@ __device__ __forceinline__ void reaction_increment(MechC mc0, const double* rho_
             Ts = solve_T<M>(mc, Y, U, Ts, fail);
         }
         if constexpr (IMPL) {
-            double A[M][M];
+            double A[K][K];
             rates_jac<M, NT, true>(mc, cur, Ts, ls, w, A);
 #pragma unroll
-            for (int a = 0; a < M; ++a) {
+            for (int a = 0; a < K; ++a) {
 #pragma unroll
-                for (int b = 0; b < M; ++b) A[a][b] = (a == b ? 1.0 : 0.0) - inv_l * A[a][b];
+                for (int b = 0; b < K; ++b) A[a][b] = (a == b ? 1.0 : 0.0) - inv_l * A[a][b];
                 w[a] *= inv_l;
             }
-            solve_pivoted<M>(A, w);
+            solve_pivoted<K>(A, w);
+            double sum = 0.0;
 #pragma unroll
-            for (int a = 0; a < M; ++a) cur[a] += w[a];
+            for (int a = 0; a < K; ++a) {
+                cur[a] += w[a];
+                sum += w[a];
+            }
+            cur[K] -= sum;
         } else {
             production_rates<M, NT>(mc, cur, Ts, ls, w);
 #pragma unroll
@@ -446,7 +474,7 @@ __device__ __forceinline__ void reaction_increment(MechC mc0, const double* rho_
         }
     }
 #pragma unroll
-    for (int a = 0; a < M; ++a) drho[a] = cur[a] - rho_a[a];
+    for (int a = 0; a < M; ++a) out[a] = cur[a];
 }
 
 }  // namespace rlbm

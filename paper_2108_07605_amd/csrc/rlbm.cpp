@@ -346,6 +346,16 @@ int rlbm_mech_create(const rlbm_mech_desc* d, rlbm_mech** out) {
             for (int k = 0; k < b; ++k) x.fac_r[x.nr++] = a;
         }
         x.dnu_sum = s;
+        // sum_a m_a dnu_a = 0: the rates conserve mass (eq. sumRhoDot)
+        double net = 0.0, gross = 0.0;
+        for (int a = 0; a < M; ++a) {
+            net += d->molar_mass[a] * x.dnu[a];
+            gross += d->molar_mass[a] * std::fabs(x.dnu[a]);
+        }
+        if (std::fabs(net) > 1e-12 * gross) {
+            delete m;
+            return fail(RLBM_EINVAL, "a reaction does not conserve mass (sum_a m_a dnu_a != 0)");
+        }
     }
     md.T_ref = d->T_ref;
     md.inv_T_ref = 1.0 / d->T_ref;

@@ -44,6 +44,14 @@ def test_mechanism_validation(mech9):
         rlbm.Mechanism(bad)
 
 
+def test_reaction_must_conserve_mass(mech_abc):
+    bad = dict(mech_abc)
+    bad["molar_mass"] = [2.0, 32.0, 18.0]        # A + B -> 2C with 34 != 36
+    with pytest.raises(rlbm.RlbmError) as e:
+        rlbm.Mechanism(bad)
+    assert e.value.code == -1
+
+
 def test_unsupported_species_count():
     mech = wl.mechanism_abc()
     five = dict(mech)

@@ -9,7 +9,9 @@ imposed values.
 
 Stored lattices are the M-1 unslaved species, the momentum lattice f and the
 energy lattice g; the slaved species (eq. strongest) is implied by
-f - sum_a f_a and is not reconstructed separately.
+f - sum_a f_a and is not reconstructed separately.  In the weakly coupled
+storage (slaved = None) all M species are stored and reconstructed, and the
+composition of a population set is Y_a = rho_a / sum_b rho_b.
 
 Readings where the paper is silent:
   * A node touching several non-periodic faces takes the union of their
@@ -44,8 +46,10 @@ RHO_GUARD = 1e-14
 def mixed_moments(mech, stored, slaved, fa, f, g, T_guess):
     """Moments of a population set (eqs. density1, momentum1, fdensity,
     f1momMomentum, g0momTotalEnergy) and the temperature (eq. temperature).
-    fa: [M-1, 27, n] stored species.  Returns rho [n], u [3, n], rho_a [M, n],
-    u_a [M, 3, n], Y [M, n], U [n] and T [n]."""
+    fa: [len(stored), 27, n] stored species.  Returns rho [n], u [3, n],
+    rho_a [M, n], u_a [M, 3, n], Y [M, n], U [n], T [n] and rho_Y [n], the
+    density that normalises Y (rho when a species is slaved, sum_a rho_a in
+    the weakly coupled storage, slaved = None)."""
     M = mech["M"]
     rho = f.sum(axis=0)
     j = np.stack([(f * C[:, k][:, None]).sum(axis=0) for k in range(3)])
@@ -57,9 +61,13 @@ def mixed_moments(mech, stored, slaved, fa, f, g, T_guess):
         rho_a[a] = fa[k].sum(axis=0)
         for d in range(3):
             j_a[a, d] = (fa[k] * C[:, d][:, None]).sum(axis=0)
-    rho_a[slaved] = rho - sum(rho_a[a] for a in stored)
-    j_a[slaved] = j - sum(j_a[a] for a in stored)
-    Y = rho_a / rho
+    if slaved is None:
+        rho_Y = rho_a.sum(axis=0)
+    else:
+        rho_a[slaved] = rho - sum(rho_a[a] for a in stored)
+        j_a[slaved] = j - sum(j_a[a] for a in stored)
+        rho_Y = rho
+    Y = rho_a / rho_Y
     u_a = np.empty_like(j_a)
     for a in range(M):
         small = rho_a[a] <= RHO_GUARD * rho
@@ -68,7 +76,8 @@ def mixed_moments(mech, stored, slaved, fa, f, g, T_guess):
     rhoE = g.sum(axis=0)
     U = rhoE / rho - 0.5 * (u ** 2).sum(axis=0)
     T = solve_temperature(mech, Y, U, T_guess)
-    return {"rho": rho, "u": u, "rho_a": rho_a, "u_a": u_a, "Y": Y, "U": U, "T": T}
+    return {"rho": rho, "u": u, "rho_a": rho_a, "u_a": u_a, "Y": Y, "U": U, "T": T,
+            "rho_Y": rho_Y}
 
 
 def equilibria_set(mech, stored, rho, Y, u, T, u_species=None):
@@ -104,8 +113,11 @@ def tms_wall(mech, stored, slaved, D, fa, f, g, fa_prev, f_prev, g_prev, opp,
     rhoY = np.zeros((M, n))
     for k, a in enumerate(stored):
         rhoY[a] = fa_bb[k].sum(axis=0)
-    rhoY[slaved] = rho_bb - sum(rhoY[a] for a in stored)
-    Y_bb = rhoY / rho_bb
+    if slaved is None:
+        Y_bb = rhoY / rhoY.sum(axis=0)
+    else:
+        rhoY[slaved] = rho_bb - sum(rhoY[a] for a in stored)
+        Y_bb = rhoY / rho_bb
     # step 2: target equilibria with u^tgt = u_a^tgt = 0, T^tgt
     u0 = np.zeros((3, n))
     f_t, g_t, fa_t = equilibria_set(mech, stored, rho_bb, Y_bb, u0, T_tgt)

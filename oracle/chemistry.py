@@ -127,7 +127,8 @@ def linearly_implicit_substep(mech, rho_a, T, h):
 def reaction_increment(mech, rho_a, rho, U, T, substeps, scheme="explicit"):
     """Delta rho_a over one lattice time step by l sub-steps at frozen U:
     forward Euler (eq. R3) or the linearly implicit variant.  T is the
-    temperature at the start of the step."""
+    temperature at the start of the step; rho normalises the composition,
+    Y = rho_a / rho, in the temperature solves between sub-steps."""
     if scheme not in ("explicit", "implicit"):
         raise ValueError("unknown reaction scheme %r" % (scheme,))
     cur = rho_a.copy()

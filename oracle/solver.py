@@ -35,6 +35,17 @@ Per step (dt = dx = 1, lattice units, T in kelvin):
 
 Initial populations are the equilibria f_a^eq (unslaved species), f^eq and
 g^eq at the given (rho, u, T, Y).
+
+Weakly coupled storage (case["coupling"] = "weak"; the system before the
+slaving of eq. strongest, section 3.4): all M species lattices are stored
+beside f and g, so the step advances M+2 independent lattices.  The two
+subsystems exchange fields but not populations.  Reading: the species
+subsystem supplies the composition Y_a = rho_a / sum_b rho_b; the mixture
+subsystem supplies rho, u (from f) and, with rho E, the temperature.  The
+species take u in their quasi-equilibria and in the Stefan-Maxwell
+right-hand sides u_a - u, and every species collides with its own rho_a.
+sum_a rho_a and rho are then two conserved densities that may drift apart,
+which is the redundancy the slaving removes.
 """
 import numpy as np
 
@@ -57,7 +68,10 @@ class Oracle:
         self.faces = case["faces"]
         self.l = int(case.get("substeps", 2))
         self.reaction = case.get("reaction", "explicit")
-        self.s = int(case["slaved"])
+        coupling = case.get("coupling", "strong")
+        if coupling not in ("strong", "weak"):
+            raise ValueError("unknown coupling %r" % (coupling,))
+        self.s = None if coupling == "weak" else int(case["slaved"])
         self.stored = [a for a in range(self.M) if a != self.s]
         self._geometry()
         self.set_state(case["init"])
@@ -168,15 +182,17 @@ class Oracle:
         self.time = 0
 
     def populations(self):
-        """All stored populations, [L, 27, N], ordered: unslaved species in
-        ascending species index, then f, then g."""
+        """All stored populations, [L, 27, N], ordered: stored species in
+        ascending species index, then f, then g (L = M + 1, or M + 2 in the
+        weakly coupled storage)."""
         return np.concatenate([self.fa, self.f[None], self.g[None]], axis=0)
 
     def set_populations(self, pops):
         pops = np.asarray(pops, dtype=np.float64)
-        self.fa = pops[: self.M - 1].copy()
-        self.f = pops[self.M - 1].copy()
-        self.g = pops[self.M].copy()
+        ns = len(self.stored)
+        self.fa = pops[:ns].copy()
+        self.f = pops[ns].copy()
+        self.g = pops[ns + 1].copy()
 
     # ------------------------------------------------------------------
     # step
@@ -243,8 +259,8 @@ class Oracle:
             self.out_state = out
         # 3. moments
         mo = bc.mixed_moments(mech, stored, s, fa, f, g, self.T)
-        rho, u, rho_a, u_a, Y, U, T = (mo[k_] for k_ in
-                                       ("rho", "u", "rho_a", "u_a", "Y", "U", "T"))
+        rho, u, rho_a, u_a, Y, U, T, rho_Y = (mo[k_] for k_ in
+                                              ("rho", "u", "rho_a", "u_a", "Y", "U", "T", "rho_Y"))
         R = mixture_R(mech, Y)
         theta = R * T
         P = rho * theta
@@ -264,7 +280,7 @@ class Oracle:
         omega, omega1 = mixture_omegas(mech, T, P)
         V = stefan_maxwell(Y, itab, inv_tau, u_a, u)
         # 6. reactions
-        drho = reaction_increment(mech, rho_a, rho, U, T, l, self.reaction)
+        drho = reaction_increment(mech, rho_a, rho_Y, U, T, l, self.reaction)
         # 7. species collision
         Wsp = [species_W(u, Ra[b] * T) for b in range(M)]
         feq_b = [rho_a[b] * Wsp[b] for b in range(M)]
@@ -332,7 +348,8 @@ class Oracle:
         rho_a = np.zeros((self.M, self.N))
         for k, a in enumerate(self.stored):
             rho_a[a] = self.fa[k].sum(axis=0)
-        rho_a[self.s] = rho - rho_a.sum(axis=0)
+        if self.s is not None:
+            rho_a[self.s] = rho - rho_a.sum(axis=0)
         elem = ((rho_a / m[:, None]).sum(axis=1)[:, None] * comp).sum(axis=0)
         bad = not (np.isfinite(self.fa).all() and np.isfinite(self.f).all()
                    and np.isfinite(self.g).all())

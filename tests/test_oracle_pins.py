@@ -552,6 +552,62 @@ def test_periodic_conservation_abc_box():
     assert np.allclose(fl["Y"].sum(axis=0), 1.0, rtol=0, atol=1e-15)
 
 
+def test_weak_coupling_uniform_reactor_equals_strong_coupling(mech9):
+    """Weakly coupled storage (all M species stored): in a uniform reactor at
+    rest nothing can separate sum_a rho_a from rho, so it must reproduce the
+    slaved (strongly coupled) system to round-off."""
+    case = wl.make_case("reactor", nx=2, ny=2, nz=2, mech=wl.scaled_rates(mech9, 100.0), T0=1500.0,
+                        X_radical=0.01)
+    weak = dict(case, coupling="weak")
+    os_, ow = Oracle(case), Oracle(weak)
+    assert ow.populations().shape[0] == mech9["M"] + 2
+    assert os_.populations().shape[0] == mech9["M"] + 1
+    os_.step(30)
+    ow.step(30)
+    fs, fw = os_.fields(), ow.fields()
+    assert abs(fw["T"][0] - 1500.0) > 10.0             # it reacts
+    for k in ("rho", "T", "Y"):
+        np.testing.assert_allclose(fw[k], fs[k], rtol=1e-12, atol=1e-15)
+    # the density of the slaved species' own lattice is rho - sum of the others
+    # (populations differ: each species relaxes to its own equilibrium shape)
+    s = case["slaved"]
+    others = [a for a in range(mech9["M"]) if a != s]
+    rho = ow.f.sum(axis=0)
+    np.testing.assert_allclose(ow.fa[s].sum(axis=0), rho - ow.fa[others].sum(axis=(0, 1)), rtol=1e-13)
+
+
+def test_weak_coupling_conserves_both_densities_and_drifts():
+    """Periodic box in the weakly coupled storage: the mixture mass sum rho,
+    the species mass sum_a rho_a, rho E, momentum and the element totals are
+    each conserved, while the two densities drift apart locally (the
+    redundancy that eq. strongest removes), by a small amount that keeps the
+    fields close to the strongly coupled ones."""
+    case = wl.make_case("abc_box")
+    weak = dict(case, coupling="weak")
+    o = Oracle(weak)
+    inv0 = o.invariants()
+    sp0 = o.fa.sum()
+    fl0 = o.fields()
+    o.step(100)
+    inv1 = o.invariants()
+    for k in (0, 4, 5, 6):
+        assert abs(inv1[k] - inv0[k]) <= 1e-13 * abs(inv0[k]), k
+    cs = math.sqrt(float(np.mean(fl0["P"] / fl0["rho"])))
+    for k in (1, 2, 3):
+        assert abs(inv1[k] - inv0[k]) <= 1e-13 * inv0[0] * cs
+    assert abs(o.fa.sum() - sp0) <= 1e-13 * sp0
+    rho_sp = o.fa.sum(axis=1).sum(axis=0)
+    rho = o.f.sum(axis=0)
+    drift = np.abs(rho - rho_sp).max() / rho.max()
+    assert 1e-6 < drift < 1e-2, drift
+    ref = Oracle(case)
+    ref.step(100)
+    fw, fs = o.fields(), ref.fields()
+    for k in ("rho", "T", "Y"):
+        assert np.abs(fw[k] - fs[k]).max() <= 1e-2 * np.abs(fs[k]).max(), k
+    np.testing.assert_allclose(fw["Y"].sum(axis=0), 1.0, rtol=0, atol=1e-14)
+
+
 def test_closed_tms_box_conserves_mass():
     """Bounce-back conserves mass; TMS sets the wall-node densities and
     mass fractions to their bounce-back values (eqs. BBrho, BBY), so a box

@@ -19,7 +19,8 @@
  *    velocity is i = 13 and the opposite of i is 26 - i.
  *  - Population buffers exchanged through this ABI are FP64, ordered
  *    [L][27][N] with L = M + 1 stored lattices: the M - 1 unslaved species in
- *    ascending species index, then f, then g.
+ *    ascending species index, then f, then g.  In the weakly coupled storage
+ *    (RLBM_SLAVED_NONE) L = M + 2: all M species, then f, then g.
  *  - Every call returns 0 on success or a negative RLBM_E* code; the message
  *    of the last failure on the calling thread is rlbm_last_error().  No call
  *    aborts or throws.
@@ -136,6 +137,15 @@ typedef struct rlbm_face {
 #define RLBM_REACTION_EXPLICIT 0
 #define RLBM_REACTION_LINEARLY_IMPLICIT 1
 
+/* Weakly coupled storage (section 3.6 before eq. strongest): no species is
+ * slaved; all M species lattices are stored beside f and g (L = M + 2) and
+ * the two subsystems exchange fields only.  The species supply the
+ * composition Y_a = rho_a / sum_b rho_b; f supplies rho and u, and with g the
+ * temperature.  Species relax with their own rho_a, toward quasi-equilibria
+ * at the velocity u of f; rho and sum_a rho_a are both conserved globally and
+ * may drift apart locally, which is the redundancy the slaving removes. */
+#define RLBM_SLAVED_NONE (-2)
+
 #define RLBM_STORAGE_F64 0        /* populations stored in FP64 */
 #define RLBM_STORAGE_F32_DEV 1    /* FP32 deviations from a per-(lattice, velocity) reference */
 
@@ -146,7 +156,8 @@ typedef struct rlbm_lattice_desc {
     int32_t storage;              /* RLBM_STORAGE_* */
     int32_t substeps;             /* reaction sub-steps l >= 1 (eq. R3) */
     int32_t slaved;               /* slaved species index, or -1: chosen at rlbm_set_state as
-                                     the largest domain-mean mass fraction (lowest index on ties) */
+                                     the largest domain-mean mass fraction (lowest index on ties),
+                                     or RLBM_SLAVED_NONE */
     int32_t reaction;             /* RLBM_REACTION_* */
 } rlbm_lattice_desc;
 
@@ -214,7 +225,8 @@ int rlbm_load_state(rlbm_lattice* lat, const void* buf, int on_device);
  * n_out >= 6 + E.  Synchronises the stream. */
 int rlbm_invariants(rlbm_lattice* lat, double* out, int n_out);
 
-/* Number of stored lattices L, nodes N and interface nodes. */
+/* Number of stored lattices L, nodes N and interface nodes, and the slaved
+ * species (RLBM_SLAVED_NONE in the weakly coupled storage). */
 int rlbm_lattice_shape(const rlbm_lattice* lat, int32_t* L, int64_t* N, int64_t* n_interface,
                        int32_t* slaved);
 

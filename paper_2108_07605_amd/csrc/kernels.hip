@@ -67,13 +67,24 @@ __device__ __forceinline__ double ref_g(float sg, float sf, double W, double K) 
     return (double)sg * W + (double)sf * K;
 }
 
-// Layout of the reference table: shapes G[M + 1][Q] (the energy lattice's
-// row is W), the zeroth moments sum_i G_li [M + 1], sum_i G_fi c_ix^2, the
-// energy lattice's K[Q] and sum_i K_i.
-template <int M> constexpr int REF_M0 = (M + 1) * Q;
-template <int M> constexpr int REF_M2 = (M + 1) * Q + M + 1;
-template <int M> constexpr int REF_K = (M + 1) * Q + M + 2;
-template <int M> constexpr int REF_K0 = (M + 1) * Q + M + 2 + Q;
+// Stored lattices: the species lattices (M - 1 of them when one species is
+// slaved, eq. strongest; all M in the weakly coupled storage, W = 1), then
+// the momentum lattice f at LF and the energy lattice g at LG.
+template <int M, int W>
+struct Lat {
+    static constexpr int NSP = M - 1 + W;
+    static constexpr int LF = NSP;
+    static constexpr int LG = NSP + 1;
+    static constexpr int NL = NSP + 2;
+};
+
+// Layout of the reference table for NL stored lattices: shapes G[NL][Q] (the
+// energy lattice's row is W), the zeroth moments sum_i G_li [NL],
+// sum_i G_fi c_ix^2, the energy lattice's K[Q] and sum_i K_i.
+template <int NL> constexpr int REF_M0 = NL * Q;
+template <int NL> constexpr int REF_M2 = NL * Q + NL;
+template <int NL> constexpr int REF_K = NL * Q + NL + 1;
+template <int NL> constexpr int REF_K0 = NL * Q + NL + 1 + Q;
 
 // Scales s_l of node n in buffer q: rss floats per node, lattices in order
 // (stored species, rho, rho E).
@@ -143,7 +154,8 @@ __device__ __forceinline__ void pull_offsets(const LatDev& L, int x, int y, int 
 __device__ __forceinline__ int sel3(int c, int m, int z, int p) { return c < 0 ? m : (c == 0 ? z : p); }
 __device__ __forceinline__ double sel3d(int c, double m, double z, double p) { return c < 0 ? m : (c == 0 ? z : p); }
 
-template <int M>
+// Stored lattice of species a; a slaved index of M (the weakly coupled
+// storage) stores every species at its own index.
 __device__ __forceinline__ int lat_of(int a, int slaved) { return a - (a > slaved ? 1 : 0); }
 
 // Per-thread LDS columns of k_local (stride 256 doubles between rows): the
@@ -170,9 +182,10 @@ constexpr int LOC_T = 256;   // k_local threads per block
 // densities rho_a come from k_local's LDS columns, the node's scalars from
 // its registers; writes V_a, beta_a and the energy flux base Qb plus
 // omega1 sum_a H_a rho_a V_a to the per-node record.
-template <int M>
+template <int M, int W>
 __device__ __forceinline__ void stefan_maxwell(const LatDev& L, int node, const LocalLds& ls, double T, double rho,
-                                               double common, double omega1, const double* Y, const double* Qb) {
+                                               double common, double omega1, const double* Y, const double* Qb,
+                                               double rho_over_rhoY) {
     MechC mc0 = *as_const(L.mech);
     const size_t N = (size_t)L.N;
     RLBM_GLOBAL double* prm = as_global(L.prm);
@@ -240,6 +253,14 @@ __device__ __forceinline__ void stefan_maxwell(const LatDev& L, int node, const 
         for (int dd = 0; dd < 3; ++dd) diff[dd] += hy * V[a][dd];
     }
     (void)rho;
+    // rho Y_a = rho_a, except in the weakly coupled storage where Y_a is
+    // normalised by sum_b rho_b
+    if constexpr (W) {
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) diff[dd] *= rho_over_rhoY;
+    } else {
+        (void)rho_over_rhoY;
+    }
 #pragma unroll
     for (int dd = 0; dd < 3; ++dd) st_at(prm + (PRM_QB + dd) * N, node, Qb[dd] + omega1 * diff[dd]);
 }
@@ -304,12 +325,13 @@ __device__ __forceinline__ S ld_win(const RLBM_GLOBAL S* win, unsigned plane, in
 // interface node and every population is pulled from the source buffer;
 // IF = true: interface lanes read their reconstructed populations from the
 // boundary buffer instead.
-template <int M, typename S, bool IF>
+template <int M, typename S, int W, bool IF>
 __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, int node, const PullOff& o,
                                               const LocalLds& ls, LocalMoments<M>& m) {
+    constexpr int NSP = Lat<M, W>::NSP, LF = Lat<M, W>::LF, LG = Lat<M, W>::LG, NL = Lat<M, W>::NL;
     const size_t N = (size_t)L.N;
     const int nif = L.n_if;
-    const int s = L.slaved;
+    const int s = W ? M : L.slaved;
     const RLBM_GLOBAL S* src = as_global(static_cast<const S*>(L.pop[par]));
     const RLBM_GLOBAL S* bc = as_global(static_cast<const S*>(L.bcbuf));
     RLBM_GLOBAL double* prm = as_global(L.prm);
@@ -337,8 +359,8 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
-        const double f = (double)ld(M - 1, i);
-        const double g = (double)ld(M, i);
+        const double f = (double)ld(LF, i);
+        const double g = (double)ld(LG, i);
         rho += f;
         rhoE += g;
         if (cx) { j[0] += cx > 0 ? f : -f; Pd[0] += f; q[0] += cx > 0 ? g : -g; }
@@ -350,13 +372,13 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
     }
     if constexpr (sizeof(S) == 4) {
         const RLBM_CONST double* G = as_const(L.ref);
-        const double sf = (double)sc[M - 1];
-        rho += sf * G[REF_M0<M> + M - 1];
-        rhoE += (double)sc[M] * G[REF_M0<M> + M] + sf * G[REF_K0<M>];
-        const double p2 = sf * G[REF_M2<M>];
+        const double sf = (double)sc[LF];
+        rho += sf * G[REF_M0<NL> + LF];
+        rhoE += (double)sc[LG] * G[REF_M0<NL> + LG] + sf * G[REF_K0<NL>];
+        const double p2 = sf * G[REF_M2<NL>];
         Pd[0] += p2; Pd[1] += p2; Pd[2] += p2;
-        so[M - 1] = __double2float_rn(rho);
-        so[M] = __double2float_rn(rhoE);
+        so[LF] = __double2float_rn(rho);
+        so[LG] = __double2float_rn(rhoE);
     }
     const double inv_rho = 1.0 / rho;
     const double u[3] = {j[0] * inv_rho, j[1] * inv_rho, j[2] * inv_rho};
@@ -383,11 +405,11 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
         for (int i = 0; i < Q; ++i) cur[i] = ld(0, i);
     }
 #pragma unroll 1
-    for (int l = 0; l < M - 1; ++l) {
+    for (int l = 0; l < NSP; ++l) {
         reload_barrier();
         S nxt[Q];
         if constexpr (PF) {
-            if (l + 1 < M - 1) {
+            if (l + 1 < NSP) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) nxt[i] = ld(l + 1, i);
             }
@@ -406,11 +428,11 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
             if (cz) jz += cz > 0 ? v : -v;
         }
         if constexpr (sizeof(S) == 4) {
-            const RLBM_CONST double* rm = as_const(L.ref) + REF_M0<M> + opaque_zero();
+            const RLBM_CONST double* rm = as_const(L.ref) + REF_M0<NL> + opaque_zero();
             ra += (double)sc[l] * rm[l];
             so[l] = __double2float_rn(ra);
         }
-        const int a = l + (l >= s ? 1 : 0);
+        const int a = W ? l : l + (l >= s ? 1 : 0);
         put_species(a, ra, jx, jy, jz);
         rs -= ra; js[0] -= jx; js[1] -= jy; js[2] -= jz;
         if constexpr (PF) {
@@ -418,7 +440,7 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
             for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
         }
     }
-    put_species(s, rs, js[0], js[1], js[2]);
+    if constexpr (!W) put_species(s, rs, js[0], js[1], js[2]);
     // the species densities come back from LDS rather than being held in
     // registers through the loop
 #pragma unroll
@@ -431,7 +453,7 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
     }
 }
 
-template <int M, typename S>
+template <int M, typename S, int W>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_local(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                                int n_lat, long long t, int* __restrict__ flag) {
     const int b = xcd_block();
@@ -453,8 +475,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     __shared__ double s_ra[M][LOC_T], s_dv[3 * M][LOC_T];
     const LocalLds ls{&s_ra[0][threadIdx.x], &s_dv[0][threadIdx.x]};
     LocalMoments<M> m;
-    if (__builtin_amdgcn_ballot_w64(k >= 0) != 0) local_moments<M, S, true>(L, par, k, node, o, ls, m);
-    else local_moments<M, S, false>(L, par, k, node, o, ls, m);
+    if (__builtin_amdgcn_ballot_w64(k >= 0) != 0) local_moments<M, S, W, true>(L, par, k, node, o, ls, m);
+    else local_moments<M, S, W, false>(L, par, k, node, o, ls, m);
     const double rho = m.rho, inv_rho = 1.0 / rho;
     const double u[3] = {m.u[0], m.u[1], m.u[2]};
     const double rhoE = m.rhoE;
@@ -464,9 +486,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const double* Po = m.Po;
 
     const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    // composition: Y_a = rho_a / rho, or rho_a / sum_b rho_b in the weakly
+    // coupled storage, where the species supply the composition and the
+    // momentum lattice rho
+    double rhoY = rho;
+    if constexpr (W) {
+        rhoY = 0.0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) rhoY += rho_a[a];
+    }
+    const double inv_rhoY = W ? 1.0 / rhoY : inv_rho;
     double Y[M];
 #pragma unroll
-    for (int a = 0; a < M; ++a) Y[a] = rho_a[a] * inv_rho;
+    for (int a = 0; a < M; ++a) Y[a] = rho_a[a] * inv_rhoY;
     const double U = rhoE * inv_rho - 0.5 * usq;
     int fail = 0;
     // temperature (eq. temperature), Newton from the previous step's value
@@ -532,7 +564,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     prm[PRM_COMMON * N + node] = common;
     prm[PRM_WQ * N + node] = omega - omega1;
     prm[PRM_CC * N + node] = 0.5 * (2.0 - omega1) * P;
-    stefan_maxwell<M>(L, node, ls, T, rho, common, omega1, Y, Qb);
+    stefan_maxwell<M, W>(L, node, ls, T, rho, common, omega1, Y, Qb, rho * inv_rhoY);
 }
 
 // ---------------------------------------------------------------------------
@@ -607,7 +639,14 @@ __device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const
     double rho_a[M], fin[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) rho_a[a] = prm[(PRM_SP + 6 * a) * N + node];
-    const double rho = prm[PRM_RHO * N + node];
+    // the density that normalises the composition (sum_a rho_a in the
+    // weakly coupled storage)
+    double rho = prm[PRM_RHO * N + node];
+    if (L.weak) {
+        rho = 0.0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) rho += rho_a[a];
+    }
     const double U = prm[PRM_UINT * N + node];
     const double T = prm[PRM_T * N + node];
     int fail = 0;
@@ -684,12 +723,13 @@ __device__ __forceinline__ void geq_wk(int c, double u, double th, double& W, do
 }
 
 
-template <int M, typename S>
+template <int M, typename S, int W>
 __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                                         int n_lat, long long t, int* __restrict__ flag) {
     constexpr int NR = prm_rows(M);
-    constexpr int NL = M + 1;        // stored lattices
-    constexpr int NS = sizeof(S) == 4 ? M + 1 : 1;
+    constexpr int NSP = Lat<M, W>::NSP, LF = Lat<M, W>::LF, LG = Lat<M, W>::LG;
+    constexpr int NL = Lat<M, W>::NL;   // stored lattices
+    constexpr int NS = sizeof(S) == 4 ? NL : 1;
     __shared__ double sp[NR][UPD_NODES];
     __shared__ float ssc[NS][UPD_NODES];     // FP32 storage: this node's reference scales
     const int b = xcd_block();
@@ -703,7 +743,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
     const int node = node0 + lane;
     const int N = (int)L.N;
     const bool valid = node < N;
-    const int s = L.slaved;
+    const int s = W ? M : L.slaved;
     const int par = (L.parity0 + t) & 1;
     const RLBM_GLOBAL S* src = as_global(static_cast<const S*>(L.pop[par]));
     RLBM_GLOBAL S* dst = as_global(static_cast<S*>(L.pop[par ^ 1]));
@@ -726,7 +766,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
             int srow = row;
             if (row >= PRM_SP && row < prm_grad(M)) {
                 const int slot = (row - PRM_SP) / 6, c = (row - PRM_SP) % 6;
-                const int a = slot < M - 1 ? slot + (slot >= s ? 1 : 0) : s;
+                const int a = W ? slot : (slot < M - 1 ? slot + (slot >= s ? 1 : 0) : s);
                 srow = PRM_SP + 6 * a + c;
             }
             v[q] = ld_at(prm + (size_t)(row < NR ? srow : 0) * L.N, nd);   // unconditional: no waits between
@@ -805,7 +845,17 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
         const double w = sp[PRM_OMEGA][lane];
         return (2.0 - w) / (2.0 * sp[PRM_RHO][lane] * w);
     }();
-    const double fcm = sp[PRM_COMMON][lane] / sp[PRM_RHO][lane];   // F_ai = common Y_a sum_b K_ab D_bi
+    // F_ai = common Y_a sum_b K_ab D_bi with Y_a = rho_a / rho, or
+    // rho_a / sum_b rho_b in the weakly coupled storage
+    const double fcm = [&] {
+        double ry = sp[PRM_RHO][lane];
+        if constexpr (W) {
+            ry = 0.0;
+#pragma unroll
+            for (int q = 0; q < M; ++q) ry += sp[PRM_SP + 6 * q][lane];
+        }
+        return sp[PRM_COMMON][lane] / ry;
+    }();
     const PsiCoef pz = psi_coef(c2);
 
 #pragma unroll 1
@@ -870,7 +920,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
             }
             // species (eq. finalNumericalEquationsReactive with eq. fStar)
 #pragma unroll
-            for (int j = 0; j < M - 1; ++j) {
+            for (int j = 0; j < NSP; ++j) {
                 reload_barrier();
                 double F = 0.0;
 #pragma unroll
@@ -878,11 +928,11 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
                     if (q != j) F = fma(Ks[j * M + q], D[q], F);
                 const double ra = sp[PRM_SP + 6 * j][lane], be = sp[PRM_SP + 6 * j + 4][lane],
                              dr = sp[PRM_SP + 6 * j + 5][lane];
-                const double W = psi_c<c0>(ux, fma(ux, ux, Ra[j] * T)) * YZe[j];   // W_ji, recomputed
+                const double Wj = psi_c<c0>(ux, fma(ux, ux, Ra[j] * T)) * YZe[j];   // W_ji, recomputed
                 const int li = j * Q + i;
                 double f = (double)fin[j];
                 if constexpr (sizeof(S) == 4) f += ref_of(ssc[j][lane], ref[li]);
-                const double out = f + 2.0 * be * (ra * W - f) + (be - 1.0) * (fcm * ra * F) + W * dr;
+                const double out = f + 2.0 * be * (ra * Wj - f) + (be - 1.0) * (fcm * ra * F) + Wj * dr;
                 if constexpr (sizeof(S) == 4)
                     st_at(dst + (size_t)li * L.N, node, __double2float_rn(out - ref_of(srd[j], ref[li])));
                 else st_at(dst + (size_t)li * L.N, node, out);
@@ -890,21 +940,21 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
             const double rho = sp[PRM_RHO][lane], th = sp[PRM_TH][lane], omega = sp[PRM_OMEGA][lane];
             // momentum lattice, extended equilibrium (eqs. f, feqmix, Pex)
             {
-                const int li = (M - 1) * Q + i;
-                double f = (double)fin[M - 1];
-                if constexpr (sizeof(S) == 4) f += ref_of(ssc[M - 1][lane], ref[li]);
+                const int li = LF * Q + i;
+                double f = (double)fin[LF];
+                if constexpr (sizeof(S) == 4) f += ref_of(ssc[LF][lane], ref[li]);
                 const double fe = rho * psi_c<c0>(ux, th + ux * ux + exf * sp[GR][lane]) * Fyz;
                 const double out = f + omega * (fe - f);
                 if constexpr (sizeof(S) == 4)
-                    st_at(dst + (size_t)li * L.N, node, __double2float_rn(out - ref_of(srd[M - 1], ref[li])));
+                    st_at(dst + (size_t)li * L.N, node, __double2float_rn(out - ref_of(srd[LF], ref[li])));
                 else st_at(dst + (size_t)li * L.N, node, out);
             }
             // energy lattice (eqs. g, geq_i, gstar)
             {
-                const int li = M * Q + i;
-                double g = (double)fin[M];
+                const int li = LG * Q + i;
+                double g = (double)fin[LG];
                 if constexpr (sizeof(S) == 4)
-                    g += ref_g(ssc[M][lane], ssc[M - 1][lane], ref[li], ref[REF_K<M> + i]);
+                    g += ref_g(ssc[LG][lane], ssc[LF][lane], ref[li], ref[REF_K<NL> + i]);
                 const double ux2 = ux * ux;
                 const double Wx = psi_c<c0>(ux, th + ux2);
                 double kx;
@@ -934,7 +984,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
                 }
                 if constexpr (sizeof(S) == 4)
                     st_at(dst + (size_t)li * L.N, node,
-                          __double2float_rn(out - ref_g(srd[M], srd[M - 1], ref[li], ref[REF_K<M> + i])));
+                          __double2float_rn(out - ref_g(srd[LG], srd[LF], ref[li], ref[REF_K<NL> + i])));
                 else st_at(dst + (size_t)li * L.N, node, out);
             }
 #pragma unroll
@@ -968,10 +1018,11 @@ __device__ __forceinline__ void eq_prepare(MechC mc, EqState<M, SPV>& e, double 
     e.U = mix_U<M>(mc, e.Y, T);
 }
 
-template <int M, bool SPV>
+template <int M, int W, bool SPV>
 __device__ __forceinline__ double eq_value(MechC mc, const EqState<M, SPV>& e, int l, int slaved, int i) {
+    constexpr int LF = Lat<M, W>::LF, LG = Lat<M, W>::LG;
     const int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);
-    if (l == M) {
+    if (l == LG) {
         GeqAxis gx, gy, gz;
         geq_axis(e.u[0], e.th, gx);
         geq_axis(e.u[1], e.th, gy);
@@ -981,10 +1032,10 @@ __device__ __forceinline__ double eq_value(MechC mc, const EqState<M, SPV>& e, i
         const double Wz = sel3d(c2, gz.W[0], gz.W[1], gz.W[2]), kz = sel3d(c2, gz.k[0], gz.k[1], gz.k[2]);
         return e.rho * (e.U * Wx * Wy * Wz + kx * Wy * Wz + Wx * (ky * Wz + Wy * kz));
     }
-    if (l == M - 1)
+    if (l == LF)
         return e.rho * psi(c0, e.u[0], e.u[0] * e.u[0] + e.th) * psi(c1, e.u[1], e.u[1] * e.u[1] + e.th) *
                psi(c2, e.u[2], e.u[2] * e.u[2] + e.th);
-    const int a = l + (l >= slaved ? 1 : 0);
+    const int a = W ? l : l + (l >= slaved ? 1 : 0);
     double Ya = 0.0, tha = 0.0, w0 = e.u[0], w1 = e.u[1], w2 = e.u[2];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
@@ -1076,7 +1127,7 @@ __device__ __forceinline__ void bc_eq(MechC mc, const BcState<M, SPV>& e, int c0
 // moments of the populations with the incoming links set to the imposed
 // equilibrium A, outgoing links from advection (pa, pf, pg: this lane's
 // streamed values by species / momentum / energy lattice).
-template <int M, bool SPV, bool ASPV>
+template <int M, int W, bool SPV, bool ASPV>
 __device__ __forceinline__ void bc_local(MechC mc, const BcState<M, ASPV>& A, int s, bool act, bool in, int c0,
                                          int c1, int c2, const double* pa, double pf, double pg,
                                          BcState<M, SPV>& Lc, int* fail) {
@@ -1108,9 +1159,15 @@ __device__ __forceinline__ void bc_local(MechC mc, const BcState<M, ASPV>& A, in
     Lc.rho = rl;
 #pragma unroll
     for (int dd = 0; dd < 3; ++dd) Lc.u[dd] = jl[dd] / rl;
+    double ry = rl;   // the weakly coupled storage normalises Y by sum_a rho_a
+    if constexpr (W) {
+        ry = 0.0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) ry += ra[a];
+    }
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-        Lc.Y[a] = ra[a] / rl;
+        Lc.Y[a] = ra[a] / ry;
         if constexpr (SPV) {
             const bool small = ra[a] <= 1e-14 * rl;
 #pragma unroll
@@ -1124,7 +1181,7 @@ __device__ __forceinline__ void bc_local(MechC mc, const BcState<M, ASPV>& A, in
 
 constexpr int BC_THREADS = 32 * BC_NODES;
 
-template <int M, typename S>
+template <int M, typename S, int W>
 __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_boundary(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                                          int n_lat, long long t, int* __restrict__ flag) {
     const int b = xcd_block();
@@ -1143,7 +1200,8 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
     const unsigned Dm = L.if_mask[k];
     const bool in = act && ((Dm >> i) & 1u);      // incoming link (set D)
     const int type = L.if_type[k];
-    const int s = L.slaved;
+    constexpr int LF = Lat<M, W>::LF, LG = Lat<M, W>::LG, NL = Lat<M, W>::NL;
+    const int s = W ? M : L.slaved;
     const size_t N = (size_t)L.N;
     const int x = node % L.nx, r = node / L.nx, y = r % L.ny, z = r / L.ny;
     PullOff o;
@@ -1165,16 +1223,16 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
     // FP32 deviation storage: the advected value's reference belongs to this
     // node; a bounce-back source f'_{opp(i)}(x) is referred to the node that
     // would pull it, the pull source x - c_i (wrapped)
-    float s_ld[M + 1], s_own[M + 1];
+    float s_ld[NL], s_own[NL];
     if constexpr (sizeof(S) == 4) {
         const RLBM_GLOBAL float* a0 = scale_at(L, par, bbl ? off : node);
         const RLBM_GLOBAL float* a1 = scale_at(L, par, node);
 #pragma unroll
-        for (int l = 0; l <= M; ++l) { s_ld[l] = a0[l]; s_own[l] = a1[l]; }
+        for (int l = 0; l < NL; ++l) { s_ld[l] = a0[l]; s_own[l] = a1[l]; }
     }
     auto refv = [&](const float* sc, int l, int li) -> double {
         if constexpr (sizeof(S) == 4)
-            return l < M ? ref_of(sc[l], G[li]) : ref_g(sc[M], sc[M - 1], G[li], G[REF_K<M> + li % Q]);
+            return l < LG ? ref_of(sc[l], G[li]) : ref_g(sc[LG], sc[LF], G[li], G[REF_K<NL> + li % Q]);
         else return 0.0;
     };
     double pa[M], pf = 0.0, pg = 0.0;
@@ -1182,19 +1240,19 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
     for (int a = 0; a < M; ++a) {
         pa[a] = 0.0;
         if (a == s || !need) continue;
-        const int l = lat_of<M>(a, s);
+        const int l = lat_of(a, s);
         const int li = l * Q + ld_i;
         pa[a] = Codec<S>::ld(src, (size_t)li * N + ld_off, refv(s_ld, l, li));
     }
     if (need) {
-        const int lf = (M - 1) * Q + ld_i;
-        pf = Codec<S>::ld(src, (size_t)lf * N + ld_off, refv(s_ld, M - 1, lf));
+        const int lf = LF * Q + ld_i;
+        pf = Codec<S>::ld(src, (size_t)lf * N + ld_off, refv(s_ld, LF, lf));
         if (!in) {
-            const int lg = M * Q + i;
-            pg = Codec<S>::ld(src, (size_t)lg * N + off, refv(s_own, M, lg));
+            const int lg = LG * Q + i;
+            pg = Codec<S>::ld(src, (size_t)lg * N + off, refv(s_own, LG, lg));
         } else if (bback) {
-            const int lg = M * Q + ld_i;
-            pg = Codec<S>::ld(src, (size_t)lg * N + ld_off, refv(s_ld, M, lg));
+            const int lg = LG * Q + ld_i;
+            pg = Codec<S>::ld(src, (size_t)lg * N + ld_off, refv(s_ld, LG, lg));
         }
     }
     auto put = [&](int l, double val) {
@@ -1207,9 +1265,9 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
         // opposite population of the same node, outgoing links keep theirs
 #pragma unroll
         for (int a = 0; a < M; ++a)
-            if (a != s) put(lat_of<M>(a, s), pa[a]);
-        put(M - 1, pf);
-        put(M, pg);
+            if (a != s) put(lat_of(a, s), pa[a]);
+        put(LF, pf);
+        put(LG, pg);
     } else if (wall) {
         // Tamm-Mott-Smith wall (section 4.2.2)
         BcState<M, false> A;   // target: bounce-back rho and Y (eqs. BBrho, BBY), u^tgt = 0, T^tgt
@@ -1223,24 +1281,31 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
                 rY[a] = hsum32(pa[a]);
                 rs -= rY[a];
             }
+            // the weakly coupled storage normalises Y by sum_a rho_a
+            double ry = rb;
+            if constexpr (W) {
+                ry = 0.0;
 #pragma unroll
-            for (int a = 0; a < M; ++a) A.Y[a] = (a == s ? rs : rY[a]) / rb;
+                for (int a = 0; a < M; ++a) ry += rY[a];
+            }
+#pragma unroll
+            for (int a = 0; a < M; ++a) A.Y[a] = (a == s ? rs : rY[a]) / ry;
             A.rho = rb;
             A.u[0] = A.u[1] = A.u[2] = 0.0;
             bc_prepare<M, false>(mc, A, L.if_T[k]);
         }
         // step 3: local state with species velocities (eqs. locRho .. locT)
         BcState<M, true> Lc;
-        bc_local<M, true, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
+        bc_local<M, W, true, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
         // step 4 (eqs. ftms, gtms, fatms)
         double eA[M], fA, gA, eL[M], fL, gL;
         bc_eq<M, false>(mc, A, c0, c1, c2, eA, fA, gA);
         bc_eq<M, true>(mc, Lc, c0, c1, c2, eL, fL, gL);
 #pragma unroll
         for (int a = 0; a < M; ++a)
-            if (a != s) put(lat_of<M>(a, s), in ? 2.0 * eA[a] - eL[a] : eA[a] + pa[a] - eL[a]);
-        put(M - 1, in ? 2.0 * fA - fL : fA + pf - fL);
-        put(M, in ? 2.0 * gA - gL : gA + pg - gL);
+            if (a != s) put(lat_of(a, s), in ? 2.0 * eA[a] - eL[a] : eA[a] + pa[a] - eL[a]);
+        put(LF, in ? 2.0 * fA - fL : fA + pf - fL);
+        put(LG, in ? 2.0 * gA - gL : gA + pg - gL);
     } else if (type == RLBM_FACE_INLET_LOCAL) {
         // simplified flux inlet (end of section 4.3): the local state of step 2
         // with the incoming links at the inlet equilibrium, and every
@@ -1252,14 +1317,14 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
         for (int a = 0; a < M; ++a) A.Y[a] = L.Y_in[a];
         bc_prepare<M, false>(mc, A, L.T_in);
         BcState<M, false> Lc;
-        bc_local<M, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
+        bc_local<M, W, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
         double eL[M], fL, gL;
         bc_eq<M, false>(mc, Lc, c0, c1, c2, eL, fL, gL);
 #pragma unroll
         for (int a = 0; a < M; ++a)
-            if (a != s) put(lat_of<M>(a, s), eL[a]);
-        put(M - 1, fL);
-        put(M, gL);
+            if (a != s) put(lat_of(a, s), eL[a]);
+        put(LF, fL);
+        put(LG, gL);
     } else if (type == RLBM_FACE_INLET) {
         // flux inlet (section 4.3)
         BcState<M, false> A;   // inlet equilibrium (eqs. in_f, in_g, in_fa)
@@ -1269,7 +1334,7 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
         for (int a = 0; a < M; ++a) A.Y[a] = L.Y_in[a];
         bc_prepare<M, false>(mc, A, L.T_in);
         BcState<M, false> Lc;  // local state (eqs. inletlocRho .. inletlocT)
-        bc_local<M, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
+        bc_local<M, W, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
         // target: local density and composition at the imposed u, T (eqs. in_tgt_*)
         BcState<M, false> Tg;
         Tg.rho = Lc.rho;
@@ -1284,9 +1349,9 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
         bc_eq<M, false>(mc, Tg, c0, c1, c2, eT, fT, gT);
 #pragma unroll
         for (int a = 0; a < M; ++a)
-            if (a != s) put(lat_of<M>(a, s), eT[a] + (in ? eA[a] : pa[a]) - eL[a]);
-        put(M - 1, fT + (in ? fA : pf) - fL);
-        put(M, gT + (in ? gA : pg) - gL);
+            if (a != s) put(lat_of(a, s), eT[a] + (in ? eA[a] : pa[a]) - eL[a]);
+        put(LF, fT + (in ? fA : pf) - fL);
+        put(LG, gT + (in ? gA : pg) - gL);
     } else {
         // outlet (section 4.4): LODI state from the previous outlet state and
         // the previous post-boundary moments of the first interior node
@@ -1345,16 +1410,16 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
             }
         }
         BcState<M, false> Lc;  // local state (eqs. outletlocRho .. outletlocT)
-        bc_local<M, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
+        bc_local<M, W, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
         // (eqs. f_outlet, g_outlet, fa_outlet)
         double eA[M], fA, gA, eL[M], fL, gL;
         bc_eq<M, false>(mc, A, c0, c1, c2, eA, fA, gA);
         bc_eq<M, false>(mc, Lc, c0, c1, c2, eL, fL, gL);
 #pragma unroll
         for (int a = 0; a < M; ++a)
-            if (a != s) put(lat_of<M>(a, s), in ? 2.0 * eA[a] - eL[a] : eA[a] + pa[a] - eL[a]);
-        put(M - 1, in ? 2.0 * fA - fL : fA + pf - fL);
-        put(M, in ? 2.0 * gA - gL : gA + pg - gL);
+            if (a != s) put(lat_of(a, s), in ? 2.0 * eA[a] - eL[a] : eA[a] + pa[a] - eL[a]);
+        put(LF, in ? 2.0 * fA - fL : fA + pf - fL);
+        put(LG, in ? 2.0 * gA - gL : gA + pg - gL);
     }
     if (fail && v == 0) atomicOr(flag, 1);
 }
@@ -1374,21 +1439,22 @@ __device__ __forceinline__ long long reader_of(const LatDev& L, long long node, 
 }
 
 // Reference value of slot (node, i) of lattice l in buffer q (FP32 storage).
-template <int M, typename S>
+template <int M, typename S, int W>
 __device__ __forceinline__ double slot_ref(const LatDev& L, int q, long long node, int l, int i) {
     if constexpr (sizeof(S) == 8) {
         return 0.0;
     } else {
+        constexpr int LF = Lat<M, W>::LF, LG = Lat<M, W>::LG, NL = Lat<M, W>::NL;
         const RLBM_CONST double* G = as_const(L.ref);
         const RLBM_GLOBAL float* sc = scale_at(L, q, reader_of(L, node, i));
-        if (l == M) return ref_g(sc[M], sc[M - 1], G[l * Q + i], G[REF_K<M> + i]);
+        if (l == LG) return ref_g(sc[LG], sc[LF], G[l * Q + i], G[REF_K<NL> + i]);
         return ref_of(sc[l], G[l * Q + i]);
     }
 }
 
 // Reference scales of the initial populations: the zeroth moments rho_a of
 // the stored species, rho and rho E.
-template <int M>
+template <int M, int W>
 __global__ __launch_bounds__(256) void k_scale_init(const LatDev* __restrict__ lat, const double* __restrict__ rho_in,
                                                     const double* __restrict__ u_in, const double* __restrict__ T_in,
                                                     const double* __restrict__ Y_in) {
@@ -1397,24 +1463,25 @@ __global__ __launch_bounds__(256) void k_scale_init(const LatDev* __restrict__ l
     if (node >= L.N) return;
     MechC mc = *as_const(L.mech);
     const size_t N = (size_t)L.N;
-    const int s = L.slaved;
+    constexpr int NSP = Lat<M, W>::NSP, LF = Lat<M, W>::LF, LG = Lat<M, W>::LG;
+    const int s = W ? M : L.slaved;
     const double rho = rho_in[node];
     float* so = L.rscale[L.parity0] + (size_t)node * L.rss;
     double Y[M];
 #pragma unroll
     for (int a = 0; a < M; ++a) Y[a] = Y_in[a * N + node];
-    for (int l = 0; l < M - 1; ++l) {
-        const int a = l + (l >= s ? 1 : 0);
+    for (int l = 0; l < NSP; ++l) {
+        const int a = W ? l : l + (l >= s ? 1 : 0);
         so[l] = __double2float_rn(rho * Y_in[a * N + node]);
     }
-    so[M - 1] = __double2float_rn(rho);
+    so[LF] = __double2float_rn(rho);
     double usq = 0.0;
 #pragma unroll
     for (int dd = 0; dd < 3; ++dd) usq += u_in[dd * N + node] * u_in[dd * N + node];
-    so[M] = __double2float_rn(rho * (mix_U<M>(mc, Y, T_in[node]) + 0.5 * usq));
+    so[LG] = __double2float_rn(rho * (mix_U<M>(mc, Y, T_in[node]) + 0.5 * usq));
 }
 
-template <int M, typename S>
+template <int M, typename S, int W>
 __global__ __launch_bounds__(256) void k_init(const LatDev* __restrict__ lat, const double* __restrict__ rho_in,
                                               const double* __restrict__ u_in, const double* __restrict__ T_in,
                                               const double* __restrict__ Y_in) {
@@ -1432,11 +1499,11 @@ __global__ __launch_bounds__(256) void k_init(const LatDev* __restrict__ lat, co
 #pragma unroll
     for (int a = 0; a < M; ++a) e.Y[a] = Y_in[a * N + node];
     eq_prepare<M, false>(mc, e, T);
-    for (int l = 0; l <= M; ++l)
+    for (int l = 0; l < Lat<M, W>::NL; ++l)
         for (int i = 0; i < Q; ++i) {
             const int li = l * Q + i;
-            Codec<S>::st(dst, (size_t)li * N + node, eq_value<M, false>(mc, e, l, L.slaved, i),
-                         slot_ref<M, S>(L, L.parity0, node, l, i));
+            Codec<S>::st(dst, (size_t)li * N + node, eq_value<M, W, false>(mc, e, l, L.slaved, i),
+                         slot_ref<M, S, W>(L, L.parity0, node, l, i));
         }
     double* aux = L.aux;
     aux[AUX_RHO * N + node] = e.rho;
@@ -1469,45 +1536,47 @@ __global__ __launch_bounds__(256) void k_init(const LatDev* __restrict__ lat, co
 // domain-mean temperature and composition, and the energy lattice's theta^2
 // part K (eq. geq_i at u = 0 with rho = 1, U = 0); then the zeroth moments,
 // the momentum shape's sum_i G c_x^2 and sum_i K_i.
-template <int M>
+template <int M, int W>
 __global__ __launch_bounds__(512) void k_refs(const LatDev* __restrict__ lat, double* __restrict__ ref, double rho,
                                               double T, const double* __restrict__ Y) {
+    constexpr int NSP = Lat<M, W>::NSP, LF = Lat<M, W>::LF, LG = Lat<M, W>::LG, NL = Lat<M, W>::NL;
+    static_assert(NL * Q <= 512, "one thread per reference shape value");
     (void)rho;
     const LatDev& L = *lat;
     const int li = threadIdx.x;
     MechC mc = *as_const(L.mech);
     const double th_mix = mc.R_univ * mix_inv_m<M>(mc, Y) * T;
-    if (li < (M + 1) * Q) {
+    if (li < NL * Q) {
         const int l = li / Q, i = li % Q;
         const int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);
         double th = th_mix;
-        if (l < M - 1) th = mc.Ra[l + (l >= L.slaved ? 1 : 0)] * T;
+        if (l < NSP) th = mc.Ra[W ? l : l + (l >= L.slaved ? 1 : 0)] * T;
         // shapes are rounded to FP32 values (see ref_of)
         ref[li] = (double)(float)(psi(c0, 0.0, th) * psi(c1, 0.0, th) * psi(c2, 0.0, th));
-        if (l == M) {
+        if (l == LG) {
             const double Wx = psi(c0, 0.0, th), Wy = psi(c1, 0.0, th), Wz = psi(c2, 0.0, th);
             const double k0 = -th * th, k1 = 0.5 * th * th;
             const double kx = c0 ? k1 : k0, ky = c1 ? k1 : k0, kz = c2 ? k1 : k0;
-            ref[REF_K<M> + i] = (double)(float)(kx * Wy * Wz + Wx * (ky * Wz + Wy * kz));
+            ref[REF_K<NL> + i] = (double)(float)(kx * Wy * Wz + Wx * (ky * Wz + Wy * kz));
         }
     }
     __syncthreads();
-    if (li <= M) {
+    if (li < NL) {
         double m0 = 0.0;
         for (int i = 0; i < Q; ++i) m0 += ref[li * Q + i];
-        ref[REF_M0<M> + li] = m0;
-    } else if (li == M + 1) {
+        ref[REF_M0<NL> + li] = m0;
+    } else if (li == NL) {
         double m2 = 0.0;
-        for (int i = 0; i < Q; ++i) m2 += ref[(M - 1) * Q + i] * (double)(cx_of(i) * cx_of(i));
-        ref[REF_M2<M>] = m2;
-    } else if (li == M + 2) {
+        for (int i = 0; i < Q; ++i) m2 += ref[LF * Q + i] * (double)(cx_of(i) * cx_of(i));
+        ref[REF_M2<NL>] = m2;
+    } else if (li == NL + 1) {
         double k0 = 0.0;
-        for (int i = 0; i < Q; ++i) k0 += ref[REF_K<M> + i];
-        ref[REF_K0<M>] = k0;
+        for (int i = 0; i < Q; ++i) k0 += ref[REF_K<NL> + i];
+        ref[REF_K0<NL>] = k0;
     }
 }
 
-template <int M, typename S>
+template <int M, typename S, int W>
 __global__ __launch_bounds__(256) void k_fields(const LatDev* __restrict__ lat, long long t, double* rho_o,
                                                 double* u_o, double* T_o, double* Y_o, double* P_o,
                                                 int* __restrict__ flag) {
@@ -1518,29 +1587,36 @@ __global__ __launch_bounds__(256) void k_fields(const LatDev* __restrict__ lat, 
     const size_t N = (size_t)L.N;
     const int q = (L.parity0 + t) & 1;
     const void* src = L.pop[q];
-    const int s = L.slaved;
+    constexpr int LF = Lat<M, W>::LF, LG = Lat<M, W>::LG;
+    const int s = W ? M : L.slaved;
     double rho = 0.0, j[3] = {0.0, 0.0, 0.0}, rE = 0.0, ra[M];
     for (int i = 0; i < Q; ++i) {
-        const double f = Codec<S>::ld(src, (size_t)((M - 1) * Q + i) * N + node, slot_ref<M, S>(L, q, node, M - 1, i));
+        const double f = Codec<S>::ld(src, (size_t)(LF * Q + i) * N + node, slot_ref<M, S, W>(L, q, node, LF, i));
         rho += f; j[0] += f * cx_of(i); j[1] += f * cy_of(i); j[2] += f * cz_of(i);
-        rE += Codec<S>::ld(src, (size_t)(M * Q + i) * N + node, slot_ref<M, S>(L, q, node, M, i));
+        rE += Codec<S>::ld(src, (size_t)(LG * Q + i) * N + node, slot_ref<M, S, W>(L, q, node, LG, i));
     }
     double rs = rho;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
         ra[a] = 0.0;
         if (a == s) continue;
-        const int l = lat_of<M>(a, s);
+        const int l = lat_of(a, s);
         for (int i = 0; i < Q; ++i)
-            ra[a] += Codec<S>::ld(src, (size_t)(l * Q + i) * N + node, slot_ref<M, S>(L, q, node, l, i));
+            ra[a] += Codec<S>::ld(src, (size_t)(l * Q + i) * N + node, slot_ref<M, S, W>(L, q, node, l, i));
         rs -= ra[a];
     }
 #pragma unroll
     for (int a = 0; a < M; ++a)
         if (a == s) ra[a] = rs;
+    double ry = rho;   // the weakly coupled storage normalises Y by sum_a rho_a
+    if constexpr (W) {
+        ry = 0.0;
+#pragma unroll
+        for (int a = 0; a < M; ++a) ry += ra[a];
+    }
     double Y[M];
 #pragma unroll
-    for (int a = 0; a < M; ++a) Y[a] = ra[a] / rho;
+    for (int a = 0; a < M; ++a) Y[a] = ra[a] / ry;
     const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
     const double U = rE / rho - 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     int fail = 0;
@@ -1556,7 +1632,7 @@ __global__ __launch_bounds__(256) void k_fields(const LatDev* __restrict__ lat, 
     if (P_o) P_o[node] = rho * mc.R_univ * mix_inv_m<M>(mc, Y) * T;
 }
 
-template <int M, typename S>
+template <int M, typename S, int W>
 __global__ __launch_bounds__(256) void k_pops(const LatDev* __restrict__ lat, long long t, int nl, double* buf,
                                               int write) {
     const LatDev& L = *lat;
@@ -1567,20 +1643,21 @@ __global__ __launch_bounds__(256) void k_pops(const LatDev* __restrict__ lat, lo
     const long long node = (long long)(idx % L.N);
     const int q = (L.parity0 + t) & 1;
     void* p = L.pop[q];
-    const double ref = slot_ref<M, S>(L, q, node, li / Q, li % Q);
+    const double ref = slot_ref<M, S, W>(L, q, node, li / Q, li % Q);
     if (write) Codec<S>::st(p, idx, buf[idx], ref);
     else buf[idx] = Codec<S>::ld(p, idx, ref);
 }
 
 // Per-block partial sums of the invariants; nv = 6 + E values per block.
-template <int M, typename S>
+template <int M, typename S, int W>
 __global__ __launch_bounds__(256) void k_invariants(const LatDev* __restrict__ lat, long long t,
                                                     double* __restrict__ partial, int nv) {
     const LatDev& L = *lat;
     MechC mc = *as_const(L.mech);
     const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
     const size_t N = (size_t)L.N;
-    const int s = L.slaved;
+    constexpr int LF = Lat<M, W>::LF, LG = Lat<M, W>::LG;
+    const int s = W ? M : L.slaved;
     double v[6 + MAXE];
     for (int q = 0; q < 6 + MAXE; ++q) v[q] = 0.0;
     if (node < L.N) {
@@ -1590,8 +1667,8 @@ __global__ __launch_bounds__(256) void k_invariants(const LatDev* __restrict__ l
         double rho = 0.0;
         for (int i = 0; i < Q; ++i) {
             const double f =
-                Codec<S>::ld(src, (size_t)((M - 1) * Q + i) * N + node, slot_ref<M, S>(L, q, node, M - 1, i));
-            const double g = Codec<S>::ld(src, (size_t)(M * Q + i) * N + node, slot_ref<M, S>(L, q, node, M, i));
+                Codec<S>::ld(src, (size_t)(LF * Q + i) * N + node, slot_ref<M, S, W>(L, q, node, LF, i));
+            const double g = Codec<S>::ld(src, (size_t)(LG * Q + i) * N + node, slot_ref<M, S, W>(L, q, node, LG, i));
             if (!isfinite(f) || !isfinite(g)) bad = 1.0;
             rho += f;
             v[1] += f * cx_of(i); v[2] += f * cy_of(i); v[3] += f * cz_of(i);
@@ -1604,9 +1681,9 @@ __global__ __launch_bounds__(256) void k_invariants(const LatDev* __restrict__ l
         for (int a = 0; a < M; ++a) {
             ra[a] = 0.0;
             if (a == s) continue;
-            const int l = lat_of<M>(a, s);
+            const int l = lat_of(a, s);
             for (int i = 0; i < Q; ++i) {
-                const double f = Codec<S>::ld(src, (size_t)(l * Q + i) * N + node, slot_ref<M, S>(L, q, node, l, i));
+                const double f = Codec<S>::ld(src, (size_t)(l * Q + i) * N + node, slot_ref<M, S, W>(L, q, node, l, i));
                 if (!isfinite(f)) bad = 1.0;
                 ra[a] += f;
             }
@@ -1661,16 +1738,25 @@ __global__ void k_reduce_partials(const double* __restrict__ partial, int nblock
         case 9: { constexpr int MM = 9; __VA_ARGS__; break; } \
         default: return hipErrorInvalidValue;             \
     }
+// species count and storage coupling (WW = 1: weakly coupled, all M species stored)
+#define RLBM_DISPATCH_W(M_, W_, ...)                                                   \
+    if (W_) {                                                                          \
+        constexpr int WW = 1;                                                          \
+        RLBM_DISPATCH(M_, __VA_ARGS__)                                                 \
+    } else {                                                                           \
+        constexpr int WW = 0;                                                          \
+        RLBM_DISPATCH(M_, __VA_ARGS__)                                                 \
+    }
 
 template <typename S>
-static hipError_t launch_step_phase(int phase, int M, const StepLaunch& a) {
+static hipError_t launch_step_phase(int phase, int M, int weak, const StepLaunch& a) {
     if (a.blocks <= 0) return hipSuccess;
     if (phase == 0) {
-        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_boundary<MM, S>), dim3(a.blocks), dim3(BC_THREADS), 0, a.stream, a.lats,
-                                                a.blk, a.n_lat, a.t, a.flag))
+        RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_boundary<MM, S, WW>), dim3(a.blocks), dim3(BC_THREADS), 0,
+                                                    a.stream, a.lats, a.blk, a.n_lat, a.t, a.flag))
     } else if (phase == 1) {
-        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_local<MM, S>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
-                                                a.blk, a.n_lat, a.t, a.flag))
+        RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_local<MM, S, WW>), dim3(a.blocks), dim3(256), 0, a.stream,
+                                                    a.lats, a.blk, a.n_lat, a.t, a.flag))
     } else if (phase == 2) {
         if (a.schemes & (1u << RLBM_REACTION_EXPLICIT))
             RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
@@ -1679,81 +1765,84 @@ static hipError_t launch_step_phase(int phase, int M, const StepLaunch& a) {
             RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem_implicit<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
                                                     a.blk, a.n_lat, a.t, a.flag))
     } else {
-        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_update<MM, S>), dim3(a.blocks), dim3(UPD_THREADS), 0, a.stream, a.lats,
-                                                a.blk, a.n_lat, a.t, a.flag))
+        RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_update<MM, S, WW>), dim3(a.blocks), dim3(UPD_THREADS), 0,
+                                                    a.stream, a.lats, a.blk, a.n_lat, a.t, a.flag))
     }
     return hipGetLastError();
 }
 
-hipError_t launch_phase(int phase, int M, int storage, const StepLaunch& a) {
-    return storage == RLBM_STORAGE_F32_DEV ? launch_step_phase<float>(phase, M, a)
-                                           : launch_step_phase<double>(phase, M, a);
+hipError_t launch_phase(int phase, int M, int storage, int weak, const StepLaunch& a) {
+    return storage == RLBM_STORAGE_F32_DEV ? launch_step_phase<float>(phase, M, weak, a)
+                                           : launch_step_phase<double>(phase, M, weak, a);
 }
 
 template <typename S>
-static hipError_t launch_init_t(int M, const LatDev* lat, long long N, const double* rho, const double* u,
-                                const double* T, const double* Y, hipStream_t st) {
+static hipError_t launch_init_t(int M, int weak, const LatDev* lat, long long N, const double* rho,
+                                const double* u, const double* T, const double* Y, hipStream_t st) {
     const int blocks = (int)((N + 255) / 256);
-    if constexpr (sizeof(S) == 4)
-        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_scale_init<MM>), dim3(blocks), dim3(256), 0, st, lat, rho, u, T, Y))
-    RLBM_DISPATCH(M, hipLaunchKernelGGL((k_init<MM, S>), dim3(blocks), dim3(256), 0, st, lat, rho, u, T, Y))
+    if constexpr (sizeof(S) == 4) {
+        RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_scale_init<MM, WW>), dim3(blocks), dim3(256), 0, st, lat, rho,
+                                                    u, T, Y))
+    }
+    RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_init<MM, S, WW>), dim3(blocks), dim3(256), 0, st, lat, rho, u,
+                                                T, Y))
     return hipGetLastError();
 }
 
-hipError_t launch_init(int M, int storage, const LatDev* lat, long long N, const double* rho, const double* u,
-                       const double* T, const double* Y, hipStream_t st) {
-    return storage == RLBM_STORAGE_F32_DEV ? launch_init_t<float>(M, lat, N, rho, u, T, Y, st)
-                                           : launch_init_t<double>(M, lat, N, rho, u, T, Y, st);
+hipError_t launch_init(int M, int storage, int weak, const LatDev* lat, long long N, const double* rho,
+                       const double* u, const double* T, const double* Y, hipStream_t st) {
+    return storage == RLBM_STORAGE_F32_DEV ? launch_init_t<float>(M, weak, lat, N, rho, u, T, Y, st)
+                                           : launch_init_t<double>(M, weak, lat, N, rho, u, T, Y, st);
 }
 
-hipError_t launch_refs(int M, const LatDev* lat, double* ref, double rho, double T, const double* Y,
+hipError_t launch_refs(int M, int weak, const LatDev* lat, double* ref, double rho, double T, const double* Y,
                        hipStream_t st) {
-    RLBM_DISPATCH(M, hipLaunchKernelGGL((k_refs<MM>), dim3(1), dim3(512), 0, st, lat, ref, rho, T, Y))
+    RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_refs<MM, WW>), dim3(1), dim3(512), 0, st, lat, ref, rho, T, Y))
     return hipGetLastError();
 }
 
 template <typename S>
-static hipError_t launch_fields_t(int M, const LatDev* lat, long long N, long long t, double* rho, double* u,
-                                  double* T, double* Y, double* P, int* flag, hipStream_t st) {
+static hipError_t launch_fields_t(int M, int weak, const LatDev* lat, long long N, long long t, double* rho,
+                                  double* u, double* T, double* Y, double* P, int* flag, hipStream_t st) {
     const int blocks = (int)((N + 255) / 256);
-    RLBM_DISPATCH(M, hipLaunchKernelGGL((k_fields<MM, S>), dim3(blocks), dim3(256), 0, st, lat, t, rho, u, T,
-                                            Y, P, flag))
+    RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_fields<MM, S, WW>), dim3(blocks), dim3(256), 0, st, lat, t, rho,
+                                                u, T, Y, P, flag))
     return hipGetLastError();
 }
 
-hipError_t launch_fields(int M, int storage, const LatDev* lat, long long N, long long t, double* rho, double* u,
-                         double* T, double* Y, double* P, int* flag, hipStream_t st) {
-    return storage == RLBM_STORAGE_F32_DEV ? launch_fields_t<float>(M, lat, N, t, rho, u, T, Y, P, flag, st)
-                                           : launch_fields_t<double>(M, lat, N, t, rho, u, T, Y, P, flag, st);
+hipError_t launch_fields(int M, int storage, int weak, const LatDev* lat, long long N, long long t, double* rho,
+                         double* u, double* T, double* Y, double* P, int* flag, hipStream_t st) {
+    return storage == RLBM_STORAGE_F32_DEV ? launch_fields_t<float>(M, weak, lat, N, t, rho, u, T, Y, P, flag, st)
+                                           : launch_fields_t<double>(M, weak, lat, N, t, rho, u, T, Y, P, flag, st);
 }
 
-hipError_t launch_pops(int M, int storage, const LatDev* lat, long long N, int nl, long long t, double* buf,
-                       int write, hipStream_t st) {
+hipError_t launch_pops(int M, int storage, int weak, const LatDev* lat, long long N, int nl, long long t,
+                       double* buf, int write, hipStream_t st) {
     const size_t total = (size_t)nl * Q * (size_t)N;
     const int blocks = (int)((total + 255) / 256);
     if (storage == RLBM_STORAGE_F32_DEV)
-        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_pops<MM, float>), dim3(blocks), dim3(256), 0, st, lat, t, nl, buf,
-                                                write))
+        RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_pops<MM, float, WW>), dim3(blocks), dim3(256), 0, st, lat, t,
+                                                    nl, buf, write))
     else
-        RLBM_DISPATCH(M, hipLaunchKernelGGL((k_pops<MM, double>), dim3(blocks), dim3(256), 0, st, lat, t, nl, buf,
-                                                write))
+        RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_pops<MM, double, WW>), dim3(blocks), dim3(256), 0, st, lat, t,
+                                                    nl, buf, write))
     return hipGetLastError();
 }
 
 template <typename S>
-static hipError_t launch_inv_t(int M, const LatDev* lat, long long N, long long t, double* partial, int nv,
-                               double* out, hipStream_t st) {
+static hipError_t launch_inv_t(int M, int weak, const LatDev* lat, long long N, long long t, double* partial,
+                               int nv, double* out, hipStream_t st) {
     const int blocks = (int)((N + 255) / 256);
-    RLBM_DISPATCH(M, hipLaunchKernelGGL((k_invariants<MM, S>), dim3(blocks), dim3(256), 0, st, lat, t, partial,
-                                            nv))
+    RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_invariants<MM, S, WW>), dim3(blocks), dim3(256), 0, st, lat, t,
+                                                partial, nv))
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(64), 0, st, partial, blocks, nv, out);
     return hipGetLastError();
 }
 
-hipError_t launch_invariants(int M, int storage, const LatDev* lat, long long N, long long t, double* partial,
-                             int nv, double* out, hipStream_t st) {
-    return storage == RLBM_STORAGE_F32_DEV ? launch_inv_t<float>(M, lat, N, t, partial, nv, out, st)
-                                           : launch_inv_t<double>(M, lat, N, t, partial, nv, out, st);
+hipError_t launch_invariants(int M, int storage, int weak, const LatDev* lat, long long N, long long t,
+                             double* partial, int nv, double* out, hipStream_t st) {
+    return storage == RLBM_STORAGE_F32_DEV ? launch_inv_t<float>(M, weak, lat, N, t, partial, nv, out, st)
+                                           : launch_inv_t<double>(M, weak, lat, N, t, partial, nv, out, st);
 }
 
 bool species_supported(int M) { return M == 2 || M == 3 || M == 4 || M == 9; }

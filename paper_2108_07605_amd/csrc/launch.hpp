@@ -25,17 +25,18 @@ constexpr int BC_NODES = 8;
 // phase 0: boundary (BC_NODES interface nodes per block); phases 1 and 2:
 // moments and diffusion, chemistry and gradients (256-thread blocks over
 // nodes); phase 3: update (one block per 64 nodes).
-hipError_t launch_phase(int phase, int M, int storage, const StepLaunch& a);
-hipError_t launch_init(int M, int storage, const LatDev* lat, long long N, const double* rho, const double* u,
-                       const double* T, const double* Y, hipStream_t st);
-hipError_t launch_refs(int M, const LatDev* lat, double* ref, double rho, double T, const double* Y,
+hipError_t launch_phase(int phase, int M, int storage, int weak, const StepLaunch& a);
+// weak: the weakly coupled storage (all M species lattices, no slaved species)
+hipError_t launch_init(int M, int storage, int weak, const LatDev* lat, long long N, const double* rho,
+                       const double* u, const double* T, const double* Y, hipStream_t st);
+hipError_t launch_refs(int M, int weak, const LatDev* lat, double* ref, double rho, double T, const double* Y,
                        hipStream_t st);
-hipError_t launch_fields(int M, int storage, const LatDev* lat, long long N, long long t, double* rho, double* u,
-                         double* T, double* Y, double* P, int* flag, hipStream_t st);
-hipError_t launch_pops(int M, int storage, const LatDev* lat, long long N, int nl, long long t, double* buf,
-                       int write, hipStream_t st);
-hipError_t launch_invariants(int M, int storage, const LatDev* lat, long long N, long long t, double* partial,
-                             int nv, double* out, hipStream_t st);
+hipError_t launch_fields(int M, int storage, int weak, const LatDev* lat, long long N, long long t, double* rho,
+                         double* u, double* T, double* Y, double* P, int* flag, hipStream_t st);
+hipError_t launch_pops(int M, int storage, int weak, const LatDev* lat, long long N, int nl, long long t,
+                       double* buf, int write, hipStream_t st);
+hipError_t launch_invariants(int M, int storage, int weak, const LatDev* lat, long long N, long long t,
+                             double* partial, int nv, double* out, hipStream_t st);
 bool species_supported(int M);
 
 }  // namespace rlbm

@@ -58,6 +58,7 @@ struct LatDev {
     int nx, ny, nz, pad0;
     int per[3];                 // periodic flags per axis
     int slaved, substeps, storage, reaction;
+    int weak, pad3;             // weak: all M species stored (slaved = M), else one slaved species
     long long N;
     int n_if, n_out;
     const MechDev* mech;

@@ -101,7 +101,7 @@ int validate_desc(const rlbm_lattice_desc* d, int M) {
     if (d->substeps < 1) return fail(RLBM_EINVAL, "substeps must be >= 1");
     if (d->reaction != RLBM_REACTION_EXPLICIT && d->reaction != RLBM_REACTION_LINEARLY_IMPLICIT)
         return fail(RLBM_EINVAL, "unknown reaction scheme");
-    if (d->slaved < -1 || d->slaved >= M) return fail(RLBM_EINVAL, "slaved species index out of range");
+    if (d->slaved < RLBM_SLAVED_NONE || d->slaved >= M) return fail(RLBM_EINVAL, "slaved species index out of range");
     return RLBM_OK;
 }
 
@@ -186,9 +186,13 @@ void build_geometry(const rlbm_lattice_desc* d, Geometry& g) {
     g = std::move(s);
 }
 
+// Stored lattices: M - 1 species (one slaved), or all M in the weakly coupled
+// storage, plus f and g.
+int stored_lattices(const rlbm_lattice_desc* d, int M) { return d->slaved == RLBM_SLAVED_NONE ? M + 2 : M + 1; }
+
 Plan make_plan(const rlbm_lattice_desc* d, int M, int E, const Geometry& g) {
     Plan p{};
-    const int L = M + 1;
+    const int L = stored_lattices(d, M);
     const size_t N = (size_t)g.N;
     const size_t s = d->storage == RLBM_STORAGE_F32_DEV ? 4 : 8;
     const size_t nif = g.if_node.size();
@@ -215,7 +219,7 @@ Plan make_plan(const rlbm_lattice_desc* d, int M, int E, const Geometry& g) {
     p.off_out = take((size_t)(5 + M) * g.n_out * sizeof(double));
     p.off_partial = take(nblocks * (6 + E) * sizeof(double));
     p.off_invout = take((6 + E) * sizeof(double));
-    const size_t rss = d->storage == RLBM_STORAGE_F32_DEV ? (size_t)((M + 1 + 3) / 4 * 4) : 0;
+    const size_t rss = d->storage == RLBM_STORAGE_F32_DEV ? (size_t)((L + 3) / 4 * 4) : 0;
     p.off_rscale0 = take(rss * N * sizeof(float));
     p.off_rscale1 = take(rss * N * sizeof(float));
     p.total = o;
@@ -394,7 +398,7 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     lat->desc = *d;
     lat->M = M;
     lat->mech = mech->dev;
-    lat->L = M + 1;
+    lat->L = stored_lattices(d, M);
     lat->E = mech->dev.E;
     lat->storage = d->storage;
     lat->stream = (hipStream_t)stream;
@@ -417,7 +421,9 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     std::memset(&h, 0, sizeof(h));
     h.nx = d->nx; h.ny = d->ny; h.nz = d->nz;
     for (int ax = 0; ax < 3; ++ax) h.per[ax] = d->faces[2 * ax].type == RLBM_FACE_PERIODIC;
-    h.slaved = d->slaved < 0 ? M - 1 : d->slaved;
+    // the weakly coupled storage marks "no slaved species" with the index M
+    h.weak = d->slaved == RLBM_SLAVED_NONE ? 1 : 0;
+    h.slaved = h.weak ? M : (d->slaved < 0 ? M - 1 : d->slaved);
     h.substeps = d->substeps;
     h.storage = d->storage;
     h.reaction = d->reaction;
@@ -439,7 +445,7 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     h.bcbuf = base + p.off_bcbuf;
     h.out_state = (double*)(base + p.off_out);
     h.ref = d->storage == RLBM_STORAGE_F32_DEV ? (const double*)(base + p.off_ref) : nullptr;
-    h.rss = d->storage == RLBM_STORAGE_F32_DEV ? (M + 1 + 3) / 4 * 4 : 0;
+    h.rss = d->storage == RLBM_STORAGE_F32_DEV ? (lat->L + 3) / 4 * 4 : 0;
     h.rscale[0] = d->storage == RLBM_STORAGE_F32_DEV ? (float*)(base + p.off_rscale0) : nullptr;
     h.rscale[1] = d->storage == RLBM_STORAGE_F32_DEV ? (float*)(base + p.off_rscale1) : nullptr;
     const rlbm_face& fi = d->faces[0];
@@ -499,18 +505,20 @@ int rlbm_lattice_shape(const rlbm_lattice* lat, int32_t* L, int64_t* N, int64_t*
     if (L) *L = lat->L;
     if (N) *N = lat->geo.N;
     if (n_interface) *n_interface = (int64_t)lat->geo.if_node.size();
-    if (slaved) *slaved = lat->host.slaved;
+    if (slaved) *slaved = lat->host.weak ? RLBM_SLAVED_NONE : lat->host.slaved;
     return RLBM_OK;
 }
 
 // Slot order for the collision: stored species in lattice order, then the
-// slaved one; gas constants R_a and couplings 1/(D_ref m_a m_b) permuted.
+// slaved one (species order in the weakly coupled storage); gas constants R_a
+// and couplings 1/(D_ref m_a m_b) permuted.
 // The host vector is synchronised before it goes out of scope.
 static int upload_slot_table(rlbm_lattice* lat) {
     const int M = lat->M;
     std::vector<double> slot((size_t)M + (size_t)M * M);
     const int sl = lat->host.slaved;
-    auto spc = [&](int j) { return j < M - 1 ? j + (j >= sl ? 1 : 0) : sl; };
+    const bool weak = lat->host.weak != 0;
+    auto spc = [&](int j) { return weak ? j : (j < M - 1 ? j + (j >= sl ? 1 : 0) : sl); };
     for (int j = 0; j < M; ++j) {
         slot[j] = lat->mech.Ra[spc(j)];
         for (int q = 0; q < M; ++q) slot[M + (size_t)j * M + q] = lat->mech.Kab[spc(j)][spc(q)];
@@ -567,7 +575,7 @@ int rlbm_set_state(rlbm_lattice* lat, const double* rho, const double* u, const 
     mean_rho /= (double)N;
     mean_T /= (double)N;
     for (int a = 0; a < M; ++a) mean_Y[a] /= (double)N;
-    if (lat->desc.slaved < 0) {
+    if (lat->desc.slaved == -1) {
         int best = 0;
         for (int a = 1; a < M; ++a)
             if (mean_Y[a] > mean_Y[best]) best = a;
@@ -587,9 +595,10 @@ int rlbm_set_state(rlbm_lattice* lat, const double* rho, const double* u, const 
     HIP_TRY(hipMemcpyAsync(dmeanY, mean_Y.data(), M * sizeof(double), hipMemcpyHostToDevice, lat->stream),
             "upload");
     if (lat->storage == RLBM_STORAGE_F32_DEV)
-        HIP_TRY(launch_refs(M, lat->d_lat, lat->d_ref, mean_rho, mean_T, dmeanY, lat->stream), "refs kernel");
-    HIP_TRY(launch_init(M, lat->storage, lat->d_lat, (long long)N, stage, stage + N, stage + 4 * N, stage + 5 * N,
-                        lat->stream),
+        HIP_TRY(launch_refs(M, lat->host.weak, lat->d_lat, lat->d_ref, mean_rho, mean_T, dmeanY, lat->stream),
+                "refs kernel");
+    HIP_TRY(launch_init(M, lat->storage, lat->host.weak, lat->d_lat, (long long)N, stage, stage + N, stage + 4 * N,
+                        stage + 5 * N, lat->stream),
             "init kernel");
     HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
     lat->state_set = true;
@@ -628,7 +637,7 @@ static int step_one(rlbm_lattice* lat, long long t) {
             ev->kernel = phase;
             HIP_TRY(hipEventRecord(ev->a, lat->stream), "hipEventRecord");
         }
-        HIP_TRY(launch_phase(phase, lat->M, lat->storage, a), "step kernel launch");
+        HIP_TRY(launch_phase(phase, lat->M, lat->storage, lat->host.weak, a), "step kernel launch");
         if (ev) HIP_TRY(hipEventRecord(ev->b, lat->stream), "hipEventRecord");
     }
     return RLBM_OK;
@@ -666,7 +675,7 @@ int rlbm_read_fields(rlbm_lattice* lat, double* rho, double* u, double* T, doubl
     const int M = lat->M;
     const size_t N = (size_t)lat->geo.N;
     if (on_device) {
-        HIP_TRY(launch_fields(M, lat->storage, lat->d_lat, (long long)N, lat->steps_done, rho, u, T, Y, P,
+        HIP_TRY(launch_fields(M, lat->storage, lat->host.weak, lat->d_lat, (long long)N, lat->steps_done, rho, u, T, Y, P,
                               lat->d_flag, lat->stream),
                 "fields kernel");
         HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
@@ -676,7 +685,7 @@ int rlbm_read_fields(rlbm_lattice* lat, double* rho, double* u, double* T, doubl
     const size_t nf = (6 + (size_t)M) * N;
     HIP_TRY(hipMalloc(&tmp, nf * sizeof(double)), "hipMalloc");
     double *dr = tmp, *du = dr + N, *dT = du + 3 * N, *dY = dT + N, *dP = dY + (size_t)M * N;
-    hipError_t e = launch_fields(M, lat->storage, lat->d_lat, (long long)N, lat->steps_done, rho ? dr : nullptr,
+    hipError_t e = launch_fields(M, lat->storage, lat->host.weak, lat->d_lat, (long long)N, lat->steps_done, rho ? dr : nullptr,
                                  u ? du : nullptr, T ? dT : nullptr, Y ? dY : nullptr, P ? dP : nullptr,
                                  lat->d_flag, lat->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(lat->stream);
@@ -697,7 +706,7 @@ static int pops_io(rlbm_lattice* lat, double* buf, int on_device, int write) {
     const size_t N = (size_t)lat->geo.N;
     const size_t n = (size_t)lat->L * Q * N;
     if (on_device) {
-        HIP_TRY(launch_pops(lat->M, lat->storage, lat->d_lat, (long long)N, lat->L, lat->steps_done, buf, write, lat->stream),
+        HIP_TRY(launch_pops(lat->M, lat->storage, lat->host.weak, lat->d_lat, (long long)N, lat->L, lat->steps_done, buf, write, lat->stream),
                 "populations kernel");
         HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
         return RLBM_OK;
@@ -707,7 +716,7 @@ static int pops_io(rlbm_lattice* lat, double* buf, int on_device, int write) {
     hipError_t e = hipSuccess;
     if (write) e = hipMemcpy(tmp, buf, n * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = launch_pops(lat->M, lat->storage, lat->d_lat, (long long)N, lat->L, lat->steps_done, tmp, write, lat->stream);
+        e = launch_pops(lat->M, lat->storage, lat->host.weak, lat->d_lat, (long long)N, lat->L, lat->steps_done, tmp, write, lat->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(lat->stream);
     if (e == hipSuccess && !write) e = hipMemcpy(buf, tmp, n * sizeof(double), hipMemcpyDeviceToHost);
     (void)hipFree(tmp);
@@ -792,7 +801,8 @@ int rlbm_load_state(rlbm_lattice* lat, const void* buf, int on_device) {
     HIP_TRY(hipMemcpy(&h, b, sizeof(h), hipMemcpyDefault), "load state");
     if (h.magic != STATE_MAGIC || h.version != 1u) return fail(RLBM_EINVAL, "not a lattice state snapshot");
     if (h.M != lat->M || h.L != lat->L || h.storage != lat->storage || h.N != lat->geo.N ||
-        h.n_out != lat->geo.n_out || h.rss != lat->host.rss || h.slaved < 0 || h.slaved >= lat->M)
+        h.n_out != lat->geo.n_out || h.rss != lat->host.rss || h.slaved < 0 || h.slaved >= lat->M + lat->host.weak ||
+        (lat->host.weak && h.slaved != lat->M))
         return fail(RLBM_EINVAL, "snapshot taken on a lattice of another shape, species count or storage");
     lat->host.slaved = h.slaved;
     HIP_TRY(hipMemcpy(lat->d_lat, &lat->host, sizeof(LatDev), hipMemcpyHostToDevice), "load state");
@@ -816,7 +826,8 @@ int rlbm_invariants(rlbm_lattice* lat, double* out, int n_out) {
     const int nv = 6 + lat->E;
     if (n_out < nv) return fail(RLBM_EINVAL, "output array too small (needs 6 + E)");
     HIP_TRY(hipSetDevice(lat->device), "hipSetDevice");
-    HIP_TRY(launch_invariants(lat->M, lat->storage, lat->d_lat, lat->geo.N, lat->steps_done, lat->d_partial, nv,
+    HIP_TRY(launch_invariants(lat->M, lat->storage, lat->host.weak, lat->d_lat, lat->geo.N, lat->steps_done,
+                              lat->d_partial, nv,
                               lat->d_invout, lat->stream),
             "invariants kernel");
     HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
@@ -868,7 +879,8 @@ int rlbm_batch_create(rlbm_lattice* const* lats, int32_t k, void* dev_mem, size_
     if (((uintptr_t)dev_mem & 255) != 0) return fail(RLBM_EINVAL, "device memory must be 256-byte aligned");
     for (int j = 0; j < k; ++j) {
         if (!lats[j]) return fail(RLBM_EINVAL, "null lattice in batch");
-        if (lats[j]->M != lats[0]->M || lats[j]->storage != lats[0]->storage || lats[j]->device != lats[0]->device)
+        if (lats[j]->M != lats[0]->M || lats[j]->storage != lats[0]->storage || lats[j]->device != lats[0]->device ||
+            lats[j]->host.weak != lats[0]->host.weak)
             return fail(RLBM_EINVAL, "batched lattices need the same species count, storage and device");
     }
     rlbm_batch* b = new (std::nothrow) rlbm_batch();
@@ -930,7 +942,7 @@ int rlbm_batch_step(rlbm_batch* b, const int64_t* steps) {
             a.stream = l0->stream;
             a.schemes = schemes;
             if (a.blocks == 0) continue;
-            HIP_TRY(launch_phase(phase, l0->M, l0->storage, a), "batch kernel launch");
+            HIP_TRY(launch_phase(phase, l0->M, l0->storage, l0->host.weak, a), "batch kernel launch");
         }
     }
     // keep the host table alive until the copies above have been consumed

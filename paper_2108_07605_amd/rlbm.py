@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "librlbm.so")
 FACE_PERIODIC, FACE_WALL, FACE_INLET, FACE_OUTLET, FACE_BOUNCEBACK, FACE_INLET_LOCAL = 0, 1, 2, 3, 4, 5
 STORAGE_F64, STORAGE_F32_DEV = 0, 1
 REACTION_EXPLICIT, REACTION_LINEARLY_IMPLICIT = 0, 1
+SLAVED_NONE = -2   # weakly coupled storage: all M species lattices stored
 _FACE_CODES = {"periodic": FACE_PERIODIC, "wall": FACE_WALL, "inlet": FACE_INLET,
                "outlet": FACE_OUTLET, "bounceback": FACE_BOUNCEBACK, "inlet_local": FACE_INLET_LOCAL}
 _STORAGE = {"f64": STORAGE_F64, "f32dev": STORAGE_F32_DEV}
@@ -199,7 +200,10 @@ def lattice_desc(case, storage="f64"):
             fc.P_inf, fc.sigma = f["P_inf"], f["sigma"]
     d.storage = _STORAGE[storage]
     d.substeps = int(case.get("substeps", 2))
-    d.slaved = int(case.get("slaved", -1))
+    coupling = case.get("coupling", "strong")
+    if coupling not in ("strong", "weak"):
+        raise KeyError("unknown coupling %r" % (coupling,))
+    d.slaved = SLAVED_NONE if coupling == "weak" else int(case.get("slaved", -1))
     d.reaction = _REACTION[case.get("reaction", "explicit")]
     return d, keep
 

@@ -433,7 +433,8 @@ def make_case(name: str, seed: int = 0, **kw):
     (Lx1x1 flame tube), 'binary' (two-species periodic box), 'bbbox' (duct
     with bounce-back walls), plus keyword
     overrides nx, ny, nz, storage ('f64' | 'f32dev'), substeps, reaction
-    ('explicit' | 'implicit'), steps."""
+    ('explicit' | 'implicit'), coupling ('strong': one slaved species;
+    'weak': all M species lattices stored), steps."""
     builders = {
         "abc_box": _case_abc_box,
         "reactor": _case_reactor,
@@ -447,6 +448,7 @@ def make_case(name: str, seed: int = 0, **kw):
     case.setdefault("storage", kw.get("storage", "f64"))
     case.setdefault("substeps", kw.get("substeps", 2))
     case.setdefault("reaction", kw.get("reaction", "explicit"))
+    case.setdefault("coupling", kw.get("coupling", "strong"))
     case["name"] = name
     case["N"] = case["nx"] * case["ny"] * case["nz"]
     return case

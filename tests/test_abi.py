@@ -122,6 +122,26 @@ def test_reaction_scheme_validation(mech9):
         rlbm.lattice_desc(dict(case, reaction="rk4"), "f64")
 
 
+def test_weak_coupling_stores_every_species(mech9):
+    """RLBM_SLAVED_NONE: L = M + 2 lattices (one more population buffer pair
+    and reference scale per node than with a slaved species)."""
+    m = rlbm.Mechanism(mech9)
+    strong = wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9)
+    weak = wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9, coupling="weak")
+    d, _keep = rlbm.lattice_desc(weak, "f64")
+    assert d.slaved == rlbm.SLAVED_NONE
+    N = 32 * 8
+    for st, s in (("f64", 8), ("f32dev", 4)):
+        extra = rlbm.lattice_bytes(weak, m, st) - rlbm.lattice_bytes(strong, m, st)
+        assert extra >= 2 * 27 * N * s                  # two population buffers of one more lattice
+        assert extra <= 2 * 27 * N * s + 27 * 256 * 8 + 2 * 4 * N * 4 + 8 * 4096
+    d.slaved = -3
+    n = ctypes.c_size_t()
+    assert rlbm.lib().rlbm_lattice_bytes(ctypes.byref(d), m.handle, ctypes.byref(n)) == -1
+    with pytest.raises(KeyError):
+        rlbm.lattice_desc(dict(weak, coupling="loose"), "f64")
+
+
 def test_inlet_composition_must_sum_to_one(mech9):
     m = rlbm.Mechanism(mech9)
     case = wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9)

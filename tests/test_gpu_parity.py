@@ -99,6 +99,10 @@ def test_abc_box_initial_state_exact():
     ("channel2d", dict(nx=40, ny=10, nz=1, substeps=4), [1, 20]),
     ("channel2d", dict(nx=48, ny=12, nz=1, reaction="implicit"), [1, 30]),
     ("reactor", dict(nx=4, ny=4, nz=4, T0=1500.0, X_radical=0.01, reaction="implicit", substeps=1), [1, 40]),
+    ("channel2d", dict(nx=48, ny=12, nz=1, coupling="weak"), [1, 30]),
+    ("channel3d", dict(nx=20, ny=8, nz=6, perturb=0.5, coupling="weak"), [1, 12]),
+    ("bbbox", dict(nx=12, ny=8, nz=6, coupling="weak"), [1, 30]),
+    ("tube", dict(nx=96, coupling="weak"), [1, 60]),
 ])
 def test_nine_species_parity(mech9, name, kw, steps):
     print(f"case {name} {kw} M=9 f64", flush=True)
@@ -127,6 +131,27 @@ def test_stiff_reactor_linearly_implicit(mech9, l):
         _compare_pops(gp, op, TOL64)
         _compare_fields(gf, of, TOL64, _u_floor(case))
     assert out[-1][3]["T"].min() > 1800.0
+
+
+def test_weak_coupling_three_species_parity():
+    """Weakly coupled storage (all M species lattices, L = M + 2) with three
+    species in a perturbed periodic box, against the oracle, and its
+    separately conserved densities."""
+    rlbm = _gpu()
+    print("case abc_box 32x8x8 M=3 weak f64", flush=True)
+    case = wl.make_case("abc_box", coupling="weak")
+    lat, ora, out = _run_pair(case, [1, 10, 100])
+    assert lat.L == 5 and lat.slaved == rlbm.SLAVED_NONE
+    for gp, op, gf, of in out:
+        _compare_pops(gp, op, TOL64)
+        _compare_fields(gf, of, TOL64, _u_floor(case))
+    gi, oi = lat.invariants(), ora.invariants()
+    np.testing.assert_allclose(gi[[0, 4, 5, 6]], oi[[0, 4, 5, 6]], rtol=1e-13)
+    pops = lat.populations()
+    rho_sp = pops[:3].sum(axis=1)
+    rho = pops[3].sum(axis=0)
+    assert np.abs(rho_sp.sum(axis=0) - rho).max() > 1e-8 * rho.max()      # the densities drift apart
+    assert abs(rho_sp.sum() - ora.fa.sum()) <= 1e-13 * ora.fa.sum()
 
 
 def test_bounce_back_box_conservation():
@@ -188,6 +213,17 @@ def test_f32_deviation_channel_vs_oracle(mech9):
     assert max(ey) <= TOL32 and et <= TOL32
 
 
+def test_f32_deviation_weak_coupling_vs_oracle(mech9):
+    print("case channel2d 48x12 f32dev weak", flush=True)
+    case = wl.make_case("channel2d", nx=48, ny=12, nz=1, mech=mech9, coupling="weak")
+    lat, ora, out = _run_pair(case, [30], storage="f32dev")
+    gp, op, gf, of = out[-1]
+    ey = [_nerr(gf["Y"][a], of["Y"][a], 1e-6) for a in range(of["Y"].shape[0])]
+    et = _nerr(gf["T"], of["T"])
+    print(f"f32dev weak vs oracle, channel2d 48x12 30 steps: Y {max(ey):.3e} T {et:.3e}", flush=True)
+    assert max(ey) <= TOL32 and et <= TOL32
+
+
 def test_f32_deviation_long_run_vs_f64(mech9):
     """FP32 deviation storage against FP64 storage on the GPU over 1000 steps
     of a walled channel with inlet and outlet: mass fractions (each species
@@ -219,12 +255,12 @@ def test_invariants_match_oracle():
     assert gi[-1] == 0.0
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32dev"])
-def test_populations_round_trip(storage, mech9):
+@pytest.mark.parametrize("storage,coupling", [("f64", "strong"), ("f32dev", "strong"), ("f32dev", "weak")])
+def test_populations_round_trip(storage, coupling, mech9):
     """FP64 populations read out and written straight back are unchanged
     (the FP32 encoding against the same references is idempotent)."""
     rlbm = _gpu()
-    case = wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9)
+    case = wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9, coupling=coupling)
     lat = rlbm.Lattice(case, storage=storage).set_state()
     lat.step(5)
     saved = lat.populations()
@@ -236,13 +272,13 @@ def test_populations_round_trip(storage, mech9):
     assert np.array_equal(lat.populations(), p3)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32dev"])
-def test_state_snapshot_resume(storage, mech9):
+@pytest.mark.parametrize("storage,coupling", [("f64", "strong"), ("f32dev", "strong"), ("f32dev", "weak")])
+def test_state_snapshot_resume(storage, coupling, mech9):
     """Checkpoint/resume: a raw snapshot taken after 5 steps, loaded back into
     the same lattice after 7 more steps or into a fresh lattice, continues
     bit-identically."""
     rlbm = _gpu()
-    case = wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9)
+    case = wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9, coupling=coupling)
     lat = rlbm.Lattice(case, storage=storage).set_state()
     lat.step(5)
     snap = lat.save_state()
@@ -259,6 +295,10 @@ def test_state_snapshot_resume(storage, mech9):
     for key in ("rho", "T", "Y", "u"):
         assert np.array_equal(f2[key], fa[key]), key
     other = rlbm.Lattice(wl.make_case("channel2d", nx=16, ny=8, nz=1, mech=mech9), storage=storage)
+    with pytest.raises(rlbm.RlbmError):
+        other.load_state(snap)
+    flip = "strong" if coupling == "weak" else "weak"
+    other = rlbm.Lattice(wl.make_case("channel2d", nx=32, ny=8, nz=1, mech=mech9, coupling=flip), storage=storage)
     with pytest.raises(rlbm.RlbmError):
         other.load_state(snap)
 

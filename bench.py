@@ -238,6 +238,35 @@ def _bench_substeps(args):
             "paper_cpu_increase": {"2": 0.06, "4": 0.15}}
 
 
+def _bench_coupling(args):
+    """Cost of the weakly coupled storage (all M species lattices, L = M + 2)
+    against the slaved one (L = M + 1) on the 512x64x64 channel in both
+    storages: MLUPS, per-kernel times and k_update's algorithmic HBM rate
+    (2 L 27 s bytes per node)."""
+    from paper_2108_07605_amd import workloads as wl
+    mech = wl.mechanism_h2air9()
+    N = args.nx * args.ny * args.nz
+    rows = {}
+    for coupling in ("strong", "weak"):
+        case = wl.make_case("channel3d", nx=args.nx, ny=args.ny, nz=args.nz, mech=mech, coupling=coupling)
+        L = mech["M"] + (2 if coupling == "weak" else 1)
+        for st in ("f32dev", "f64"):
+            r = _time_storage(case, st, args.steps, args.warmup)
+            ms = r["ms_total"] / args.steps
+            upd_ms, upd_n = r["update_timed"]
+            upd = upd_ms / max(upd_n, 1)
+            s_b = 4 if st == "f32dev" else 8
+            rows[f"{coupling} {st}"] = {
+                "L": L, "ms_per_step": ms, "mlups": N / (ms * 1e-3) / 1e6,
+                "kernels_ms_avg": {k: v[0] / max(v[1], 1) for k, v in r["kernels"].items()},
+                "update_GBps": 2 * L * 27 * s_b * N / (upd * 1e-3) / 1e9, "finite": r["finite"]}
+    return {"metric": "MLUPS, weakly coupled vs slaved storage", "value": rows["weak f32dev"]["mlups"],
+            "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"channel3d {args.nx}x{args.ny}x{args.nz}, 9 species"},
+            "rows": rows}
+
+
 def _bench_precision(args):
     """FP32-deviation storage against FP64 storage from the same initial
     state: the 512x64x64 channel after --steps steps (2000 in the recipe) and
@@ -319,12 +348,13 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--storage", default="both", choices=["both", "f32dev", "f64"])
     ap.add_argument("--workload", default="channel3d",
-                    choices=["channel3d", "tubes", "serve", "precision", "substeps"],
+                    choices=["channel3d", "tubes", "serve", "precision", "substeps", "coupling"],
                     help="channel3d: the 512x64x64 channel (default); tubes: 256 uneven flame "
                          "tubes in batched launches vs one lattice at a time; serve: the "
                          "continuous-batching server on a Poisson request trace; precision: "
                          "FP32-deviation vs FP64 storage field errors after --steps steps; "
-                         "substeps: step time with l = 1, 2, 4 reaction sub-steps")
+                         "substeps: step time with l = 1, 2, 4 reaction sub-steps; coupling: the "
+                         "weakly coupled storage (all M species lattices) vs the slaved one")
     ap.add_argument("--tubes", type=int, default=256)
     ap.add_argument("--seq-steps", type=int, default=20,
                     help="steps of the one-lattice-at-a-time comparison (tubes)")
@@ -356,6 +386,9 @@ def main():
         return
     if args.workload == "substeps":
         print(json.dumps(_bench_substeps(args)))
+        return
+    if args.workload == "coupling":
+        print(json.dumps(_bench_coupling(args)))
         return
     case = wl.make_case("channel3d", nx=args.nx, ny=args.ny, nz=args.nz)
     N = case["nx"] * case["ny"] * case["nz"]

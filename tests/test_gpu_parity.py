@@ -103,6 +103,8 @@ def test_abc_box_initial_state_exact():
     ("channel3d", dict(nx=20, ny=8, nz=6, perturb=0.5, coupling="weak"), [1, 12]),
     ("bbbox", dict(nx=12, ny=8, nz=6, coupling="weak"), [1, 30]),
     ("tube", dict(nx=96, coupling="weak"), [1, 60]),
+    ("reactor", dict(nx=3, ny=3, nz=2, T0=1500.0, X_radical=0.01, reaction="implicit", coupling="weak"), [1, 30]),
+    ("channel2d", dict(nx=40, ny=10, nz=1, inlet="inlet_local", coupling="weak", substeps=3), [1, 20]),
 ])
 def test_nine_species_parity(mech9, name, kw, steps):
     print(f"case {name} {kw} M=9 f64", flush=True)
@@ -171,9 +173,10 @@ def test_bounce_back_box_conservation():
             assert abs(inv1[k] - inv0[k]) <= tol * abs(inv0[k]), (storage, k)
 
 
-def test_binary_parity():
-    print("case binary 64 M=2 f64", flush=True)
-    case = wl.make_case("binary", nx=64, amp=1e-2)
+@pytest.mark.parametrize("coupling", ["strong", "weak"])
+def test_binary_parity(coupling):
+    print(f"case binary 64 M=2 f64 {coupling}", flush=True)
+    case = wl.make_case("binary", nx=64, amp=1e-2, coupling=coupling)
     lat, ora, out = _run_pair(case, [1, 100])
     for gp, op, gf, of in out:
         _compare_pops(gp, op, TOL64)
@@ -183,9 +186,10 @@ def test_binary_parity():
 def test_tiny_and_degenerate_boxes():
     """2x2x2 and 1x1x1 periodic boxes (every neighbour is the node itself or
     its image) and a 3x1x1 line."""
-    for nx, ny, nz in ((2, 2, 2), (1, 1, 1), (3, 1, 1)):
-        print(f"case abc_box {nx}x{ny}x{nz}", flush=True)
-        case = wl.make_case("abc_box", nx=nx, ny=ny, nz=nz)
+    for nx, ny, nz, coupling in ((2, 2, 2, "strong"), (1, 1, 1, "strong"), (3, 1, 1, "strong"),
+                                 (1, 1, 1, "weak"), (3, 1, 1, "weak")):
+        print(f"case abc_box {nx}x{ny}x{nz} {coupling}", flush=True)
+        case = wl.make_case("abc_box", nx=nx, ny=ny, nz=nz, coupling=coupling)
         lat, ora, out = _run_pair(case, [5])
         for gp, op, gf, of in out:
             _compare_pops(gp, op, TOL64)

@@ -1057,10 +1057,11 @@ __device__ __forceinline__ double eq_value(MechC mc, const EqState<M, SPV>& e, i
 // iteration, LODI) is evaluated redundantly by the lanes of a node.
 // ---------------------------------------------------------------------------
 // Sum over the 32 lanes of a half-wave.  Lane pairs are combined within
-// quads, half-rows and rows of 16 by DPP moves (no LDS round trip), then the
-// two rows by one swizzle.  Every step adds the same two operands on both
-// lanes of a pair (a + b = b + a exactly), so all 32 lanes end with
-// bit-identical sums and the lanes of a node continue from identical moments.
+// quads, half-rows and rows of 16 by DPP moves, then the two rows of 16 by
+// gfx950's row swap (v_permlane16_swap), all in the vector ALU with no LDS
+// round trip.  Every step adds the same two operands on both lanes of a pair
+// (a + b = b + a exactly), so all 32 lanes end with bit-identical sums and
+// the lanes of a node continue from identical moments.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
     const long long b = __builtin_bit_cast(long long, v);
@@ -1073,10 +1074,14 @@ __device__ __forceinline__ double hsum32(double v) {
     v += dpp_f64<0x4e>(v);    // quad_perm [2, 3, 0, 1]
     v += dpp_f64<0x141>(v);   // row_half_mirror
     v += dpp_f64<0x140>(v);   // row_mirror
+    // rows 2k and 2k+1 exchange: with both operands v, element 0 holds row
+    // 2k's value and element 1 row 2k+1's value on every lane of the pair
     const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_ds_swizzle((int)b, 0x401f);          // lane ^ 16 within 32
-    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401f);
-    return v + __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+    const auto lo = __builtin_amdgcn_permlane16_swap((int)b, (int)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((int)(b >> 32), (int)(b >> 32), false, false);
+    const double r0 = __builtin_bit_cast(double, ((long long)hi[0] << 32) | (unsigned)lo[0]);
+    const double r1 = __builtin_bit_cast(double, ((long long)hi[1] << 32) | (unsigned)lo[1]);
+    return r0 + r1;
 }
 
 // Equilibrium state of section 4.1: density, mass fractions, velocity (with

@@ -1131,12 +1131,13 @@ __device__ __forceinline__ void bc_eq(MechC mc, const BcState<M, SPV>& e, int c0
 // Local state (eqs. locRho .. locT and their inlet/outlet counterparts): the
 // moments of the populations with the incoming links set to the imposed
 // equilibrium A, outgoing links from advection (pa, pf, pg: this lane's
-// streamed values by species / momentum / energy lattice).
+// streamed values by species / momentum / energy lattice).  A's equilibria
+// at this lane's velocity are returned in ea, ef, eg for the caller's
+// reconstruction.
 template <int M, int W, bool SPV, bool ASPV>
 __device__ __forceinline__ void bc_local(MechC mc, const BcState<M, ASPV>& A, int s, bool act, bool in, int c0,
                                          int c1, int c2, const double* pa, double pf, double pg,
-                                         BcState<M, SPV>& Lc, int* fail) {
-    double ea[M], ef, eg;
+                                         BcState<M, SPV>& Lc, int* fail, double* ea, double& ef, double& eg) {
     bc_eq<M, ASPV>(mc, A, c0, c1, c2, ea, ef, eg);
     double ra[M], ja[M][3];
     const double cx = c0, cy = c1, cz = c2;
@@ -1162,24 +1163,27 @@ __device__ __forceinline__ void bc_local(MechC mc, const BcState<M, ASPV>& A, in
     for (int a = 0; a < M; ++a)
         if (a == s) { ra[a] = rs; ja[a][0] = j0; ja[a][1] = j1; ja[a][2] = j2; }
     Lc.rho = rl;
+    const double irl = 1.0 / rl;
 #pragma unroll
-    for (int dd = 0; dd < 3; ++dd) Lc.u[dd] = jl[dd] / rl;
-    double ry = rl;   // the weakly coupled storage normalises Y by sum_a rho_a
+    for (int dd = 0; dd < 3; ++dd) Lc.u[dd] = jl[dd] * irl;
+    double iry = irl;   // the weakly coupled storage normalises Y by sum_a rho_a
     if constexpr (W) {
-        ry = 0.0;
+        double ry = 0.0;
 #pragma unroll
         for (int a = 0; a < M; ++a) ry += ra[a];
+        iry = 1.0 / ry;
     }
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-        Lc.Y[a] = ra[a] / ry;
+        Lc.Y[a] = ra[a] * iry;
         if constexpr (SPV) {
             const bool small = ra[a] <= 1e-14 * rl;
+            const double ira = small ? 0.0 : 1.0 / ra[a];
 #pragma unroll
-            for (int dd = 0; dd < 3; ++dd) Lc.us[a][dd] = small ? Lc.u[dd] : ja[a][dd] / ra[a];
+            for (int dd = 0; dd < 3; ++dd) Lc.us[a][dd] = small ? Lc.u[dd] : ja[a][dd] * ira;
         }
     }
-    const double Ul = El / rl - 0.5 * (Lc.u[0] * Lc.u[0] + Lc.u[1] * Lc.u[1] + Lc.u[2] * Lc.u[2]);
+    const double Ul = El * irl - 0.5 * (Lc.u[0] * Lc.u[0] + Lc.u[1] * Lc.u[1] + Lc.u[2] * Lc.u[2]);
     const double T_l = solve_T<M>(mc, Lc.Y, Ul, A.T, fail);
     bc_prepare<M, SPV>(mc, Lc, T_l);
 }
@@ -1293,18 +1297,18 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
 #pragma unroll
                 for (int a = 0; a < M; ++a) ry += rY[a];
             }
+            const double iry = 1.0 / ry;
 #pragma unroll
-            for (int a = 0; a < M; ++a) A.Y[a] = (a == s ? rs : rY[a]) / ry;
+            for (int a = 0; a < M; ++a) A.Y[a] = (a == s ? rs : rY[a]) * iry;
             A.rho = rb;
             A.u[0] = A.u[1] = A.u[2] = 0.0;
             bc_prepare<M, false>(mc, A, L.if_T[k]);
         }
         // step 3: local state with species velocities (eqs. locRho .. locT)
         BcState<M, true> Lc;
-        bc_local<M, W, true, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
-        // step 4 (eqs. ftms, gtms, fatms)
         double eA[M], fA, gA, eL[M], fL, gL;
-        bc_eq<M, false>(mc, A, c0, c1, c2, eA, fA, gA);
+        bc_local<M, W, true, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail, eA, fA, gA);
+        // step 4 (eqs. ftms, gtms, fatms)
         bc_eq<M, true>(mc, Lc, c0, c1, c2, eL, fL, gL);
 #pragma unroll
         for (int a = 0; a < M; ++a)
@@ -1322,7 +1326,8 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
         for (int a = 0; a < M; ++a) A.Y[a] = L.Y_in[a];
         bc_prepare<M, false>(mc, A, L.T_in);
         BcState<M, false> Lc;
-        bc_local<M, W, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
+        double eA[M], fA, gA;
+        bc_local<M, W, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail, eA, fA, gA);
         double eL[M], fL, gL;
         bc_eq<M, false>(mc, Lc, c0, c1, c2, eL, fL, gL);
 #pragma unroll
@@ -1339,7 +1344,8 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
         for (int a = 0; a < M; ++a) A.Y[a] = L.Y_in[a];
         bc_prepare<M, false>(mc, A, L.T_in);
         BcState<M, false> Lc;  // local state (eqs. inletlocRho .. inletlocT)
-        bc_local<M, W, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
+        double eA[M], fA, gA, eL[M], fL, gL, eT[M], fT, gT;
+        bc_local<M, W, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail, eA, fA, gA);
         // target: local density and composition at the imposed u, T (eqs. in_tgt_*)
         BcState<M, false> Tg;
         Tg.rho = Lc.rho;
@@ -1348,8 +1354,6 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
         for (int a = 0; a < M; ++a) Tg.Y[a] = Lc.Y[a];
         bc_prepare<M, false>(mc, Tg, L.T_in);
         // (eqs. f_inlet, g_inlet, fa_inlet)
-        double eA[M], fA, gA, eL[M], fL, gL, eT[M], fT, gT;
-        bc_eq<M, false>(mc, A, c0, c1, c2, eA, fA, gA);
         bc_eq<M, false>(mc, Lc, c0, c1, c2, eL, fL, gL);
         bc_eq<M, false>(mc, Tg, c0, c1, c2, eT, fT, gT);
 #pragma unroll
@@ -1415,10 +1419,9 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
             }
         }
         BcState<M, false> Lc;  // local state (eqs. outletlocRho .. outletlocT)
-        bc_local<M, W, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail);
-        // (eqs. f_outlet, g_outlet, fa_outlet)
         double eA[M], fA, gA, eL[M], fL, gL;
-        bc_eq<M, false>(mc, A, c0, c1, c2, eA, fA, gA);
+        bc_local<M, W, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail, eA, fA, gA);
+        // (eqs. f_outlet, g_outlet, fa_outlet)
         bc_eq<M, false>(mc, Lc, c0, c1, c2, eL, fL, gL);
 #pragma unroll
         for (int a = 0; a < M; ++a)

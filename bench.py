@@ -223,7 +223,8 @@ def _bench_substeps(args):
         r = _time_storage(case, "f32dev", args.steps, args.warmup)
         ms = r["ms_total"] / args.steps
         rows[key] = {"ms_per_step": ms,
-                     "chem_ms": r["kernels"]["chem"][0] / max(r["kernels"]["chem"][1], 1),
+                     "local_ms": r["kernels"]["local"][0] / max(r["kernels"]["local"][1], 1),
+                     "gradients_ms": r["kernels"]["gradients"][0] / max(r["kernels"]["gradients"][1], 1),
                      "finite": r["finite"]}
     N = args.nx * args.ny * args.nz
     for key in rows:

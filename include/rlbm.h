@@ -232,8 +232,9 @@ int rlbm_lattice_shape(const rlbm_lattice* lat, int32_t* L, int64_t* N, int64_t*
 
 /* Per-kernel timing with HIP events recorded on the lattice stream around
  * the launches of the kernels selected by `enable`: bit k set times kernel k
- * in {0: boundary, 1: moments and diffusion, 2: chemistry and gradients,
- * 3: update}; 0 switches timing off.  Event pairs are pooled and reused.
+ * in {0: boundary, 1: moments, diffusion and the forward-Euler reaction
+ * increment, 2: gradients (with the linearly implicit reaction increment
+ * before them where selected), 3: update}; 0 switches timing off.  Event pairs are pooled and reused.
  * rlbm_kernel_times synchronises and returns the accumulated milliseconds
  * ms[k] and launch counts counts[k] since the last reset. */
 int rlbm_set_timing(rlbm_lattice* lat, int enable);

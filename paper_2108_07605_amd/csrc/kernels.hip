@@ -1,17 +1,19 @@
 // HIP kernels of the reactive-mixture lattice Boltzmann step for gfx950.
 //
 // One time step is four launches over a (possibly batched) work list:
-//   k_boundary  interface nodes: advection + wall / inlet / outlet
-//               reconstruction (section 4) into a side buffer;
-//   k_local     every node: advection, moments, temperature (eq. temperature),
-//               relaxation rates and Stefan-Maxwell diffusion velocities (eq.
-//               transform1); publishes rho, u, T, Y, Phi_a and the enthalpy
-//               moments for the neighbours and writes the per-node record
-//               read by k_update;
-//   k_chem      reaction increment by l sub-steps (eq. R3), then the
-//               same-time gradients of Phi_a and sum_b H_b Y_b;
-//   k_update    every node: advection again and the collisions of all stored
-//               lattices, written to the other population buffer.
+//   k_boundary   interface nodes: advection + wall / inlet / outlet
+//                reconstruction (section 4) into a side buffer;
+//   k_local      every node: advection, moments, temperature (eq.
+//                temperature), relaxation rates, Stefan-Maxwell diffusion
+//                velocities (eq. transform1) and the reaction increment by l
+//                forward-Euler sub-steps (eq. R3); publishes rho, u, T, Y,
+//                Phi_a and the enthalpy moments for the neighbours and writes
+//                the per-node record read by k_update;
+//   k_gradients  the same-time gradients of Phi_a and sum_b H_b Y_b
+//                (k_chem_implicit instead for lattices with the linearly
+//                implicit reaction update: its sub-steps, then the gradients);
+//   k_update     every node: advection again and the collisions of all stored
+//                lattices, written to the other population buffer.
 // Populations are structure-of-arrays [L][27][N] (x fastest), pulled from the
 // source buffer, so every load and store of a wavefront is coalesced.  The
 // storage type S is double (FP64) or float (FP32 deviation from a reference
@@ -565,6 +567,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     prm[PRM_WQ * N + node] = omega - omega1;
     prm[PRM_CC * N + node] = 0.5 * (2.0 - omega1) * P;
     stefan_maxwell<M, W>(L, node, ls, T, rho, common, omega1, Y, Qb, rho * inv_rhoY);
+
+    // reaction increment (eq. R3, forward Euler), with the LDS columns the
+    // diffusion step has finished with; the arithmetic-bound chemistry then
+    // runs under this kernel's memory traffic.  Lattices with the linearly
+    // implicit update take it in k_chem_implicit.
+    if (L.reaction == RLBM_REACTION_EXPLICIT) {
+        reload_barrier();
+        const ChemLds<LOC_T> cl{&s_dv[0][threadIdx.x], &s_dv[M][threadIdx.x], nullptr};
+        double ra[M], fin[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) ra[a] = s_ra[a][threadIdx.x];
+        double rY = rho;   // the density that normalises the composition
+        if constexpr (W) {
+            rY = 0.0;
+#pragma unroll
+            for (int a = 0; a < M; ++a) rY += ra[a];
+        }
+        int fail_r = 0;
+        reaction_increment<M, LOC_T, false>(mc, ra, rY, U, T, L.substeps, cl, fin, &fail_r);
+        if (fail_r) atomicOr(flag, 1);
+        // Delta rho_a against the densities read again from LDS, so that they
+        // need not stay in registers through the sub-steps
+        reload_barrier();
+#pragma unroll
+        for (int a = 0; a < M; ++a) prm[(PRM_SP + 6 * a + 5) * N + node] = fin[a] - s_ra[a][threadIdx.x];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -613,13 +641,14 @@ __device__ __forceinline__ void node_gradients(const LatDev& L, int node) {
 }
 
 // ---------------------------------------------------------------------------
-// k_chem: reaction increment of every node (eq. R3), l forward-Euler
-// sub-steps at frozen specific internal energy (IMPL: linearly implicit
-// sub-steps), reading rho_a, rho, U, T from the per-node record and writing
-// Delta rho_a into it; then the node's same-time gradients.  The stencil's
-// neighbour loads are latency-bound and the chemistry is arithmetic-bound, so
-// the two share one launch.  A launch serves the lattices of its scheme; the
-// blocks of the others return at once.
+// k_gradients: the same-time gradients of every node of the lattices whose
+// reaction increment k_local has written (the forward-Euler update).
+// k_chem_implicit: for lattices with the linearly implicit update, that
+// increment (reading rho_a, rho, U, T from the per-node record and writing
+// Delta rho_a into it), then the gradients.  The stencil's neighbour loads
+// are latency-bound and the implicit chemistry arithmetic-bound, so the two
+// share one launch.  A launch serves the lattices of its scheme; the blocks of
+// the others return at once.
 // ---------------------------------------------------------------------------
 template <int M, bool IMPL>
 __device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const int* __restrict__ blk, int n_lat,
@@ -631,38 +660,43 @@ __device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const
     if ((L.reaction == RLBM_REACTION_LINEARLY_IMPLICIT) != IMPL) return;
     const int node = (b - blk[lj]) * 256 + threadIdx.x;
     if (node >= L.N) return;
-    MechC mc = *as_const(L.mech);
-    double* prm = L.prm;
-    const size_t N = (size_t)L.N;
-    __shared__ double s_c[M][256], s_g[M][256], s_q[IMPL ? M : 1][256];
-    const ChemLds<256> ls{&s_c[0][threadIdx.x], &s_g[0][threadIdx.x], IMPL ? &s_q[0][threadIdx.x] : nullptr};
-    double rho_a[M], fin[M];
+    if constexpr (IMPL) {
+        MechC mc = *as_const(L.mech);
+        double* prm = L.prm;
+        const size_t N = (size_t)L.N;
+        __shared__ double s_c[M][256], s_g[M][256], s_q[M][256];
+        const ChemLds<256> ls{&s_c[0][threadIdx.x], &s_g[0][threadIdx.x], &s_q[0][threadIdx.x]};
+        double rho_a[M], fin[M];
 #pragma unroll
-    for (int a = 0; a < M; ++a) rho_a[a] = prm[(PRM_SP + 6 * a) * N + node];
-    // the density that normalises the composition (sum_a rho_a in the
-    // weakly coupled storage)
-    double rho = prm[PRM_RHO * N + node];
-    if (L.weak) {
-        rho = 0.0;
+        for (int a = 0; a < M; ++a) rho_a[a] = prm[(PRM_SP + 6 * a) * N + node];
+        // the density that normalises the composition (sum_a rho_a in the
+        // weakly coupled storage)
+        double rho = prm[PRM_RHO * N + node];
+        if (L.weak) {
+            rho = 0.0;
 #pragma unroll
-        for (int a = 0; a < M; ++a) rho += rho_a[a];
+            for (int a = 0; a < M; ++a) rho += rho_a[a];
+        }
+        const double U = prm[PRM_UINT * N + node];
+        const double T = prm[PRM_T * N + node];
+        int fail = 0;
+        reaction_increment<M, 256, true>(mc, rho_a, rho, U, T, L.substeps, ls, fin, &fail);
+        if (fail) atomicOr(flag, 1);
+        // Delta rho_a against the densities read again, so that they need not
+        // stay in registers through the sub-steps
+        reload_barrier();
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+            prm[(PRM_SP + 6 * a + 5) * N + node] = fin[a] - prm[(PRM_SP + 6 * a) * N + node];
+    } else {
+        (void)flag;
     }
-    const double U = prm[PRM_UINT * N + node];
-    const double T = prm[PRM_T * N + node];
-    int fail = 0;
-    reaction_increment<M, 256, IMPL>(mc, rho_a, rho, U, T, L.substeps, ls, fin, &fail);
-    if (fail) atomicOr(flag, 1);
-    // Delta rho_a against the densities read again, so that they need not
-    // stay in registers through the sub-steps
-    reload_barrier();
-#pragma unroll
-    for (int a = 0; a < M; ++a) prm[(PRM_SP + 6 * a + 5) * N + node] = fin[a] - prm[(PRM_SP + 6 * a) * N + node];
     node_gradients<M>(L, node);
 }
 
 template <int M>
-__global__ __launch_bounds__(256) void k_chem(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                              int n_lat, long long t, int* __restrict__ flag) {
+__global__ __launch_bounds__(256) void k_gradients(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+                                                   int n_lat, long long t, int* __restrict__ flag) {
     chem_body<M, false>(lats, blk, n_lat, t, flag);
 }
 
@@ -1767,7 +1801,7 @@ static hipError_t launch_step_phase(int phase, int M, int weak, const StepLaunch
                                                     a.lats, a.blk, a.n_lat, a.t, a.flag))
     } else if (phase == 2) {
         if (a.schemes & (1u << RLBM_REACTION_EXPLICIT))
-            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
+            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_gradients<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
                                                     a.blk, a.n_lat, a.t, a.flag))
         if (a.schemes & (1u << RLBM_REACTION_LINEARLY_IMPLICIT))
             RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem_implicit<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,

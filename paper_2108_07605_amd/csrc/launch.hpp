@@ -23,7 +23,8 @@ struct StepLaunch {
 constexpr int BC_NODES = 8;
 
 // phase 0: boundary (BC_NODES interface nodes per block); phases 1 and 2:
-// moments and diffusion, chemistry and gradients (256-thread blocks over
+// moments, diffusion and forward-Euler chemistry, then gradients (with the
+// linearly implicit chemistry first where selected) (256-thread blocks over
 // nodes); phase 3: update (one block per 64 nodes).
 hipError_t launch_phase(int phase, int M, int storage, int weak, const StepLaunch& a);
 // weak: the weakly coupled storage (all M species lattices, no slaved species)

@@ -25,7 +25,7 @@ _FACE_CODES = {"periodic": FACE_PERIODIC, "wall": FACE_WALL, "inlet": FACE_INLET
 _STORAGE = {"f64": STORAGE_F64, "f32dev": STORAGE_F32_DEV}
 _REACTION = {"explicit": REACTION_EXPLICIT, "implicit": REACTION_LINEARLY_IMPLICIT}
 # kernels of one step, in launch order (rlbm_kernel_times)
-KERNELS = ("boundary", "local", "chem", "update")
+KERNELS = ("boundary", "local", "gradients", "update")
 
 EXPORTS = (
     "rlbm_mech_create", "rlbm_mech_destroy", "rlbm_lattice_bytes", "rlbm_lattice_create",

@@ -178,11 +178,10 @@ constexpr int LOC_T = 256;   // k_local threads per block
 // the three components at once.  Its matrix is strictly row diagonally
 // dominant with margin 1 (the off-diagonal row sums are -1/(2 tau_a)), so
 // Doolittle LU without pivoting is stable.  Rows are generated on the fly
-// from cY_b = -common Y_b / 2 (A_ab = K_ab cY_b), the forward substitution
-// runs with the factorisation, and beta_a = 1/(2 tau_a + 1) is written as
-// soon as row a has its 1/tau_a.  The velocity differences u_a - u and the
+// from cY_b = -common Y_b / 2 (A_ab = K_ab cY_b) and the forward substitution
+// runs with the factorisation.  The velocity differences u_a - u and the
 // densities rho_a come from k_local's LDS columns, the node's scalars from
-// its registers; writes V_a, beta_a and the energy flux base Qb plus
+// its registers; writes V_a and the energy flux base Qb plus
 // omega1 sum_a H_a rho_a V_a to the per-node record.
 template <int M, int W>
 __device__ __forceinline__ void stefan_maxwell(const LatDev& L, int node, const LocalLds& ls, double T, double rho,
@@ -209,7 +208,6 @@ __device__ __forceinline__ void stefan_maxwell(const LatDev& L, int node, const 
         for (int c = 0; c < M; ++c)
             if (c != i) st += mc.Kab[i][c] * cY[c];
         const double inv_tau = -2.0 * st;
-        st_at(prm + (PRM_SP + 6 * i + 4) * N, node, inv_tau / (2.0 + inv_tau));   // beta_a = dt/(2 tau_a + dt)
         double lrow[M];
 #pragma unroll
         for (int j = 0; j < i; ++j) {
@@ -265,6 +263,19 @@ __device__ __forceinline__ void stefan_maxwell(const LatDev& L, int node, const 
     }
 #pragma unroll
     for (int dd = 0; dd < 3; ++dd) st_at(prm + (PRM_QB + dd) * N, node, Qb[dd] + omega1 * diff[dd]);
+}
+
+// Relaxation rates of a node (sections 2.3 and 3.4) from its temperature,
+// pressure and mixture gas constant Rmix = R_univ sum_a Y_a / m_a: the
+// factor `common` of 1/tau_ab = common K_ab (eqs. betaa, taua), and omega,
+// omega_1 of the momentum and energy lattices.
+__device__ __forceinline__ void relax_rates(MechC mc, double T, double P, double Rmix, double& common,
+                                            double& omega, double& omega1) {
+    const double lnr = log(T * mc.inv_T_ref);
+    common = mc.R_univ * mc.R_univ * T / Rmix * P * mc.inv_P_ref * exp(-mc.D_exp * lnr);
+    const double mu = mc.mu_ref * exp(mc.mu_exp * lnr);
+    omega = 1.0 / (mu / P + 0.5);
+    omega1 = 1.0 / (mu * mc.inv_Pr / P + 0.5);
 }
 
 // ---------------------------------------------------------------------------
@@ -506,16 +517,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // temperature (eq. temperature), Newton from the previous step's value
     const double T = solve_T<M>(mc, Y, U, aux[AUX_T * N + node], &fail);
     if (fail) atomicOr(flag, 1);
-    const double inv_mix_m = mix_inv_m<M>(mc, Y);
-    const double th = mc.R_univ * inv_mix_m * T;
+    const double Rmix = mc.R_univ * mix_inv_m<M>(mc, Y);
+    const double th = Rmix * T;
     const double P = rho * th;
 
-    // relaxation rates (sections 2.3 and 3.4)
-    const double lnr = log(T * mc.inv_T_ref);
-    const double common = mc.R_univ * T / inv_mix_m * P * mc.inv_P_ref * exp(-mc.D_exp * lnr);
-    const double mu = mc.mu_ref * exp(mc.mu_exp * lnr);
-    const double omega = 1.0 / (mu / P + 0.5);
-    const double omega1 = 1.0 / (mu * mc.inv_Pr / P + 0.5);
+    // relaxation rates (sections 2.3 and 3.4); k_update derives the same
+    // values again from the record rather than reading them
+    double common, omega, omega1;
+    relax_rates(mc, T, P, Rmix, common, omega, omega1);
 
     // enthalpy-weighted composition moments sum_a H_a(T') Y_a = sum_kk T'^kk Pk
     double Pk[6];
@@ -561,11 +570,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     for (int d = 0; d < 3; ++d) prm[(PRM_U + d) * N + node] = u[d];
     prm[PRM_T * N + node] = T;
     prm[PRM_UINT * N + node] = U;
-    prm[PRM_TH * N + node] = th;
-    prm[PRM_OMEGA * N + node] = omega;
-    prm[PRM_COMMON * N + node] = common;
-    prm[PRM_WQ * N + node] = omega - omega1;
-    prm[PRM_CC * N + node] = 0.5 * (2.0 - omega1) * P;
     stefan_maxwell<M, W>(L, node, ls, T, rho, common, omega1, Y, Qb, rho * inv_rhoY);
 
     // reaction increment (eq. R3, forward Euler), with the LDS columns the
@@ -718,6 +722,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // a compile-time index.  Product-form factors along y and z are formed once
 // per row of three velocities (fixed c_y, c_z); the x factor per velocity.
 // ---------------------------------------------------------------------------
+// Record rows k_update reads: rho, u, T, U (0..5), the energy-flux base
+// (9..11), per species slot rho_a, V_a and Delta rho_a (c = 0..3, 5), and the
+// six gradient rows.  theta, omega, the diffusion factor, omega - omega_1,
+// (2 - omega_1) P / 2 and beta_a are derived in the kernel instead.
+__host__ __device__ constexpr int upd_loaded_rows(int M) { return 9 + 5 * M + 6; }
+__host__ __device__ constexpr int upd_loaded_row(int M, int idx) {
+    return idx < 6 ? idx
+                   : idx < 9 ? idx + 3
+                             : idx < 9 + 5 * M ? PRM_SP + 6 * ((idx - 9) / 5) + ((idx - 9) % 5 < 4 ? (idx - 9) % 5 : 5)
+                                               : prm_grad(M) + (idx - 9 - 5 * M);
+}
+
 constexpr int UPD_NODES = 64;
 constexpr int UPD_WAVES = 3;
 constexpr int UPD_THREADS = UPD_WAVES * UPD_NODES;
@@ -785,25 +801,28 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
     const RLBM_GLOBAL double* prm = as_global(L.prm);
     const int nif = L.n_if;
 
-    // stage the record, species rows in slot order, and (FP32 storage) this
-    // node's reference scales: wave w takes rows w, w + 3, ..., one node per
-    // lane; every load is in flight before the first LDS write
+    // stage the record's stored rows (species rows in slot order) and (FP32
+    // storage) this node's reference scales: wave w takes stored rows w,
+    // w + 3, ..., one node per lane; every load is in flight before the first
+    // LDS write.  The rows derived below are not read.
     {
-        constexpr int RPW = (NR + UPD_WAVES - 1) / UPD_WAVES;
+        constexpr int NLD = upd_loaded_rows(M);
+        constexpr int RPW = (NLD + UPD_WAVES - 1) / UPD_WAVES;
         constexpr int LPW = (NS + UPD_WAVES - 1) / UPD_WAVES;
         const int nd = node0 + lane < N ? node0 + lane : 0;   // beyond the end: a placeholder node
         double v[RPW];
         float w[LPW];
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
-            const int row = wave + UPD_WAVES * q;
+            const int idx = wave + UPD_WAVES * q;
+            const int row = upd_loaded_row(M, idx < NLD ? idx : 0);
             int srow = row;
             if (row >= PRM_SP && row < prm_grad(M)) {
                 const int slot = (row - PRM_SP) / 6, c = (row - PRM_SP) % 6;
                 const int a = W ? slot : (slot < M - 1 ? slot + (slot >= s ? 1 : 0) : s);
                 srow = PRM_SP + 6 * a + c;
             }
-            v[q] = ld_at(prm + (size_t)(row < NR ? srow : 0) * L.N, nd);   // unconditional: no waits between
+            v[q] = ld_at(prm + (size_t)srow * L.N, nd);   // unconditional: no waits between
         }
         if constexpr (sizeof(S) == 4) {
             const RLBM_GLOBAL float* sc = scale_at(L, par, nd);
@@ -815,8 +834,8 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
         }
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
-            const int row = wave + UPD_WAVES * q;
-            if (row < NR) sp[row][lane] = v[q];
+            const int idx = wave + UPD_WAVES * q;
+            if (idx < NLD) sp[upd_loaded_row(M, idx)][lane] = v[q];
         }
         if constexpr (sizeof(S) == 4) {
 #pragma unroll
@@ -869,6 +888,48 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
     S fin[NL];
     const int i_first = 9 * (c2 + 1);
     if (valid) load(i_first, offz + o.y[0] + o.x[0], fin);
+    __syncthreads();
+    // the derived rows, once per node by the first wave: theta, the
+    // relaxation rates (as k_local computes them) and beta_a =
+    // 1/(2 tau_a + 1) with 1/tau_a = common sum_{b != a} K_ab Y_b (eqs.
+    // betaa, taua), Y in slot order
+    if (wave == 0) {
+        MechC mc = *as_const(L.mech);
+        const RLBM_CONST double* slotc = as_const(L.slotc);
+        const double T = sp[PRM_T][lane], rho = sp[PRM_RHO][lane];
+        double ry = rho;   // Y_a = rho_a / rho, or rho_a / sum_b rho_b (weakly coupled)
+        if constexpr (W) {
+            ry = 0.0;
+#pragma unroll
+            for (int q = 0; q < M; ++q) ry += sp[PRM_SP + 6 * q][lane];
+        }
+        const double iry = 1.0 / ry;
+        double Y[M];
+        double Rmix = 0.0;
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            Y[q] = sp[PRM_SP + 6 * q][lane] * iry;
+            Rmix = fma(Y[q], slotc[q], Rmix);
+        }
+        const double th = Rmix * T, P = rho * th;
+        double common, omega, omega1;
+        relax_rates(mc, T, P, Rmix, common, omega, omega1);
+        sp[PRM_TH][lane] = th;
+        sp[PRM_OMEGA][lane] = omega;
+        sp[PRM_COMMON][lane] = common;
+        sp[PRM_WQ][lane] = omega - omega1;
+        sp[PRM_CC][lane] = 0.5 * (2.0 - omega1) * P;
+        const RLBM_CONST double* Ks = slotc + M;
+#pragma unroll
+        for (int j = 0; j < NSP; ++j) {
+            double st = 0.0;
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+                if (q != j) st = fma(Ks[j * M + q], Y[q], st);
+            const double inv_tau = common * st;
+            sp[PRM_SP + 6 * j + 4][lane] = inv_tau / (2.0 + inv_tau);
+        }
+    }
     __syncthreads();
     if (!valid) return;
 

@@ -552,18 +552,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
     }
 
-    // neighbour-facing fields
-    aux[AUX_RHO * N + node] = rho;
+    // neighbour-facing fields: Phi and the enthalpy moments for the gradient
+    // stencil, T for the next step's Newton start; rho, u and Y only where
+    // an outlet reads them (the first interior node of the x+ face)
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        aux[(AUX_U + d) * N + node] = u[d];
+    for (int d = 0; d < 3; ++d)
         aux[(AUX_PHI + d) * N + node] = rho * u[d] * (1.0 - 3.0 * th) - rho * u[d] * u[d] * u[d];
-    }
     aux[AUX_T * N + node] = T;
 #pragma unroll
-    for (int a = 0; a < M; ++a) aux[(AUX_Y + a) * N + node] = Y[a];
-#pragma unroll
     for (int kk = 0; kk < 6; ++kk) aux[(AUX_Y + M + kk) * N + node] = Pk[kk];
+    if (L.n_out > 0 && x == L.nx - 2) {
+        aux[AUX_RHO * N + node] = rho;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) aux[(AUX_U + d) * N + node] = u[d];
+#pragma unroll
+        for (int a = 0; a < M; ++a) aux[(AUX_Y + a) * N + node] = Y[a];
+    }
 
     prm[PRM_RHO * N + node] = rho;
 #pragma unroll

@@ -105,6 +105,7 @@ def test_abc_box_initial_state_exact():
     ("tube", dict(nx=96, coupling="weak"), [1, 60]),
     ("reactor", dict(nx=3, ny=3, nz=2, T0=1500.0, X_radical=0.01, reaction="implicit", coupling="weak"), [1, 30]),
     ("channel2d", dict(nx=40, ny=10, nz=1, inlet="inlet_local", coupling="weak", substeps=3), [1, 20]),
+    ("channel3d", dict(nx=256, ny=4, nz=3, perturb=0.5), [1, 6]),    # full 256-node blocks
 ])
 def test_nine_species_parity(mech9, name, kw, steps):
     print(f"case {name} {kw} M=9 f64", flush=True)
@@ -171,6 +172,17 @@ def test_bounce_back_box_conservation():
         assert inv1[-1] == 0.0
         for k in [0, 4] + list(range(5, 5 + E)):
             assert abs(inv1[k] - inv0[k]) <= tol * abs(inv0[k]), (storage, k)
+
+
+def test_long_periodic_box_parity():
+    """A periodic box 256 nodes long in x (every block one x row, the
+    stencils wrapping at both ends of the row)."""
+    print("case abc_box 256x2x2 M=3 f64", flush=True)
+    case = wl.make_case("abc_box", nx=256, ny=2, nz=2)
+    lat, ora, out = _run_pair(case, [1, 20])
+    for gp, op, gf, of in out:
+        _compare_pops(gp, op, TOL64)
+        _compare_fields(gf, of, TOL64, _u_floor(case))
 
 
 @pytest.mark.parametrize("coupling", ["strong", "weak"])

@@ -64,7 +64,7 @@ struct LatDev {
     const MechDev* mech;
     void* pop[2];               // ping-pong population buffers [L][27][N]
     double* aux;                // [14 + M][N]: rho, ux, uy, uz, T, Phi_x,y,z, Y_0..Y_{M-1}, P_0..P_5
-    double* prm;                // [14 + 6 M][N] per-node record from k_local for k_update
+    double* prm;                // [14 + 6 M + 6][N] per-node record for k_update
     const int* if_index;        // [N]: interface slot or -1 (NULL if n_if == 0)
     const int* if_node;         // [n_if]
     const unsigned* if_mask;    // [n_if] incoming set D as a 27-bit mask
@@ -86,8 +86,11 @@ struct LatDev {
 
 constexpr int AUX_RHO = 0, AUX_U = 1, AUX_T = 4, AUX_PHI = 5, AUX_Y = 8;
 
-// Per-node record written by k_local for k_update (structure of arrays,
-// row r of node n at prm[r * N + n]):
+// Per-node record written by k_local (the reaction increment also by
+// k_chem_implicit, the gradients by k_gradients) for k_update (structure of
+// arrays, row r of node n at prm[r * N + n]).  The rows PRM_TH, PRM_OMEGA,
+// PRM_COMMON, PRM_WQ, PRM_CC and the beta_a rows are not stored: k_update
+// derives them once per node and keeps them in its LDS copy of the record.
 constexpr int PRM_RHO = 0, PRM_U = 1, PRM_T = 4, PRM_UINT = 5, PRM_TH = 6, PRM_OMEGA = 7, PRM_COMMON = 8,
               PRM_QB = 9, PRM_WQ = 12, PRM_CC = 13, PRM_SP = 14;
 // species rows: PRM_SP + 6 a + {0: rho_a, 1..3: V_a, 4: beta_a, 5: drho_a}

@@ -49,7 +49,7 @@ class GpuBackend:
         self.mech = rlbm.Mechanism(mech) if isinstance(mech, dict) else mech
         self.storage = storage
         self.keep = keep            # "fields", "populations" or "none"
-        self._batch = None
+        self._batches = []
         self._batch_key = None
 
     def nbytes(self, case):
@@ -59,11 +59,18 @@ class GpuBackend:
         return self.rlbm.Lattice(case, storage=self.storage, mech=self.mech).set_state()
 
     def step(self, lattices, steps):
-        key = tuple(id(l) for l in lattices)
+        # one batch per storage layout: lattices with a slaved species and
+        # weakly coupled ones (one lattice more) cannot share launches
+        groups = {}
+        for k, lat in enumerate(lattices):
+            groups.setdefault(lat.L, []).append(k)
+        key = tuple((L, tuple(id(lattices[k]) for k in ks)) for L, ks in sorted(groups.items()))
         if key != self._batch_key:
-            self._batch = self.rlbm.Batch(lattices)
+            self._batches = [(self.rlbm.Batch([lattices[k] for k in ks]), ks)
+                             for _, ks in sorted(groups.items())]
             self._batch_key = key
-        self._batch.step(steps)
+        for batch, ks in self._batches:
+            batch.step([steps[k] for k in ks])
 
     def finish(self, lat):
         if self.keep == "fields":

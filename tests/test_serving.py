@@ -120,14 +120,15 @@ def test_percentile_nearest_rank():
 @pytest.mark.gpu
 def test_served_results_identical_to_alone(mech9):
     """Requests of different kinds and sizes served together (admitted at
-    different times, stepped in chunks of varying length) end bit-identical
-    to the same requests stepped alone."""
+    different times, stepped in chunks of varying length, weakly coupled ones
+    in a batch of their own, one with the linearly implicit update) end
+    bit-identical to the same requests stepped alone."""
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2108_07605_amd import rlbm, workloads as wl
     from paper_2108_07605_amd.serving import GpuBackend
-    print("case serving mix of 6 requests, f32dev", flush=True)
+    print("case serving mix of 8 requests, f32dev", flush=True)
     cases = [
         wl.make_case("reactor", seed=1, nx=6, ny=6, nz=6, mech=mech9, T0=1300.0),
         wl.make_case("tube", seed=2, nx=150, mech=mech9),
@@ -135,8 +136,11 @@ def test_served_results_identical_to_alone(mech9):
         wl.make_case("tube", seed=4, nx=77, mech=mech9),
         wl.make_case("channel3d", seed=5, nx=16, ny=8, nz=6, mech=mech9),
         wl.make_case("reactor", seed=6, nx=4, ny=5, nz=3, mech=mech9, T0=1200.0),
+        wl.make_case("tube", seed=7, nx=90, mech=mech9, coupling="weak"),
+        wl.make_case("channel2d", seed=8, nx=24, ny=8, nz=1, mech=mech9, coupling="weak",
+                     reaction="implicit"),
     ]
-    steps = [23, 41, 17, 60, 9, 33]
+    steps = [23, 41, 17, 60, 9, 33, 29, 14]
     reqs = [Request(k, 0.002 * k, c, s) for k, (c, s) in enumerate(zip(cases, steps))]
     be = GpuBackend(mech9, storage="f32dev", keep="populations")
     srv = Server(be, budget_bytes=1e10, max_slots=4, round_s=1e-4, rate_guess=1e8, min_chunk=3,

@@ -243,8 +243,10 @@ int rlbm_kernel_times(rlbm_lattice* lat, double* ms, int64_t* counts, int n);
 /* Batches of independent lattices advanced together.  Each kernel phase of a
  * step is one launch over the flattened (lattice, node-block) work list, so
  * small and uneven instances share the GPU.  All lattices of a batch must be
- * on the same device, use the same species count and storage format, and are
- * advanced on the stream of the first one.  A batch step is equivalent, bit
+ * on the same device, use the same species count, storage format and
+ * coupling (a slaved species, or RLBM_SLAVED_NONE for all), and are advanced
+ * on the stream of the first one (RLBM_EINVAL otherwise).  They may differ in
+ * everything else, the reaction scheme included.  A batch step is equivalent, bit
  * for bit, to rlbm_step on each lattice.  The batch keeps its tables in the
  * caller-owned device memory dev_mem of rlbm_batch_bytes(k) bytes. */
 typedef struct rlbm_batch rlbm_batch;

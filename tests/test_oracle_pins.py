@@ -696,6 +696,64 @@ def test_simplified_inlet_keeps_the_local_state(mech9):
     assert np.abs(mo["u"][0] - fi["u"]).max() > 1e-3 * abs(fi["u"])
 
 
+def _acoustic_pulse_reflection(right, nx=120, amp=1e-3, T0=1200.0, width=4.0):
+    """A Gaussian density pulse at rest, 0.6 nx from a bounce-back wall on x-,
+    in a non-reacting binary mixture; returns the largest pressure deviation
+    between the pulse's start and the x+ face (15 nodes from both), relative
+    to amp P0, once the right-going half has had time to reach the x+ face
+    and any reflection to come 0.2 nx back."""
+    case = wl.make_case("binary", nx=nx, amp=0.0)
+    mech = case["mech"]
+    x = np.arange(nx, dtype=float)
+    T = np.full(nx, T0)
+    Y = np.repeat(np.asarray(case["init"]["Y"]).reshape(2, nx)[:, :1], nx, axis=1)
+    rho0 = float(wl._rho_from_state(mech, mech["P0"], T, Y)[0])
+    rho = rho0 * (1.0 + amp * np.exp(-((x - 0.6 * nx) / width) ** 2))
+    P0 = rho0 * (mech["R_univ"] * (Y[:, 0] / np.asarray(mech["molar_mass"])).sum()) * T0
+    case["init"] = {"rho": rho, "u": np.zeros((3, nx)), "T": T, "Y": Y}
+    case["faces"] = [{"type": "bounceback"}, dict(right, P_inf=P0) if right["type"] == "outlet" else right,
+                     {"type": "periodic"}, {"type": "periodic"}, {"type": "periodic"}, {"type": "periodic"}]
+    o = Oracle(case)
+    f = o.fields()
+    c = math.sqrt(1.4 * float(np.mean(f["P"] / f["rho"])))      # sound speed, gamma = 7/5
+    o.step(int(((nx - 1 - 0.6 * nx) + 0.2 * nx) / c))
+    f = o.fields()
+    win = (x > 0.6 * nx + 15) & (x < nx - 15)
+    return np.abs(f["P"][win] - P0).max() / (P0 * amp)
+
+
+def test_lodi_outlet_lets_an_acoustic_pulse_leave():
+    """The partially non-reflecting outlet (section 4.4): a pressure pulse
+    that a bounce-back wall sends back with a large share of its amplitude
+    leaves through the outlet with a reflection more than ten times smaller
+    (its relaxation towards P_inf is slow against the pulse)."""
+    wall = _acoustic_pulse_reflection({"type": "bounceback"})
+    lodi = _acoustic_pulse_reflection({"type": "outlet", "sigma": 0.25})
+    assert wall > 0.2, wall
+    assert lodi < 0.1 * wall, (lodi, wall)
+
+
+def test_lodi_outlet_relaxes_pressure_towards_p_inf():
+    """The outlet's incoming wave L1 = sigma (1 - Ma^2) c / L_x (P - P_inf)
+    pulls a domain at rest and 1% above P_inf back towards P_inf (a reversed
+    sign drives it away)."""
+    nx, T0 = 40, 1200.0
+    case = wl.make_case("binary", nx=nx, amp=0.0)
+    mech = case["mech"]
+    T = np.full(nx, T0)
+    Y = np.repeat(np.asarray(case["init"]["Y"]).reshape(2, nx)[:, :1], nx, axis=1)
+    rho = wl._rho_from_state(mech, mech["P0"], T, Y)
+    P_inf = float(rho[0]) * (mech["R_univ"] * (Y[:, 0] / np.asarray(mech["molar_mass"])).sum()) * T0
+    case["init"] = {"rho": 1.01 * rho, "u": np.zeros((3, nx)), "T": T, "Y": Y}
+    case["faces"] = [{"type": "bounceback"}, {"type": "outlet", "P_inf": P_inf, "sigma": 0.25},
+                     {"type": "periodic"}, {"type": "periodic"}, {"type": "periodic"}, {"type": "periodic"}]
+    o = Oracle(case)
+    dev0 = float(np.mean(o.fields()["P"])) / P_inf - 1.0
+    o.step(400)
+    dev = float(np.mean(o.fields()["P"])) / P_inf - 1.0
+    assert dev0 > 0.009 and 0.0 < dev < 0.9 * dev0, (dev0, dev)
+
+
 def test_boundary_post_conditions(mech9):
     """After the boundary step the interface nodes carry the imposed values:
     TMS walls u = 0 and T = T_w(x) (section 4.2.2), the inlet u = u^in and

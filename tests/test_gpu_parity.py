@@ -174,6 +174,21 @@ def test_bounce_back_box_conservation():
             assert abs(inv1[k] - inv0[k]) <= tol * abs(inv0[k]), (storage, k)
 
 
+@pytest.mark.parametrize("coupling", ["strong", "weak"])
+def test_three_species_linearly_implicit(coupling):
+    """The linearly implicit update with three species (a 2x2 reduced system)
+    and rates x10 (the box burns from 1000 to 2060 K in 30 steps), with a
+    slaved species and in the weakly coupled storage."""
+    mech = wl.scaled_rates(wl.mechanism_abc(), 10.0)
+    case = wl.make_case("abc_box", nx=12, ny=4, nz=4, mech=mech, reaction="implicit", substeps=1,
+                        coupling=coupling)
+    print(f"case abc_box 12x4x4 M=3 implicit x10 {coupling}", flush=True)
+    lat, ora, out = _run_pair(case, [1, 30])
+    for gp, op, gf, of in out:
+        _compare_pops(gp, op, TOL64)
+        _compare_fields(gf, of, TOL64, _u_floor(case))
+
+
 def test_long_periodic_box_parity():
     """A periodic box 256 nodes long in x (every block one x row, the
     stencils wrapping at both ends of the row)."""

@@ -606,8 +606,6 @@ int rlbm_set_state(rlbm_lattice* lat, const double* rho, const double* u, const 
 }
 
 static int step_one(rlbm_lattice* lat, long long t) {
-    const Plan& p = lat->plan;
-    (void)p;
     const int nb_nodes = (int)((lat->geo.N + 255) / 256);
     const int nb_if = (int)((lat->geo.if_node.size() + BC_NODES - 1) / BC_NODES);
     const int nb64 = (int)((lat->geo.N + 63) / 64);

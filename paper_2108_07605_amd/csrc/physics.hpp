@@ -192,13 +192,14 @@ __device__ __forceinline__ double mix_inv_m(MechC mc, const double* Y) {
 template <int M>
 __device__ __forceinline__ double solve_T(MechC mc, const double* Y, double U,
                                           double T, int* fail) {
-    double c[6];
+    // species-major, so that one species' six coefficients are live at a
+    // time (each c[k] still sums over a in order)
+    double c[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        double s = 0.0;
+    for (int a = 0; a < M; ++a) {
+        const RLBM_CONST double* u = mc.uc[a];
 #pragma unroll
-        for (int a = 0; a < M; ++a) s += Y[a] * mc.uc[a][k];
-        c[k] = s;
+        for (int k = 0; k < 6; ++k) c[k] += Y[a] * u[k];
     }
     c[0] -= U;
     for (int it = 0; it < 100; ++it) {

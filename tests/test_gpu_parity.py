@@ -375,6 +375,34 @@ def _window(pops, case, cx, cy, cz, h=2):
     return idx
 
 
+def test_full_size_channel2d_vs_oracle(mech9):
+    """The 1024x64x1 channel at its full size, every node (TMS walls, flux
+    inlet and LODI outlet included): FP64 storage against the oracle element
+    by element after 1 and 3 steps, and FP32 deviation storage within its
+    tolerance after 3."""
+    rlbm = _gpu()
+    print("case channel2d 1024x64x1 f64 + f32dev, all nodes", flush=True)
+    case = wl.make_case("channel2d", mech=mech9)
+    assert (case["nx"], case["ny"], case["nz"]) == (1024, 64, 1)
+    lat64 = rlbm.Lattice(case, storage="f64").set_state()
+    lat32 = rlbm.Lattice(case, storage="f32dev").set_state()
+    ora = Oracle(case)
+    done = 0
+    for n in (1, 3):
+        lat64.step(n - done)
+        lat32.step(n - done)
+        ora.step(n - done)
+        done = n
+        of = ora.fields()
+        _compare_pops(lat64.populations(), ora.populations(), TOL64)
+        _compare_fields(lat64.fields(), of, TOL64, _u_floor(case))
+    gf = lat32.fields()
+    ey = [_nerr(gf["Y"][a], of["Y"][a], 1e-6) for a in range(of["Y"].shape[0])]
+    et = _nerr(gf["T"], of["T"])
+    print(f"f32dev vs oracle, channel2d 1024x64 3 steps: Y {max(ey):.3e} T {et:.3e}", flush=True)
+    assert max(ey) <= TOL32 and et <= TOL32
+
+
 def test_full_size_channel3d_sampled(mech9):
     """512x64x64 channel in the benchmark's launch configuration: the
     post-step populations at sampled interior nodes equal the oracle's update

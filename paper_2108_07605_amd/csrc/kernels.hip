@@ -21,6 +21,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "launch.hpp"
 #include "physics.hpp"
 
@@ -117,6 +119,19 @@ __device__ __forceinline__ void st_at(RLBM_GLOBAL S* base, int idx, S v) {
     *(RLBM_GLOBAL S*)((RLBM_GLOBAL char*)base + (unsigned)(idx * (int)sizeof(S))) = v;
 }
 
+// A correction row of the per-node record: FP32 (rounded to nearest even)
+// when F32, else FP64.
+template <bool F32>
+__device__ __forceinline__ void st_corr(RLBM_GLOBAL double* prm, int row, size_t N, int node, double v) {
+    if constexpr (F32) st_at(reinterpret_cast<RLBM_GLOBAL float*>(prm + (size_t)row * N), node, (float)v);
+    else st_at(prm + (size_t)row * N, node, v);
+}
+template <bool F32>
+__device__ __forceinline__ double ld_corr(const RLBM_GLOBAL double* prm, int row, size_t N, int node) {
+    if constexpr (F32) return (double)ld_at(reinterpret_cast<const RLBM_GLOBAL float*>(prm + (size_t)row * N), node);
+    else return ld_at(prm + (size_t)row * N, node);
+}
+
 // ---------------------------------------------------------------------------
 // work-list helpers
 // ---------------------------------------------------------------------------
@@ -183,7 +198,7 @@ constexpr int LOC_T = 256;   // k_local threads per block
 // densities rho_a come from k_local's LDS columns, the node's scalars from
 // its registers; writes V_a and the energy flux base Qb plus
 // omega1 sum_a H_a rho_a V_a to the per-node record.
-template <int M, int W>
+template <int M, int W, bool F32>
 __device__ __forceinline__ void stefan_maxwell(const LatDev& L, int node, const LocalLds& ls, double T, double rho,
                                                double common, double omega1, const double* Y, const double* Qb,
                                                double rho_over_rhoY) {
@@ -240,7 +255,7 @@ __device__ __forceinline__ void stefan_maxwell(const LatDev& L, int node, const 
 #pragma unroll
             for (int j = i + 1; j < M; ++j) sm -= Uu[i][j] * V[j][dd];
             V[i][dd] = sm * inv_diag[i];
-            st_at(prm + (PRM_SP + 6 * i + 1 + dd) * N, node, V[i][dd]);
+            st_corr<F32>(prm, PRM_SP + 6 * i + 1 + dd, N, node, V[i][dd]);
         }
     }
     // energy flux: Qb + omega1 sum_a H_a rho_a V_a
@@ -262,7 +277,7 @@ __device__ __forceinline__ void stefan_maxwell(const LatDev& L, int node, const 
         (void)rho_over_rhoY;
     }
 #pragma unroll
-    for (int dd = 0; dd < 3; ++dd) st_at(prm + (PRM_QB + dd) * N, node, Qb[dd] + omega1 * diff[dd]);
+    for (int dd = 0; dd < 3; ++dd) st_corr<F32>(prm, PRM_QB + dd, N, node, Qb[dd] + omega1 * diff[dd]);
 }
 
 // Relaxation rates of a node (sections 2.3 and 3.4) from its temperature,
@@ -574,7 +589,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     for (int d = 0; d < 3; ++d) prm[(PRM_U + d) * N + node] = u[d];
     prm[PRM_T * N + node] = T;
     prm[PRM_UINT * N + node] = U;
-    stefan_maxwell<M, W>(L, node, ls, T, rho, common, omega1, Y, Qb, rho * inv_rhoY);
+    stefan_maxwell<M, W, sizeof(S) == 4>(L, node, ls, T, rho, common, omega1, Y, Qb, rho * inv_rhoY);
 
     // reaction increment (eq. R3, forward Euler), with the LDS columns the
     // diffusion step has finished with; the arithmetic-bound chemistry then
@@ -599,7 +614,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         // need not stay in registers through the sub-steps
         reload_barrier();
 #pragma unroll
-        for (int a = 0; a < M; ++a) prm[(PRM_SP + 6 * a + 5) * N + node] = fin[a] - s_ra[a][threadIdx.x];
+        for (int a = 0; a < M; ++a)
+            st_corr<sizeof(S) == 4>(as_global(prm), PRM_SP + 6 * a + 5, N, node, fin[a] - s_ra[a][threadIdx.x]);
     }
 }
 
@@ -644,8 +660,13 @@ __device__ __forceinline__ void node_gradients(const LatDev& L, int node) {
             if (cz) { acc[2] += (cz * w) * aux[(AUX_PHI + 2) * N + nb]; acc[5] += (cz * w) * hy; }
         }
     }
+    if (L.storage == RLBM_STORAGE_F32_DEV) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) prm[(size_t)(prm_grad(M) + q) * N + node] = acc[q];
+        for (int q = 0; q < 6; ++q) st_corr<true>(as_global(prm), prm_grad(M) + q, N, node, acc[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) st_corr<false>(as_global(prm), prm_grad(M) + q, N, node, acc[q]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -693,9 +714,15 @@ __device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const
         // Delta rho_a against the densities read again, so that they need not
         // stay in registers through the sub-steps
         reload_barrier();
+        if (L.storage == RLBM_STORAGE_F32_DEV) {
 #pragma unroll
-        for (int a = 0; a < M; ++a)
-            prm[(PRM_SP + 6 * a + 5) * N + node] = fin[a] - prm[(PRM_SP + 6 * a) * N + node];
+            for (int a = 0; a < M; ++a)
+                st_corr<true>(as_global(prm), PRM_SP + 6 * a + 5, N, node, fin[a] - prm[(PRM_SP + 6 * a) * N + node]);
+        } else {
+#pragma unroll
+            for (int a = 0; a < M; ++a)
+                st_corr<false>(as_global(prm), PRM_SP + 6 * a + 5, N, node, fin[a] - prm[(PRM_SP + 6 * a) * N + node]);
+        }
     } else {
         (void)flag;
     }
@@ -814,40 +841,58 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
         constexpr int RPW = (NLD + UPD_WAVES - 1) / UPD_WAVES;
         constexpr int LPW = (NS + UPD_WAVES - 1) / UPD_WAVES;
         const int nd = node0 + lane < N ? node0 + lane : 0;   // beyond the end: a placeholder node
-        double v[RPW];
-        float w[LPW];
+        // one copy per wave, so that each load's row, and with it its width
+        // (the correction rows are FP32 in FP32 storage), is a compile-time
+        // constant: no branches between the loads
+        auto stage = [&](auto wave_c) {
+            constexpr int WV = decltype(wave_c)::value;
+            double v[RPW];
+            float vf[RPW];
+            float w[LPW];
 #pragma unroll
-        for (int q = 0; q < RPW; ++q) {
-            const int idx = wave + UPD_WAVES * q;
-            const int row = upd_loaded_row(M, idx < NLD ? idx : 0);
-            int srow = row;
-            if (row >= PRM_SP && row < prm_grad(M)) {
-                const int slot = (row - PRM_SP) / 6, c = (row - PRM_SP) % 6;
-                const int a = W ? slot : (slot < M - 1 ? slot + (slot >= s ? 1 : 0) : s);
-                srow = PRM_SP + 6 * a + c;
+            for (int q = 0; q < RPW; ++q) {
+                const int idx = WV + UPD_WAVES * q;
+                const int row = upd_loaded_row(M, idx < NLD ? idx : 0);
+                int srow = row;
+                if (row >= PRM_SP && row < prm_grad(M)) {
+                    const int slot = (row - PRM_SP) / 6, c = (row - PRM_SP) % 6;
+                    const int a = W ? slot : (slot < M - 1 ? slot + (slot >= s ? 1 : 0) : s);
+                    srow = PRM_SP + 6 * a + c;
+                }
+                // unconditional: no waits between
+                if (sizeof(S) == 4 && prm_is_corr(M, row))
+                    vf[q] = ld_at(reinterpret_cast<const RLBM_GLOBAL float*>(prm + (size_t)srow * L.N), nd);
+                else
+                    v[q] = ld_at(prm + (size_t)srow * L.N, nd);
             }
-            v[q] = ld_at(prm + (size_t)srow * L.N, nd);   // unconditional: no waits between
-        }
-        if constexpr (sizeof(S) == 4) {
-            const RLBM_GLOBAL float* sc = scale_at(L, par, nd);
+            if constexpr (sizeof(S) == 4) {
+                const RLBM_GLOBAL float* sc = scale_at(L, par, nd);
 #pragma unroll
-            for (int q = 0; q < LPW; ++q) {
-                const int l = wave + UPD_WAVES * q;
-                w[q] = sc[l < NS ? l : 0];
+                for (int q = 0; q < LPW; ++q) {
+                    const int l = WV + UPD_WAVES * q;
+                    w[q] = sc[l < NS ? l : 0];
+                }
             }
-        }
 #pragma unroll
-        for (int q = 0; q < RPW; ++q) {
-            const int idx = wave + UPD_WAVES * q;
-            if (idx < NLD) sp[upd_loaded_row(M, idx)][lane] = v[q];
-        }
-        if constexpr (sizeof(S) == 4) {
-#pragma unroll
-            for (int q = 0; q < LPW; ++q) {
-                const int l = wave + UPD_WAVES * q;
-                if (l < NS) ssc[l][lane] = w[q];
+            for (int q = 0; q < RPW; ++q) {
+                const int idx = WV + UPD_WAVES * q;
+                if (idx < NLD) {
+                    const int row = upd_loaded_row(M, idx);
+                    sp[row][lane] = (sizeof(S) == 4 && prm_is_corr(M, row)) ? (double)vf[q] : v[q];
+                }
             }
-        }
+            if constexpr (sizeof(S) == 4) {
+#pragma unroll
+                for (int q = 0; q < LPW; ++q) {
+                    const int l = WV + UPD_WAVES * q;
+                    if (l < NS) ssc[l][lane] = w[q];
+                }
+            }
+        };
+        static_assert(UPD_WAVES == 3, "one staging copy per wave");
+        if (wave == 0) stage(std::integral_constant<int, 0>{});
+        else if (wave == 1) stage(std::integral_constant<int, 1>{});
+        else stage(std::integral_constant<int, 2>{});
     }
 
     int x = 0, y = 0, z = 0;

@@ -96,6 +96,17 @@ constexpr int PRM_RHO = 0, PRM_U = 1, PRM_T = 4, PRM_UINT = 5, PRM_TH = 6, PRM_O
 // species rows: PRM_SP + 6 a + {0: rho_a, 1..3: V_a, 4: beta_a, 5: drho_a}
 __host__ __device__ constexpr int prm_grad(int M) { return PRM_SP + 6 * M; }   // d (3), sum H grad Y (3)
 __host__ __device__ constexpr int prm_rows(int M) { return PRM_SP + 6 * M + 6; }
+// Correction rows: the energy flux base, the diffusion velocities V_a, the
+// reaction increments drho_a and the gradients.  They enter the collision as
+// small additive terms, so in FP32 deviation storage they are kept as FP32
+// (the first half of the row's bytes, node n at ((float*)&prm[r * N])[n]);
+// the conserved moments and state (rho, u, T, U, rho_a) stay FP64 in both
+// storages.
+__host__ __device__ constexpr bool prm_is_corr(int M, int r) {
+    return (r >= PRM_QB && r < PRM_QB + 3) ||
+           (r >= PRM_SP && r < prm_grad(M) && (r - PRM_SP) % 6 != 0 && (r - PRM_SP) % 6 != 4) ||
+           (r >= prm_grad(M) && r < prm_rows(M));
+}
 
 
 // Compiler barrier: memory may have changed, so mechanism constants used after

@@ -21,5 +21,10 @@ Modules
     equilibria species, momentum and energy equilibria (sections 2.2, 3.2, 3.3)
     boundary   TMS wall, flux inlet and LODI outlet (section 4)
     solver     the time step and read-out
+
+Parity unpinned: the corner rule (a node on several non-periodic faces takes
+the union of their incoming links, walls first) has no independent check;
+the synthetic thermo, transport and mechanism laws are inputs, not method.
+Every other part is pinned in tests/test_oracle_pins.py.
 """
 from .solver import Oracle  # noqa: F401

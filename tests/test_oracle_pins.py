@@ -5,6 +5,7 @@ invariant, a special case with a textbook solution, or an independent route
 (numerical quadrature, symbolic algebra, root finding) to the same number.
 """
 import copy
+import functools
 import math
 import zlib
 
@@ -772,6 +773,190 @@ def test_lodi_outlet_relaxes_pressure_towards_p_inf():
     o.step(400)
     dev = float(np.mean(o.fields()["P"])) / P_inf - 1.0
     assert dev0 > 0.009 and 0.0 < dev < 0.9 * dev0, (dev0, dev)
+
+
+def _inlet_case(mech9):
+    """A small walled channel whose bulk differs from the inlet stream in
+    density and composition (fuel-rich and 20% hotter), so that the local
+    state of the inlet nodes is not the inlet state."""
+    case = wl.make_case("channel2d", nx=20, ny=6, mech=mech9)
+    ini = case["init"]
+    Y = np.asarray(ini["Y"]).copy()
+    Y[wl.FUEL9] *= 1.5
+    Y[wl.INERT9] = 0.0
+    Y[wl.INERT9] = 1.0 - Y.sum(axis=0)
+    T = 1.2 * np.asarray(ini["T"])
+    ini["Y"], ini["T"] = Y, T
+    ini["rho"] = wl._rho_from_state(mech9, mech9["P0"], T, Y)
+    return case
+
+
+def _pull(pops, nx, ny, nz):
+    """Pull advection f_i(x) <- f_i(x - c_i) with periodic wrap, written here
+    independently of the oracle (np.roll per velocity)."""
+    out = np.empty_like(pops)
+    for i in range(Q):
+        a = pops[..., i, :].reshape(pops.shape[:-2] + (nz, ny, nx))
+        out[..., i, :] = np.roll(a, shift=(C[i, 2], C[i, 1], C[i, 0]), axis=(-3, -2, -1)
+                                 ).reshape(pops.shape[:-2] + (nx * ny * nz,))
+    return out
+
+
+def test_flux_inlet_keeps_the_local_density_and_composition(mech9):
+    """After the flux inlet (section 4.3, eqs. in_tgt_f .. fa_inlet) the
+    inlet node carries the local density and composition of the mixed set
+    (eqs. inletlocRho, inletlocY) with the imposed u^in and T^in.  The local
+    density and composition are recomputed here in closed form: the mixed
+    set's zeroth moments are the advected populations on the outgoing links
+    plus, on the incoming links D = {c_x = +1}, the inlet equilibrium's
+    partial sum rho_in Y_a (theta_a + u_in^2 + u_in) / 2 (the product form
+    summed over c_y and c_z is 1).  A target built at the inlet's own rho^in,
+    Y^in would miss both, by far more than the tolerance."""
+    case = _inlet_case(mech9)
+    nx, ny, nz = case["nx"], case["ny"], case["nz"]
+    o = Oracle(case)
+    o.step(2)
+    pre = o.populations()
+    o.step(1)
+    k = o.inlet_nodes
+    assert np.array_equal(np.sort(o.y[k]), np.arange(1, ny - 1)) and (o.x[k] == 0).all()
+    adv = _pull(pre, nx, ny, nz)[:, :, k]
+    fi = o.inlet_face
+    m = np.asarray(mech9["molar_mass"], dtype=np.float64)
+    Ra = mech9["R_univ"] / m
+    Yin = np.asarray(fi["Y"], dtype=np.float64)
+    uin, Tin, rin = fi["u"], fi["T"], fi["rho"]
+    out_links = C[:, 0] != 1
+    theta_in = mech9["R_univ"] * (Yin / m).sum() * Tin
+    ns = len(o.stored)
+    rho_loc = adv[ns][out_links].sum(axis=0) + rin * 0.5 * (theta_in + uin ** 2 + uin)
+    rho_a = np.zeros((o.M, k.size))
+    for j, a in enumerate(o.stored):
+        rho_a[a] = adv[j][out_links].sum(axis=0) + rin * Yin[a] * 0.5 * (Ra[a] * Tin + uin ** 2 + uin)
+    rho_a[o.s] = rho_loc - rho_a.sum(axis=0)
+    Y_loc = rho_a / rho_loc
+    mo = o.last
+    np.testing.assert_allclose(mo["rho"][k], rho_loc, rtol=1e-13)
+    np.testing.assert_allclose(mo["Y"][:, k], Y_loc, rtol=1e-11, atol=1e-15)
+    np.testing.assert_allclose(mo["u"][0, k], uin, rtol=1e-10)
+    assert np.abs(mo["u"][1:, k]).max() < 1e-15
+    np.testing.assert_allclose(mo["T"][k], Tin, rtol=1e-12)
+    # the local state is not the inlet state: a target at (rho^in, Y^in)
+    # would fail the checks above
+    assert np.abs(rho_loc / rin - 1.0).min() > 1e-4
+    assert np.abs(Y_loc[wl.FUEL9] / Yin[wl.FUEL9] - 1.0).min() > 1e-4
+
+
+@functools.lru_cache(maxsize=1)
+def _outlet_pulse(nx=120, amp=1e-3, T0=1200.0, width=4.0):
+    """A Gaussian density pulse at rest at 0.6 nx in a non-reacting binary
+    mixture, bounce-back wall on x-, LODI outlet on x+; steps until the
+    right-going half has left.  Returns the pressure histories of the first
+    interior node and of the outlet node, the outlet state's density and
+    pressure histories, gamma and the sound speed."""
+    case = wl.make_case("binary", nx=nx, amp=0.0)
+    mech = case["mech"]
+    x = np.arange(nx, dtype=float)
+    T = np.full(nx, T0)
+    Y = np.repeat(np.asarray(case["init"]["Y"]).reshape(2, nx)[:, :1], nx, axis=1)
+    rho0 = float(wl._rho_from_state(mech, mech["P0"], T, Y)[0])
+    rho = rho0 * (1.0 + amp * np.exp(-((x - 0.6 * nx) / width) ** 2))
+    R = mech["R_univ"] * (Y[:, 0] / np.asarray(mech["molar_mass"])).sum()
+    P0 = rho0 * R * T0
+    case["init"] = {"rho": rho, "u": np.zeros((3, nx)), "T": T, "Y": Y}
+    case["faces"] = [{"type": "bounceback"}, {"type": "outlet", "P_inf": P0, "sigma": 0.25},
+                     {"type": "periodic"}, {"type": "periodic"}, {"type": "periodic"}, {"type": "periodic"}]
+    o = Oracle(case)
+    # gamma of this mixture at T0 from its heat capacities (quadrature-pinned thermo)
+    cv = float((Y[:, 0] * cv_species(mech, np.array([T0]))[:, 0]).sum())
+    gamma = (cv + R) / cv
+    c = math.sqrt(gamma * R * T0)
+    p_in, p_out, r_st, p_st = [], [], [], []
+    for _ in range(int(0.6 * nx / c)):
+        o.step(1)
+        p_in.append(float(o.last["P"][nx - 2]) - P0)
+        p_out.append(float(o.last["P"][nx - 1]) - P0)
+        st = o.out_state
+        r_st.append(float(st["rho"][0]))
+        p_st.append(float(st["rho"][0] * R * st["T"][0]))
+    return np.array(p_in), np.array(p_out), np.array(r_st), np.array(p_st), gamma, c
+
+
+def test_lodi_outlet_carries_the_pulse_at_the_sound_speed():
+    """The outgoing acoustic wave crosses the last link, from the first
+    interior node to the outlet node, in one link-crossing time 1/(u + c)
+    (u = 0 here): the outlet node's pressure pulse arrives that much later
+    than the interior node's (centroids of the pulses above a tenth of
+    their peaks).  The characteristic update of section 4.4 moves the
+    outgoing wave amplitude L5 with the speed u + c; a wave speed doubled
+    in L5 halves the delay, which this pin catches."""
+    p_in, p_out, _, _, _, c = _outlet_pulse()
+    t = np.arange(p_in.size, dtype=float)
+
+    def centroid(p):
+        m = p > 0.1 * p.max()
+        return (t[m] * p[m]).sum() / p[m].sum()
+
+    delay = centroid(p_out) - centroid(p_in)
+    assert 0.8 < delay * c < 1.25, (delay, 1.0 / c)
+    assert 0.9 < p_out.max() / p_in.max() < 1.05
+
+
+def test_lodi_outlet_state_stays_isentropic_for_an_acoustic_pulse():
+    """An acoustic pulse is isentropic: as it leaves, the outlet state's
+    pressure and density change together, dP = c^2 drho with c^2 = gamma
+    P / rho.  In the LODI update the density's change carries the outgoing
+    wave L5 as the pressure's does (section 4.4); dropping L5 from the
+    density breaks the relation at first order in the amplitude."""
+    _, _, r_st, p_st, gamma, _ = _outlet_pulse()
+    dP = np.diff(p_st)
+    drho = np.diff(r_st)
+    c2 = gamma * p_st[:-1] / r_st[:-1]
+    assert p_st.max() - p_st[0] > 2e-4 * p_st[0]       # the pulse (amplitude ~5e-4) has passed
+    assert np.abs(dP - c2 * drho).max() < 1e-2 * np.abs(dP).max()
+
+
+def test_lodi_outlet_lets_an_advected_hot_spot_and_composition_leave():
+    """A hot spot at uniform pressure, with a composition spot on it, carried
+    by a uniform flow u0 (fed by a flux inlet) leaves through the outlet: the
+    outlet node's density (the entropy wave, L2 of section 4.4) and mass
+    fractions (eq. convectiveBC) follow the first interior node's with the
+    link-crossing delay 1/u0 and without growing.  A reversed L2 makes the
+    outlet unstable; a composition that is not convected never changes."""
+    nx, u0, T0, width, amp = 40, 0.06, 1200.0, 2.5, 0.01
+    case = wl.make_case("binary", nx=nx, amp=0.0)
+    mech = case["mech"]
+    x = np.arange(nx, dtype=float)
+    Yb = np.asarray(case["init"]["Y"]).reshape(2, nx)[:, 0]
+    bump = np.exp(-((x - (nx - 12)) / width) ** 2)
+    T = T0 * (1.0 + amp * bump)
+    Y = np.stack([Yb[0] * (1.0 + 2.0 * amp * bump), np.zeros(nx)])
+    Y[1] = 1.0 - Y[0]
+    P0 = mech["P0"]
+    u = np.zeros((3, nx))
+    u[0] = u0
+    rin = float(wl._rho_from_state(mech, P0, np.array([T0]), Yb[:, None])[0])
+    case["init"] = {"rho": wl._rho_from_state(mech, P0, T, Y), "u": u, "T": T, "Y": Y}
+    case["faces"] = [{"type": "inlet", "rho": rin, "u": u0, "T": T0, "Y": list(Yb)},
+                     {"type": "outlet", "P_inf": P0, "sigma": 0.25}] + [{"type": "periodic"}] * 4
+    o = Oracle(case)
+    hist = []
+    for _ in range(int((12 + 4 * width) / u0)):
+        o.step(1)
+        hist.append((o.last["rho"][nx - 2], o.last["rho"][nx - 1], o.last["Y"][0, nx - 2], o.last["Y"][0, nx - 1]))
+    h = np.asarray(hist, dtype=float)
+    t = np.arange(h.shape[0], dtype=float)
+
+    def centroid(p):
+        p = np.abs(p - p[0])
+        m = p > 0.1 * p.max()
+        return (t[m] * p[m]).sum() / p[m].sum()
+
+    for a, b in ((0, 1), (2, 3)):
+        delay = centroid(h[:, b]) - centroid(h[:, a])
+        assert 0.8 < delay * u0 < 1.25, (a, delay, 1.0 / u0)
+        ratio = np.abs(h[:, b] - h[0, b]).max() / np.abs(h[:, a] - h[0, a]).max()
+        assert 0.9 < ratio < 1.05, (a, ratio)
 
 
 def test_boundary_post_conditions(mech9):

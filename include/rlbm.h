@@ -73,7 +73,8 @@ extern "C" {
  * The library copies everything; the caller may free the descriptor after
  * rlbm_mech_create returns. */
 typedef struct rlbm_mech_desc {
-    int32_t M;                    /* species, 2..RLBM_MAX_SPECIES */
+    int32_t M;                    /* species: kernels are compiled for M = 2, 3, 4 and 9
+                                     (RLBM_EUNSUP for other M up to RLBM_MAX_SPECIES) */
     int32_t R;                    /* reactions, 0..RLBM_MAX_REACTIONS */
     int32_t E;                    /* elements, 0..RLBM_MAX_ELEMENTS */
     const double* molar_mass;     /* [M] > 0 */
@@ -225,6 +226,17 @@ int rlbm_load_state(rlbm_lattice* lat, const void* buf, int on_device);
  * n_out >= 6 + E.  Synchronises the stream. */
 int rlbm_invariants(rlbm_lattice* lat, double* out, int n_out);
 
+/* Failure detection (the per-lattice flag).  Every kernel that solves the
+ * temperature equation (section 3.1, eq. temperature: moments, boundary
+ * constructions, reaction sub-steps, read-out) sets bit 0 of its lattice's
+ * flag when the bounded Newton iteration does not converge, which is how a
+ * non-physical or non-finite state shows itself; the kernels still finish.
+ * Lattices of a batch each keep their own flag.  rlbm_lattice_status
+ * synchronises the lattice stream, returns the bits set since the last
+ * call in *status (0: healthy) and clears them.  rlbm_read_fields also
+ * reports a set flag, as RLBM_ENONFINITE, and clears it. */
+int rlbm_lattice_status(rlbm_lattice* lat, int32_t* status);
+
 /* Number of stored lattices L, nodes N and interface nodes, and the slaved
  * species (RLBM_SLAVED_NONE in the weakly coupled storage). */
 int rlbm_lattice_shape(const rlbm_lattice* lat, int32_t* L, int64_t* N, int64_t* n_interface,
@@ -240,22 +252,40 @@ int rlbm_lattice_shape(const rlbm_lattice* lat, int32_t* L, int64_t* N, int64_t*
 int rlbm_set_timing(rlbm_lattice* lat, int enable);
 int rlbm_kernel_times(rlbm_lattice* lat, double* ms, int64_t* counts, int n);
 
-/* Batches of independent lattices advanced together.  Each kernel phase of a
- * step is one launch over the flattened (lattice, node-block) work list, so
- * small and uneven instances share the GPU.  All lattices of a batch must be
- * on the same device, use the same species count, storage format and
- * coupling (a slaved species, or RLBM_SLAVED_NONE for all), and are advanced
- * on the stream of the first one (RLBM_EINVAL otherwise).  They may differ in
- * everything else, the reaction scheme included.  A batch step is equivalent, bit
- * for bit, to rlbm_step on each lattice.  The batch keeps its tables in the
- * caller-owned device memory dev_mem of rlbm_batch_bytes(k) bytes. */
+/* Batches of independent lattices advanced together (the batched uneven
+ * instances of one GPU).  Each kernel phase of a step is one launch over the
+ * flattened (lattice, node-block) work list of all lattices of the batch, so
+ * small and uneven instances share the GPU; a lattice with fewer steps in a
+ * call returns from its blocks once they are done.  All lattices of a batch
+ * must be on the same device, use the same species count, storage format and
+ * coupling (a slaved species, or RLBM_SLAVED_NONE for all), and appear once
+ * (RLBM_EINVAL otherwise).  They may differ in everything else, the reaction
+ * scheme included.  A batch step is equivalent, bit for bit, to rlbm_step on
+ * each lattice.
+ *   rlbm_batch_bytes: device bytes of the batch's tables for k lattices.
+ *   rlbm_batch_create: the batch keeps its tables in the caller-owned device
+ *     memory dev_mem (rlbm_batch_bytes(k) bytes, 256-byte aligned), which must
+ *     stay valid until rlbm_batch_destroy; the lattices must stay valid while
+ *     the batch is stepped or queried.  It also
+ *     holds a little pinned host memory, events and a private stream.
+ *     Synchronous. */
 typedef struct rlbm_batch rlbm_batch;
 int rlbm_batch_bytes(int32_t k, size_t* bytes);
 int rlbm_batch_create(rlbm_lattice* const* lats, int32_t k, void* dev_mem, size_t bytes,
                       rlbm_batch** out);
-/* Advance lattice j by steps[j] >= 0 steps (all lattices share the launches;
- * a lattice drops out once its steps are done).  Asynchronous. */
+/* Advance lattice j by steps[j] >= 0 steps.  Asynchronous: the work is
+ * enqueued on the first lattice's stream, after the work already queued on
+ * the other lattices' streams, and those streams wait for it, so later calls
+ * on any lattice of the batch see its result.  Whole chunks of 16 steps are
+ * enqueued as replays of one captured HIP graph (kernel nodes only), the
+ * rest as direct launches.  Returns at once unless the host staging of the
+ * call before last is still in flight. */
 int rlbm_batch_step(rlbm_batch* batch, const int64_t* steps);
+/* Failure flags of every lattice, status[k] (see rlbm_lattice_status), read
+ * and cleared by one gather on the batch stream; synchronises that stream. */
+int rlbm_batch_status(rlbm_batch* batch, int32_t* status);
+/* Waits for the batch's enqueued work, then frees the batch (not the
+ * lattices, which may already have been destroyed). */
 void rlbm_batch_destroy(rlbm_batch* batch);
 
 const char* rlbm_last_error(void);

@@ -135,6 +135,11 @@ __device__ __forceinline__ double ld_corr(const RLBM_GLOBAL double* prm, int row
 // ---------------------------------------------------------------------------
 // work-list helpers
 // ---------------------------------------------------------------------------
+// Step counter of a launch: a device counter (batched steps replayed from a
+// captured graph advance it with k_advance_time) plus the launch's offset.
+__device__ __forceinline__ long long step_time(const long long* tp, long long toff) {
+    return (tp ? *tp : 0) + toff;
+}
 __device__ __forceinline__ int find_lattice(const int* blk, int n_lat, int b) {
     int lo = 0, hi = n_lat - 1;
     while (lo < hi) {
@@ -483,7 +488,8 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
 
 template <int M, typename S, int W>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_local(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                               int n_lat, long long t, int* __restrict__ flag) {
+                                               int n_lat, const long long* __restrict__ tp, long long toff) {
+    const long long t = step_time(tp, toff);
     const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
@@ -531,7 +537,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     int fail = 0;
     // temperature (eq. temperature), Newton from the previous step's value
     const double T = solve_T<M>(mc, Y, U, aux[AUX_T * N + node], &fail);
-    if (fail) atomicOr(flag, 1);
+    if (fail) atomicOr(L.flag, 1);
     const double Rmix = mc.R_univ * mix_inv_m<M>(mc, Y);
     const double th = Rmix * T;
     const double P = rho * th;
@@ -609,7 +615,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
         int fail_r = 0;
         reaction_increment<M, LOC_T, false>(mc, ra, rY, U, T, L.substeps, cl, fin, &fail_r);
-        if (fail_r) atomicOr(flag, 1);
+        if (fail_r) atomicOr(L.flag, 1);
         // Delta rho_a against the densities read again from LDS, so that they
         // need not stay in registers through the sub-steps
         reload_barrier();
@@ -681,7 +687,8 @@ __device__ __forceinline__ void node_gradients(const LatDev& L, int node) {
 // ---------------------------------------------------------------------------
 template <int M, bool IMPL>
 __device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const int* __restrict__ blk, int n_lat,
-                                          long long t, int* __restrict__ flag) {
+                                          const long long* __restrict__ tp, long long toff) {
+    const long long t = step_time(tp, toff);
     const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
@@ -710,7 +717,7 @@ __device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const
         const double T = prm[PRM_T * N + node];
         int fail = 0;
         reaction_increment<M, 256, true>(mc, rho_a, rho, U, T, L.substeps, ls, fin, &fail);
-        if (fail) atomicOr(flag, 1);
+        if (fail) atomicOr(L.flag, 1);
         // Delta rho_a against the densities read again, so that they need not
         // stay in registers through the sub-steps
         reload_barrier();
@@ -723,23 +730,21 @@ __device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const
             for (int a = 0; a < M; ++a)
                 st_corr<false>(as_global(prm), PRM_SP + 6 * a + 5, N, node, fin[a] - prm[(PRM_SP + 6 * a) * N + node]);
         }
-    } else {
-        (void)flag;
     }
     node_gradients<M>(L, node);
 }
 
 template <int M>
 __global__ __launch_bounds__(256) void k_gradients(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                                   int n_lat, long long t, int* __restrict__ flag) {
-    chem_body<M, false>(lats, blk, n_lat, t, flag);
+                                                   int n_lat, const long long* __restrict__ tp, long long toff) {
+    chem_body<M, false>(lats, blk, n_lat, tp, toff);
 }
 
 // The linearly implicit variant holds an (M-1)^2 matrix in registers.
 template <int M>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_chem_implicit(
-    const LatDev* __restrict__ lats, const int* __restrict__ blk, int n_lat, long long t, int* __restrict__ flag) {
-    chem_body<M, true>(lats, blk, n_lat, t, flag);
+    const LatDev* __restrict__ lats, const int* __restrict__ blk, int n_lat, const long long* __restrict__ tp, long long toff) {
+    chem_body<M, true>(lats, blk, n_lat, tp, toff);
 }
 
 
@@ -806,7 +811,8 @@ __device__ __forceinline__ void geq_wk(int c, double u, double th, double& W, do
 
 template <int M, typename S, int W>
 __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                                        int n_lat, long long t, int* __restrict__ flag) {
+                                                        int n_lat, const long long* __restrict__ tp, long long toff) {
+    const long long t = step_time(tp, toff);
     constexpr int NR = prm_rows(M);
     constexpr int NSP = Lat<M, W>::NSP, LF = Lat<M, W>::LF, LG = Lat<M, W>::LG;
     constexpr int NL = Lat<M, W>::NL;   // stored lattices
@@ -1336,7 +1342,8 @@ constexpr int BC_THREADS = 32 * BC_NODES;
 
 template <int M, typename S, int W>
 __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_boundary(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                                         int n_lat, long long t, int* __restrict__ flag) {
+                                                         int n_lat, const long long* __restrict__ tp, long long toff) {
+    const long long t = step_time(tp, toff);
     const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
@@ -1573,7 +1580,7 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
         put(LF, in ? 2.0 * fA - fL : fA + pf - fL);
         put(LG, in ? 2.0 * gA - gL : gA + pg - gL);
     }
-    if (fail && v == 0) atomicOr(flag, 1);
+    if (fail && v == 0) atomicOr(L.flag, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1730,8 +1737,7 @@ __global__ __launch_bounds__(512) void k_refs(const LatDev* __restrict__ lat, do
 
 template <int M, typename S, int W>
 __global__ __launch_bounds__(256) void k_fields(const LatDev* __restrict__ lat, long long t, double* rho_o,
-                                                double* u_o, double* T_o, double* Y_o, double* P_o,
-                                                int* __restrict__ flag) {
+                                                double* u_o, double* T_o, double* Y_o, double* P_o) {
     const LatDev& L = *lat;
     const long long node = (long long)blockIdx.x * 256 + threadIdx.x;
     if (node >= L.N) return;
@@ -1773,7 +1779,7 @@ __global__ __launch_bounds__(256) void k_fields(const LatDev* __restrict__ lat, 
     const double U = rE / rho - 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     int fail = 0;
     const double T = solve_T<M>(mc, Y, U, L.aux[AUX_T * N + node], &fail);
-    if (fail) atomicOr(flag, 1);
+    if (fail) atomicOr(L.flag, 1);
     if (rho_o) rho_o[node] = rho;
     if (u_o)
         for (int dd = 0; dd < 3; ++dd) u_o[dd * N + node] = u[dd];
@@ -1784,20 +1790,23 @@ __global__ __launch_bounds__(256) void k_fields(const LatDev* __restrict__ lat, 
     if (P_o) P_o[node] = rho * mc.R_univ * mix_inv_m<M>(mc, Y) * T;
 }
 
+// FP64 copies of the stored lattices l0 .. l0 + nl - 1 from (write = 0) or
+// into (write = 1) the current population buffer; buf holds [nl][27][N].
 template <int M, typename S, int W>
-__global__ __launch_bounds__(256) void k_pops(const LatDev* __restrict__ lat, long long t, int nl, double* buf,
-                                              int write) {
+__global__ __launch_bounds__(256) void k_pops(const LatDev* __restrict__ lat, long long t, int l0, int nl,
+                                              double* buf, int write) {
     const LatDev& L = *lat;
     const size_t total = (size_t)nl * Q * L.N;
     const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;
-    const int li = (int)(idx / L.N);
-    const long long node = (long long)(idx % L.N);
+    const size_t gidx = (size_t)l0 * Q * L.N + idx;
+    const int li = (int)(gidx / L.N);
+    const long long node = (long long)(gidx % L.N);
     const int q = (L.parity0 + t) & 1;
     void* p = L.pop[q];
     const double ref = slot_ref<M, S, W>(L, q, node, li / Q, li % Q);
-    if (write) Codec<S>::st(p, idx, buf[idx], ref);
-    else buf[idx] = Codec<S>::ld(p, idx, ref);
+    if (write) Codec<S>::st(p, gidx, buf[idx], ref);
+    else buf[idx] = Codec<S>::ld(p, gidx, ref);
 }
 
 // Per-block partial sums of the invariants; nv = 6 + E values per block.
@@ -1879,6 +1888,31 @@ __global__ void k_reduce_partials(const double* __restrict__ partial, int nblock
     out[q] = acc;
 }
 
+// Advances the device step counter of a launch series by n (the last node
+// of a captured chunk of batched steps).
+__global__ void k_advance_time(long long* __restrict__ tp, long long n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *tp += n;
+}
+
+// Reads and clears the failure flags of k lattices: out[j] = *flags[j].
+__global__ __launch_bounds__(256) void k_gather_flags(int* const* __restrict__ flags, int k, int* __restrict__ out) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < k) out[j] = atomicExch(flags[j], 0);
+}
+
+hipError_t launch_advance_time(long long* tp, long long n, hipStream_t st) {
+    (void)hipGetLastError();   // report this launch's error only
+    hipLaunchKernelGGL(k_advance_time, dim3(1), dim3(64), 0, st, tp, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_flags(int* const* flags, int k, int* out, hipStream_t st) {
+    (void)hipGetLastError();   // report this launch's error only
+    if (k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_flags, dim3((k + 255) / 256), dim3(256), 0, st, flags, k, out);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------
@@ -1903,22 +1937,23 @@ __global__ void k_reduce_partials(const double* __restrict__ partial, int nblock
 template <typename S>
 static hipError_t launch_step_phase(int phase, int M, int weak, const StepLaunch& a) {
     if (a.blocks <= 0) return hipSuccess;
+    (void)hipGetLastError();   // report this launch's error only
     if (phase == 0) {
         RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_boundary<MM, S, WW>), dim3(a.blocks), dim3(BC_THREADS), 0,
-                                                    a.stream, a.lats, a.blk, a.n_lat, a.t, a.flag))
+                                                    a.stream, a.lats, a.blk, a.n_lat, a.tp, a.toff))
     } else if (phase == 1) {
         RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_local<MM, S, WW>), dim3(a.blocks), dim3(256), 0, a.stream,
-                                                    a.lats, a.blk, a.n_lat, a.t, a.flag))
+                                                    a.lats, a.blk, a.n_lat, a.tp, a.toff))
     } else if (phase == 2) {
         if (a.schemes & (1u << RLBM_REACTION_EXPLICIT))
             RLBM_DISPATCH(M, hipLaunchKernelGGL((k_gradients<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
-                                                    a.blk, a.n_lat, a.t, a.flag))
+                                                    a.blk, a.n_lat, a.tp, a.toff))
         if (a.schemes & (1u << RLBM_REACTION_LINEARLY_IMPLICIT))
             RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem_implicit<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
-                                                    a.blk, a.n_lat, a.t, a.flag))
+                                                    a.blk, a.n_lat, a.tp, a.toff))
     } else {
         RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_update<MM, S, WW>), dim3(a.blocks), dim3(UPD_THREADS), 0,
-                                                    a.stream, a.lats, a.blk, a.n_lat, a.t, a.flag))
+                                                    a.stream, a.lats, a.blk, a.n_lat, a.tp, a.toff))
     }
     return hipGetLastError();
 }
@@ -1931,6 +1966,7 @@ hipError_t launch_phase(int phase, int M, int storage, int weak, const StepLaunc
 template <typename S>
 static hipError_t launch_init_t(int M, int weak, const LatDev* lat, long long N, const double* rho,
                                 const double* u, const double* T, const double* Y, hipStream_t st) {
+    (void)hipGetLastError();   // report this launch's error only
     const int blocks = (int)((N + 255) / 256);
     if constexpr (sizeof(S) == 4) {
         RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_scale_init<MM, WW>), dim3(blocks), dim3(256), 0, st, lat, rho,
@@ -1949,41 +1985,45 @@ hipError_t launch_init(int M, int storage, int weak, const LatDev* lat, long lon
 
 hipError_t launch_refs(int M, int weak, const LatDev* lat, double* ref, double rho, double T, const double* Y,
                        hipStream_t st) {
+    (void)hipGetLastError();   // report this launch's error only
     RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_refs<MM, WW>), dim3(1), dim3(512), 0, st, lat, ref, rho, T, Y))
     return hipGetLastError();
 }
 
 template <typename S>
 static hipError_t launch_fields_t(int M, int weak, const LatDev* lat, long long N, long long t, double* rho,
-                                  double* u, double* T, double* Y, double* P, int* flag, hipStream_t st) {
+                                  double* u, double* T, double* Y, double* P, hipStream_t st) {
+    (void)hipGetLastError();   // report this launch's error only
     const int blocks = (int)((N + 255) / 256);
     RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_fields<MM, S, WW>), dim3(blocks), dim3(256), 0, st, lat, t, rho,
-                                                u, T, Y, P, flag))
+                                                u, T, Y, P))
     return hipGetLastError();
 }
 
 hipError_t launch_fields(int M, int storage, int weak, const LatDev* lat, long long N, long long t, double* rho,
-                         double* u, double* T, double* Y, double* P, int* flag, hipStream_t st) {
-    return storage == RLBM_STORAGE_F32_DEV ? launch_fields_t<float>(M, weak, lat, N, t, rho, u, T, Y, P, flag, st)
-                                           : launch_fields_t<double>(M, weak, lat, N, t, rho, u, T, Y, P, flag, st);
+                         double* u, double* T, double* Y, double* P, hipStream_t st) {
+    return storage == RLBM_STORAGE_F32_DEV ? launch_fields_t<float>(M, weak, lat, N, t, rho, u, T, Y, P, st)
+                                           : launch_fields_t<double>(M, weak, lat, N, t, rho, u, T, Y, P, st);
 }
 
-hipError_t launch_pops(int M, int storage, int weak, const LatDev* lat, long long N, int nl, long long t,
+hipError_t launch_pops(int M, int storage, int weak, const LatDev* lat, long long N, int l0, int nl, long long t,
                        double* buf, int write, hipStream_t st) {
+    (void)hipGetLastError();   // report this launch's error only
     const size_t total = (size_t)nl * Q * (size_t)N;
     const int blocks = (int)((total + 255) / 256);
     if (storage == RLBM_STORAGE_F32_DEV)
         RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_pops<MM, float, WW>), dim3(blocks), dim3(256), 0, st, lat, t,
-                                                    nl, buf, write))
+                                                    l0, nl, buf, write))
     else
         RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_pops<MM, double, WW>), dim3(blocks), dim3(256), 0, st, lat, t,
-                                                    nl, buf, write))
+                                                    l0, nl, buf, write))
     return hipGetLastError();
 }
 
 template <typename S>
 static hipError_t launch_inv_t(int M, int weak, const LatDev* lat, long long N, long long t, double* partial,
                                int nv, double* out, hipStream_t st) {
+    (void)hipGetLastError();   // report this launch's error only
     const int blocks = (int)((N + 255) / 256);
     RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_invariants<MM, S, WW>), dim3(blocks), dim3(256), 0, st, lat, t,
                                                 partial, nv))

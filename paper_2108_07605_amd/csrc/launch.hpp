@@ -13,8 +13,8 @@ struct StepLaunch {
     const int* blk;       // device prefix of blocks per lattice [n_lat + 1]
     int n_lat;
     int blocks;           // total blocks (blk[n_lat])
-    long long t;          // step counter of this launch series
-    int* flag;            // device failure flag (temperature iteration)
+    const long long* tp;  // device step counter of the launch series, or NULL (counter 0)
+    long long toff;       // step of this launch: *tp + toff
     hipStream_t stream;
     unsigned schemes;     // bit r set if a lattice uses RLBM_REACTION r (phase 2 launches one kernel per scheme)
 };
@@ -33,11 +33,14 @@ hipError_t launch_init(int M, int storage, int weak, const LatDev* lat, long lon
 hipError_t launch_refs(int M, int weak, const LatDev* lat, double* ref, double rho, double T, const double* Y,
                        hipStream_t st);
 hipError_t launch_fields(int M, int storage, int weak, const LatDev* lat, long long N, long long t, double* rho,
-                         double* u, double* T, double* Y, double* P, int* flag, hipStream_t st);
-hipError_t launch_pops(int M, int storage, int weak, const LatDev* lat, long long N, int nl, long long t,
+                         double* u, double* T, double* Y, double* P, hipStream_t st);
+hipError_t launch_pops(int M, int storage, int weak, const LatDev* lat, long long N, int l0, int nl, long long t,
                        double* buf, int write, hipStream_t st);
 hipError_t launch_invariants(int M, int storage, int weak, const LatDev* lat, long long N, long long t,
                              double* partial, int nv, double* out, hipStream_t st);
+// batched steps: advance the device step counter; read and clear k flags
+hipError_t launch_advance_time(long long* tp, long long n, hipStream_t st);
+hipError_t launch_gather_flags(int* const* flags, int k, int* out, hipStream_t st);
 bool species_supported(int M);
 
 }  // namespace rlbm

@@ -82,6 +82,7 @@ struct LatDev {
     int parity0;                // buffer holding the current populations at t = 0
     int pad1;
     long long t_end;            // batch: lattice active while t < t_end
+    int* flag;                  // this lattice's failure flag (bit 0: a temperature iteration failed)
 };
 
 constexpr int AUX_RHO = 0, AUX_U = 1, AUX_T = 4, AUX_PHI = 5, AUX_Y = 8;

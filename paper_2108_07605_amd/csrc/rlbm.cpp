@@ -263,15 +263,6 @@ struct rlbm_lattice {
     long long counts[NPHASE] = {0, 0, 0, 0};
 };
 
-struct rlbm_batch {
-    std::vector<rlbm_lattice*> lats;
-    char* base = nullptr;
-    LatDev* d_table = nullptr;
-    int* d_blk = nullptr;     // [k + 1] node-block prefix, then [k + 1] interface-block prefix
-    std::vector<LatDev> host_table;
-    std::vector<int> host_blk;
-};
-
 extern "C" {
 
 const char* rlbm_last_error(void) { return g_last_error.c_str(); }
@@ -457,6 +448,7 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     if (fo.type == RLBM_FACE_OUTLET) { h.P_inf = fo.P_inf; h.sigma = fo.sigma; }
     h.parity0 = 0;
     h.t_end = LLONG_MAX;
+    h.flag = (int*)(base + p.off_flag);
     lat->d_lat = (LatDev*)(base + p.off_lat);
     lat->d_blk = (int*)(base + p.off_blk);
     lat->d_flag = (int*)(base + p.off_flag);
@@ -615,8 +607,8 @@ static int step_one(rlbm_lattice* lat, long long t) {
         a.blk = phase == 0 ? lat->d_blk + 2 : (phase == NPHASE - 1 ? lat->d_blk + 4 : lat->d_blk);
         a.n_lat = 1;
         a.blocks = phase == 0 ? nb_if : (phase == NPHASE - 1 ? nb64 : nb_nodes);
-        a.t = t;
-        a.flag = lat->d_flag;
+        a.tp = nullptr;
+        a.toff = t;
         a.stream = lat->stream;
         a.schemes = 1u << lat->host.reaction;
         if (a.blocks == 0) continue;
@@ -666,6 +658,12 @@ static int check_flag(rlbm_lattice* lat) {
     return RLBM_OK;
 }
 
+// The population buffer the next step writes: idle between steps, so the
+// host read and write paths stage through it instead of allocating.
+static double* idle_buffer(const rlbm_lattice* lat) {
+    return (double*)lat->host.pop[(lat->host.parity0 + lat->steps_done + 1) & 1];
+}
+
 int rlbm_read_fields(rlbm_lattice* lat, double* rho, double* u, double* T, double* Y, double* P, int on_device) {
     if (!lat) return fail(RLBM_EINVAL, "null lattice");
     if (!lat->state_set) return fail(RLBM_EINVAL, "rlbm_set_state has not been called");
@@ -674,25 +672,24 @@ int rlbm_read_fields(rlbm_lattice* lat, double* rho, double* u, double* T, doubl
     const size_t N = (size_t)lat->geo.N;
     if (on_device) {
         HIP_TRY(launch_fields(M, lat->storage, lat->host.weak, lat->d_lat, (long long)N, lat->steps_done, rho, u, T, Y, P,
-                              lat->d_flag, lat->stream),
+                              lat->stream),
                 "fields kernel");
         HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
         return check_flag(lat);
     }
-    double* tmp = nullptr;
-    const size_t nf = (6 + (size_t)M) * N;
-    HIP_TRY(hipMalloc(&tmp, nf * sizeof(double)), "hipMalloc");
-    double *dr = tmp, *du = dr + N, *dT = du + 3 * N, *dY = dT + N, *dP = dY + (size_t)M * N;
-    hipError_t e = launch_fields(M, lat->storage, lat->host.weak, lat->d_lat, (long long)N, lat->steps_done, rho ? dr : nullptr,
-                                 u ? du : nullptr, T ? dT : nullptr, Y ? dY : nullptr, P ? dP : nullptr,
-                                 lat->d_flag, lat->stream);
+    // (6 + M) N doubles staged in the idle population buffer, which holds
+    // 27 L N s >= 27 * 3 * 4 N bytes
+    double* stage = idle_buffer(lat);
+    double *dr = stage, *du = dr + N, *dT = du + 3 * N, *dY = dT + N, *dP = dY + (size_t)M * N;
+    hipError_t e = launch_fields(M, lat->storage, lat->host.weak, lat->d_lat, (long long)N, lat->steps_done,
+                                 rho ? dr : nullptr, u ? du : nullptr, T ? dT : nullptr, Y ? dY : nullptr,
+                                 P ? dP : nullptr, lat->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(lat->stream);
     if (e == hipSuccess && rho) e = hipMemcpy(rho, dr, N * sizeof(double), hipMemcpyDeviceToHost);
     if (e == hipSuccess && u) e = hipMemcpy(u, du, 3 * N * sizeof(double), hipMemcpyDeviceToHost);
     if (e == hipSuccess && T) e = hipMemcpy(T, dT, N * sizeof(double), hipMemcpyDeviceToHost);
     if (e == hipSuccess && Y) e = hipMemcpy(Y, dY, (size_t)M * N * sizeof(double), hipMemcpyDeviceToHost);
     if (e == hipSuccess && P) e = hipMemcpy(P, dP, N * sizeof(double), hipMemcpyDeviceToHost);
-    (void)hipFree(tmp);
     if (e != hipSuccess) return hip_fail(e, "read fields");
     return check_flag(lat);
 }
@@ -702,23 +699,28 @@ static int pops_io(rlbm_lattice* lat, double* buf, int on_device, int write) {
     if (!lat->state_set) return fail(RLBM_EINVAL, "rlbm_set_state has not been called");
     HIP_TRY(hipSetDevice(lat->device), "hipSetDevice");
     const size_t N = (size_t)lat->geo.N;
-    const size_t n = (size_t)lat->L * Q * N;
     if (on_device) {
-        HIP_TRY(launch_pops(lat->M, lat->storage, lat->host.weak, lat->d_lat, (long long)N, lat->L, lat->steps_done, buf, write, lat->stream),
+        HIP_TRY(launch_pops(lat->M, lat->storage, lat->host.weak, lat->d_lat, (long long)N, 0, lat->L, lat->steps_done,
+                            buf, write, lat->stream),
                 "populations kernel");
         HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
         return RLBM_OK;
     }
-    double* tmp = nullptr;
-    HIP_TRY(hipMalloc(&tmp, n * sizeof(double)), "hipMalloc");
-    hipError_t e = hipSuccess;
-    if (write) e = hipMemcpy(tmp, buf, n * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = launch_pops(lat->M, lat->storage, lat->host.weak, lat->d_lat, (long long)N, lat->L, lat->steps_done, tmp, write, lat->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(lat->stream);
-    if (e == hipSuccess && !write) e = hipMemcpy(buf, tmp, n * sizeof(double), hipMemcpyDeviceToHost);
-    (void)hipFree(tmp);
-    if (e != hipSuccess) return hip_fail(e, "populations transfer");
+    // one stored lattice at a time (27 N doubles) through the idle
+    // population buffer, which holds 27 L N s >= 27 N * 8 bytes
+    double* stage = idle_buffer(lat);
+    const size_t n = (size_t)Q * N;
+    for (int l = 0; l < lat->L; ++l) {
+        double* hb = buf + (size_t)l * n;
+        hipError_t e = hipSuccess;
+        if (write) e = hipMemcpyAsync(stage, hb, n * sizeof(double), hipMemcpyHostToDevice, lat->stream);
+        if (e == hipSuccess)
+            e = launch_pops(lat->M, lat->storage, lat->host.weak, lat->d_lat, (long long)N, l, 1, lat->steps_done, stage,
+                            write, lat->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(lat->stream);
+        if (e == hipSuccess && !write) e = hipMemcpy(hb, stage, n * sizeof(double), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "populations transfer");
+    }
     return RLBM_OK;
 }
 
@@ -859,34 +861,213 @@ int rlbm_kernel_times(rlbm_lattice* lat, double* ms, int64_t* counts, int n) {
     return RLBM_OK;
 }
 
+int rlbm_lattice_status(rlbm_lattice* lat, int32_t* status) {
+    if (!lat || !status) return fail(RLBM_EINVAL, "null argument");
+    HIP_TRY(hipSetDevice(lat->device), "hipSetDevice");
+    HIP_TRY(hipStreamSynchronize(lat->stream), "hipStreamSynchronize");
+    int flag = 0;
+    HIP_TRY(hipMemcpy(&flag, lat->d_flag, sizeof(int), hipMemcpyDeviceToHost), "read flag");
+    if (flag) {
+        const int zero = 0;
+        HIP_TRY(hipMemcpy(lat->d_flag, &zero, sizeof(int), hipMemcpyHostToDevice), "clear flag");
+    }
+    *status = flag;
+    return RLBM_OK;
+}
+
 // ---------------------------------------------------------------------------
 // batches
 // ---------------------------------------------------------------------------
+namespace {
+// Device memory of a batch: the step counter of the launch series, the
+// lattice table and the block prefixes (uploaded together at every step
+// call), then the lattices' flag pointers (uploaded once) and the gathered
+// flags.
+struct BatchPlan {
+    size_t off_t, off_table, off_blk, upload, off_flagp, off_status, total;
+};
+BatchPlan batch_plan(int k) {
+    BatchPlan p{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
+    p.off_t = take(sizeof(long long));
+    p.off_table = take((size_t)k * sizeof(LatDev));
+    p.off_blk = take(3 * (size_t)(k + 1) * sizeof(int));
+    p.upload = o;
+    p.off_flagp = take((size_t)k * sizeof(int*));
+    p.off_status = take((size_t)k * sizeof(int));
+    p.total = o;
+    return p;
+}
+// Steps per captured chunk of a batch.
+constexpr int BATCH_CHUNK = 16;
+constexpr int BATCH_RING = 2;
+}  // namespace
+
+}  // extern "C"
+
+struct rlbm_batch {
+    std::vector<rlbm_lattice*> lats;
+    BatchPlan plan{};
+    char* base = nullptr;
+    int device = 0;
+    bool stepped = false;                       // `done` has been recorded
+    hipStream_t stream = nullptr;               // the first lattice's stream
+    std::vector<hipStream_t> others;            // the other lattices' distinct streams
+    std::vector<hipEvent_t> other_ev;           // their work before a batch step
+    hipEvent_t done = nullptr;                  // the batch step's work, for the other streams
+    char* pinned[BATCH_RING] = {nullptr, nullptr};   // host staging of the per-call upload
+    hipEvent_t slot_ev[BATCH_RING] = {nullptr, nullptr};
+    bool slot_used[BATCH_RING] = {false, false};
+    int next_slot = 0;
+    int* pinned_status = nullptr;
+    int nb[3] = {0, 0, 0};                      // node, interface and 64-node blocks of all lattices
+    unsigned schemes = 0;
+    std::vector<int> host_blk;
+    bool graphs = true;
+    hipStream_t cap = nullptr;                  // private stream for graph capture
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static void batch_free(rlbm_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (auto e : b->other_ev) (void)hipEventDestroy(e);
+    if (b->done) (void)hipEventDestroy(b->done);
+    for (int r = 0; r < BATCH_RING; ++r) {
+        if (b->slot_ev[r]) (void)hipEventDestroy(b->slot_ev[r]);
+        if (b->pinned[r]) (void)hipHostFree(b->pinned[r]);
+    }
+    if (b->pinned_status) (void)hipHostFree(b->pinned_status);
+    delete b;
+}
+
+// Launches of steps t = *tp + toff0 .. *tp + toff0 + n - 1 of every lattice
+// of the batch (a lattice is active while t < its t_end).
+static hipError_t batch_launch(rlbm_batch* b, hipStream_t st, long long toff0, long long n) {
+    const int k = (int)b->lats.size();
+    rlbm_lattice* l0 = b->lats[0];
+    const long long* tp = (const long long*)(b->base + b->plan.off_t);
+    const LatDev* table = (const LatDev*)(b->base + b->plan.off_table);
+    const int* blk = (const int*)(b->base + b->plan.off_blk);
+    for (long long t = toff0; t < toff0 + n; ++t) {
+        for (int phase = 0; phase < NPHASE; ++phase) {
+            StepLaunch a;
+            a.lats = table;
+            a.blk = phase == 0 ? blk + (k + 1) : (phase == NPHASE - 1 ? blk + 2 * (k + 1) : blk);
+            a.n_lat = k;
+            a.blocks = phase == 0 ? b->nb[1] : (phase == NPHASE - 1 ? b->nb[2] : b->nb[0]);
+            a.tp = tp;
+            a.toff = t;
+            a.stream = st;
+            a.schemes = b->schemes;
+            if (a.blocks == 0) continue;
+            const hipError_t e = launch_phase(phase, l0->M, l0->storage, l0->host.weak, a);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+// Captures BATCH_CHUNK steps and the counter advance as one graph.
+static int batch_capture(rlbm_batch* b) {
+    HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+    hipError_t e = batch_launch(b, b->cap, 0, BATCH_CHUNK);
+    if (e == hipSuccess) e = launch_advance_time((long long*)(b->base + b->plan.off_t), BATCH_CHUNK, b->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(e, "batch capture");
+    }
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    b->graph = g;
+    b->exec = x;
+    return RLBM_OK;
+}
+
+extern "C" {
+
 int rlbm_batch_bytes(int32_t k, size_t* bytes) {
     if (k < 1 || !bytes) return fail(RLBM_EINVAL, "batch needs k >= 1");
-    *bytes = align256((size_t)k * sizeof(LatDev)) + align256(3 * (size_t)(k + 1) * sizeof(int));
+    *bytes = batch_plan(k).total;
     return RLBM_OK;
 }
 
 int rlbm_batch_create(rlbm_lattice* const* lats, int32_t k, void* dev_mem, size_t bytes, rlbm_batch** out) {
     if (!lats || k < 1 || !dev_mem || !out) return fail(RLBM_EINVAL, "null argument or k < 1");
     *out = nullptr;
-    size_t need = 0;
-    rlbm_batch_bytes(k, &need);
-    if (bytes < need) return fail(RLBM_ENOSPC, "device buffer smaller than rlbm_batch_bytes");
+    const BatchPlan plan = batch_plan(k);
+    if (bytes < plan.total) return fail(RLBM_ENOSPC, "device buffer smaller than rlbm_batch_bytes");
     if (((uintptr_t)dev_mem & 255) != 0) return fail(RLBM_EINVAL, "device memory must be 256-byte aligned");
     for (int j = 0; j < k; ++j) {
         if (!lats[j]) return fail(RLBM_EINVAL, "null lattice in batch");
         if (lats[j]->M != lats[0]->M || lats[j]->storage != lats[0]->storage || lats[j]->device != lats[0]->device ||
             lats[j]->host.weak != lats[0]->host.weak)
             return fail(RLBM_EINVAL, "batched lattices need the same species count, storage and device");
+        for (int i = 0; i < j; ++i)
+            if (lats[i] == lats[j]) return fail(RLBM_EINVAL, "a lattice appears twice in the batch");
     }
+    HIP_TRY(hipSetDevice(lats[0]->device), "hipSetDevice");
     rlbm_batch* b = new (std::nothrow) rlbm_batch();
     if (!b) return fail(RLBM_EINVAL, "out of host memory");
     b->lats.assign(lats, lats + k);
+    b->plan = plan;
     b->base = (char*)dev_mem;
-    b->d_table = (LatDev*)b->base;
-    b->d_blk = (int*)(b->base + align256((size_t)k * sizeof(LatDev)));
+    b->device = lats[0]->device;
+    b->stream = lats[0]->stream;
+    auto bail = [&](hipError_t e, const char* what) {
+        batch_free(b);
+        return hip_fail(e, what);
+    };
+    hipError_t e;
+    for (int j = 1; j < k; ++j) {
+        const hipStream_t sj = lats[j]->stream;
+        if (sj == b->stream || std::find(b->others.begin(), b->others.end(), sj) != b->others.end()) continue;
+        hipEvent_t ev = nullptr;
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return bail(e, "hipEventCreate");
+        b->others.push_back(sj);
+        b->other_ev.push_back(ev);
+    }
+    if ((e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)) != hipSuccess) return bail(e, "hipEventCreate");
+    for (int r = 0; r < BATCH_RING; ++r) {
+        if ((e = hipEventCreateWithFlags(&b->slot_ev[r], hipEventDisableTiming)) != hipSuccess)
+            return bail(e, "hipEventCreate");
+        if ((e = hipHostMalloc((void**)&b->pinned[r], plan.upload, hipHostMallocDefault)) != hipSuccess)
+            return bail(e, "hipHostMalloc");
+    }
+    if ((e = hipHostMalloc((void**)&b->pinned_status, (size_t)k * sizeof(int), hipHostMallocDefault)) != hipSuccess)
+        return bail(e, "hipHostMalloc");
+    if ((e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess) return bail(e, "hipStreamCreate");
+    // every lattice takes part in every launch (a lattice without steps in a
+    // call returns at once), so the grids, and with them a captured chunk,
+    // stay the same from call to call
+    b->host_blk.assign(3 * (k + 1), 0);
+    std::vector<int*> flagp(k);
+    for (int j = 0; j < k; ++j) {
+        const rlbm_lattice* lat = lats[j];
+        b->schemes |= 1u << lat->host.reaction;
+        b->host_blk[j + 1] = b->host_blk[j] + (int)((lat->geo.N + 255) / 256);
+        b->host_blk[(k + 1) + j + 1] =
+            b->host_blk[(k + 1) + j] + (int)((lat->geo.if_node.size() + BC_NODES - 1) / BC_NODES);
+        b->host_blk[2 * (k + 1) + j + 1] = b->host_blk[2 * (k + 1) + j] + (int)((lat->geo.N + 63) / 64);
+        flagp[j] = lat->d_flag;
+    }
+    b->nb[0] = b->host_blk[k];
+    b->nb[1] = b->host_blk[2 * (k + 1) - 1];
+    b->nb[2] = b->host_blk[3 * (k + 1) - 1];
+    if ((e = hipMemcpy(b->base + plan.off_flagp, flagp.data(), (size_t)k * sizeof(int*), hipMemcpyHostToDevice)) !=
+        hipSuccess)
+        return bail(e, "upload batch table");
     *out = b;
     return RLBM_OK;
 }
@@ -894,7 +1075,6 @@ int rlbm_batch_create(rlbm_lattice* const* lats, int32_t k, void* dev_mem, size_
 int rlbm_batch_step(rlbm_batch* b, const int64_t* steps) {
     if (!b || !steps) return fail(RLBM_EINVAL, "null argument");
     const int k = (int)b->lats.size();
-    rlbm_lattice* l0 = b->lats[0];
     long long tmax = 0;
     for (int j = 0; j < k; ++j) {
         if (steps[j] < 0) return fail(RLBM_EINVAL, "negative step count");
@@ -902,53 +1082,76 @@ int rlbm_batch_step(rlbm_batch* b, const int64_t* steps) {
         tmax = std::max<long long>(tmax, steps[j]);
     }
     if (tmax == 0) return RLBM_OK;
-    HIP_TRY(hipSetDevice(l0->device), "hipSetDevice");
-    b->host_table.resize(k);
-    b->host_blk.assign(3 * (k + 1), 0);
-    unsigned schemes = 0;
+    HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
+    // host staging slot: free once the copy that last read it has run
+    const int r = b->next_slot;
+    if (b->slot_used[r]) HIP_TRY(hipEventSynchronize(b->slot_ev[r]), "hipEventSynchronize");
+    char* up = b->pinned[r];
+    *(long long*)(up + b->plan.off_t) = 0;
+    LatDev* tab = (LatDev*)(up + b->plan.off_table);
     for (int j = 0; j < k; ++j) {
-        rlbm_lattice* lat = b->lats[j];
-        if (steps[j]) schemes |= 1u << lat->host.reaction;
+        const rlbm_lattice* lat = b->lats[j];
         LatDev e = lat->host;
-        e.parity0 = (int)(lat->steps_done & 1);
+        e.parity0 = (int)((lat->host.parity0 + lat->steps_done) & 1);
         e.t_end = steps[j];
-        b->host_table[j] = e;
-        const int nbn = steps[j] ? (int)((lat->geo.N + 255) / 256) : 0;
-        const int nbi = steps[j] ? (int)((lat->geo.if_node.size() + BC_NODES - 1) / BC_NODES) : 0;
-        const int nb6 = steps[j] ? (int)((lat->geo.N + 63) / 64) : 0;
-        b->host_blk[j + 1] = b->host_blk[j] + nbn;
-        b->host_blk[(k + 1) + j + 1] = b->host_blk[(k + 1) + j] + nbi;
-        b->host_blk[2 * (k + 1) + j + 1] = b->host_blk[2 * (k + 1) + j] + nb6;
+        tab[j] = e;
     }
-    HIP_TRY(hipMemcpyAsync(b->d_table, b->host_table.data(), k * sizeof(LatDev), hipMemcpyHostToDevice, l0->stream),
-            "upload batch table");
-    HIP_TRY(hipMemcpyAsync(b->d_blk, b->host_blk.data(), b->host_blk.size() * sizeof(int), hipMemcpyHostToDevice,
-                           l0->stream),
-            "upload batch table");
-    const int nb_nodes = b->host_blk[k];
-    const int nb_if = b->host_blk[2 * (k + 1) - 1];
-    const int nb64 = b->host_blk[3 * (k + 1) - 1];
-    for (long long t = 0; t < tmax; ++t) {
-        for (int phase = 0; phase < NPHASE; ++phase) {
-            StepLaunch a;
-            a.lats = b->d_table;
-            a.blk = phase == 0 ? b->d_blk + (k + 1) : (phase == NPHASE - 1 ? b->d_blk + 2 * (k + 1) : b->d_blk);
-            a.n_lat = k;
-            a.blocks = phase == 0 ? nb_if : (phase == NPHASE - 1 ? nb64 : nb_nodes);
-            a.t = t;
-            a.flag = l0->d_flag;
-            a.stream = l0->stream;
-            a.schemes = schemes;
-            if (a.blocks == 0) continue;
-            HIP_TRY(launch_phase(phase, l0->M, l0->storage, l0->host.weak, a), "batch kernel launch");
-        }
+    std::memcpy(up + b->plan.off_blk, b->host_blk.data(), b->host_blk.size() * sizeof(int));
+    // order after the work already queued on the lattices' own streams
+    for (size_t q = 0; q < b->others.size(); ++q) {
+        HIP_TRY(hipEventRecord(b->other_ev[q], b->others[q]), "hipEventRecord");
+        HIP_TRY(hipStreamWaitEvent(b->stream, b->other_ev[q], 0), "hipStreamWaitEvent");
     }
-    // keep the host table alive until the copies above have been consumed
-    HIP_TRY(hipStreamSynchronize(l0->stream), "hipStreamSynchronize");
+    HIP_TRY(hipMemcpyAsync(b->base, up, b->plan.upload, hipMemcpyHostToDevice, b->stream), "upload batch table");
+    HIP_TRY(hipEventRecord(b->slot_ev[r], b->stream), "hipEventRecord");
+    b->slot_used[r] = true;
+    b->next_slot = (r + 1) % BATCH_RING;
+    // whole chunks replay the captured graph; the rest are direct launches
+    long long full = b->graphs ? tmax / BATCH_CHUNK : 0;
+    if (full > 0 && !b->exec) {
+        const int rc = batch_capture(b);
+        if (rc) return rc;
+    }
+    for (long long c = 0; c < full; ++c) HIP_TRY(hipGraphLaunch(b->exec, b->stream), "hipGraphLaunch");
+    HIP_TRY(batch_launch(b, b->stream, 0, tmax - full * BATCH_CHUNK), "batch kernel launch");
+    HIP_TRY(hipEventRecord(b->done, b->stream), "hipEventRecord");
+    b->stepped = true;
+    for (size_t q = 0; q < b->others.size(); ++q)
+        HIP_TRY(hipStreamWaitEvent(b->others[q], b->done, 0), "hipStreamWaitEvent");
     for (int j = 0; j < k; ++j) b->lats[j]->steps_done += steps[j];
     return RLBM_OK;
 }
 
-void rlbm_batch_destroy(rlbm_batch* b) { delete b; }
+int rlbm_batch_status(rlbm_batch* b, int32_t* status) {
+    if (!b || !status) return fail(RLBM_EINVAL, "null argument");
+    const int k = (int)b->lats.size();
+    HIP_TRY(hipSetDevice(b->device), "hipSetDevice");
+    // the lattices' own streams may hold work of their own
+    for (size_t q = 0; q < b->others.size(); ++q) {
+        HIP_TRY(hipEventRecord(b->other_ev[q], b->others[q]), "hipEventRecord");
+        HIP_TRY(hipStreamWaitEvent(b->stream, b->other_ev[q], 0), "hipStreamWaitEvent");
+    }
+    int* d_status = (int*)(b->base + b->plan.off_status);
+    HIP_TRY(launch_gather_flags((int* const*)(b->base + b->plan.off_flagp), k, d_status, b->stream), "flags kernel");
+    HIP_TRY(hipMemcpyAsync(b->pinned_status, d_status, (size_t)k * sizeof(int), hipMemcpyDeviceToHost, b->stream),
+            "read flags");
+    HIP_TRY(hipStreamSynchronize(b->stream), "hipStreamSynchronize");
+    for (int j = 0; j < k; ++j) status[j] = b->pinned_status[j];
+    return RLBM_OK;
+}
+
+void rlbm_batch_destroy(rlbm_batch* b) {
+    if (!b) return;
+    // the batch's last launches read its tables and the pinned staging its
+    // copies: wait for them through the batch's own events (the lattices
+    // and their streams may already be gone)
+    if (hipSetDevice(b->device) == hipSuccess) {
+        if (b->stepped) (void)hipEventSynchronize(b->done);
+        for (int r = 0; r < BATCH_RING; ++r)
+            if (b->slot_used[r]) (void)hipEventSynchronize(b->slot_ev[r]);
+    }
+    batch_free(b);
+    (void)hipGetLastError();   // leave no error of this teardown for the next call
+}
 
 }  // extern "C"

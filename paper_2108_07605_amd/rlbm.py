@@ -34,6 +34,7 @@ EXPORTS = (
     "rlbm_lattice_shape", "rlbm_set_timing", "rlbm_kernel_times", "rlbm_batch_bytes",
     "rlbm_state_bytes", "rlbm_save_state", "rlbm_load_state",
     "rlbm_batch_create", "rlbm_batch_step", "rlbm_batch_destroy", "rlbm_last_error",
+    "rlbm_lattice_status", "rlbm_batch_status",
 )
 
 
@@ -112,6 +113,8 @@ def lib():
         "rlbm_batch_create": (c_int, [POINTER(vp), c_int32, vp, c_size_t, POINTER(vp)]),
         "rlbm_batch_step": (c_int, [vp, POINTER(c_int64)]),
         "rlbm_batch_destroy": (None, [vp]),
+        "rlbm_lattice_status": (c_int, [vp, POINTER(c_int32)]),
+        "rlbm_batch_status": (c_int, [vp, POINTER(c_int32)]),
         "rlbm_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -314,6 +317,12 @@ class Lattice:
         _check(lib().rlbm_invariants(self.handle, out, n))
         return np.array(out[:])
 
+    def status(self):
+        """Failure bits set since the last call (0: healthy); clears them."""
+        st = c_int32()
+        _check(lib().rlbm_lattice_status(self.handle, ctypes.byref(st)))
+        return st.value
+
     def set_timing(self, on=True, kernels=None):
         """HIP events around the launches of the named kernels (all when
         `kernels` is None) while `on`."""
@@ -349,6 +358,14 @@ class Batch:
         k = len(self.lattices)
         arr = (c_int64 * k)(*[int(s) for s in steps])
         _check(lib().rlbm_batch_step(self.handle, arr))
+
+    def status(self):
+        """Failure bits of every lattice since the last call (0: healthy);
+        clears them."""
+        k = len(self.lattices)
+        arr = (c_int32 * k)()
+        _check(lib().rlbm_batch_status(self.handle, arr))
+        return list(arr)
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib_handle is not None:

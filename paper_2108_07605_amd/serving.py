@@ -14,6 +14,14 @@ updates buys (at least one), so small requests finish in few rounds instead of
 advancing in lock-step with the largest ones, and an arriving request waits at
 most about one round for admission.
 
+Failures are isolated per request.  After every round the backend reports
+each resident lattice's failure flag (the library sets it when a temperature
+iteration does not converge, which is how a non-physical or non-finite state
+shows itself); a flagged request is retired at once with an error and its
+memory released, while the others continue untouched (their lattices share
+launches but no data).  A request whose lattice cannot be created, or whose
+result cannot be read back, is failed the same way.
+
 Scheduling is host logic over a small backend interface, so it is tested on
 the CPU with a simulated backend; `GpuBackend` is the one that runs the step.
 """
@@ -34,6 +42,11 @@ class Request:
     admitted: float | None = None
     done: float | None = None
     result: dict | None = None
+    error: str | None = None
+
+    @property
+    def failed(self):
+        return self.error is not None
 
     @property
     def latency(self):
@@ -59,6 +72,9 @@ class GpuBackend:
         return self.rlbm.Lattice(case, storage=self.storage, mech=self.mech).set_state()
 
     def step(self, lattices, steps):
+        """Enqueue one round (asynchronous), then gather every lattice's
+        failure flag (one small read per batch, which waits for the round);
+        returns the flags in the order of `lattices`."""
         # one batch per storage layout: lattices with a slaved species and
         # weakly coupled ones (one lattice more) cannot share launches
         groups = {}
@@ -71,6 +87,11 @@ class GpuBackend:
             self._batch_key = key
         for batch, ks in self._batches:
             batch.step([steps[k] for k in ks])
+        status = [0] * len(lattices)
+        for batch, ks in self._batches:
+            for k, st in zip(ks, batch.status()):
+                status[k] = st
+        return status
 
     def finish(self, lat):
         if self.keep == "fields":
@@ -81,6 +102,9 @@ class GpuBackend:
         return {}
 
     def release(self, lat):
+        # batches that hold the lattice go first; the next round builds new ones
+        self._batches = []
+        self._batch_key = None
         lat.close()
 
 
@@ -129,33 +153,49 @@ class Server:
                     and used + queue[head].nbytes <= self.budget:
                 r = queue[head]
                 head += 1
-                lat = self.backend.create(r.case)
+                try:
+                    lat = self.backend.create(r.case)
+                except Exception as e:          # the request fails, the server goes on
+                    r.error = f"create: {e}"
+                    r.done = self.clock() - t0
+                    continue
                 r.admitted = self.clock() - t0
                 used += r.nbytes
                 active.append([r, lat, r.steps])
             if not active:
-                self.sleep(max(0.0, queue[head].arrival - (self.clock() - t0)))
+                if head < len(queue):
+                    self.sleep(max(0.0, queue[head].arrival - (self.clock() - t0)))
                 continue
             steps = self._steps(active)
             ts = self.clock()
-            self.backend.step([a[1] for a in active], steps)
-            work = sum(a[0].nodes * s for a, s in zip(active, steps))
+            status = self.backend.step([a[1] for a in active], steps)
+            if status is None:
+                status = [0] * len(active)
+            work = sum(a[0].nodes * s for a, s, st in zip(active, steps, status) if not st)
             dt = self.clock() - ts
-            if dt > 0:
+            if dt > 0 and work > 0:
                 self.rate = 0.5 * self.rate + 0.5 * work / dt
             self.updates += work
             self.rounds += 1
             keep = []
-            for a, s in zip(active, steps):
+            for a, s, st in zip(active, steps, status):
                 a[2] -= s
-                if a[2] == 0:
-                    r, lat = a[0], a[1]
-                    r.result = self.backend.finish(lat)
-                    r.done = self.clock() - t0
-                    self.backend.release(lat)
-                    used -= r.nbytes
+                r, lat = a[0], a[1]
+                if st:
+                    # quarantine: retire the failed request alone
+                    r.error = f"failure flag {st}: a temperature iteration did not converge " \
+                              f"(non-physical or non-finite state)"
+                elif a[2] == 0:
+                    try:
+                        r.result = self.backend.finish(lat)
+                    except Exception as e:
+                        r.error = f"read-back: {e}"
                 else:
                     keep.append(a)
+                    continue
+                r.done = self.clock() - t0
+                self.backend.release(lat)
+                used -= r.nbytes
             active = keep
         return queue
 
@@ -170,9 +210,12 @@ def percentile(values, p):
 
 
 def summarize(requests, wall_s):
-    lat = [r.latency for r in requests]
-    work = sum(r.nodes * r.steps for r in requests)
-    return {"requests": len(requests), "wall_s": wall_s, "updates": work,
-            "mlups": work / wall_s / 1e6 if wall_s > 0 else None,
+    """Throughput over the completed requests' lattice updates; latency
+    percentiles over the completed requests (failed ones are counted apart)."""
+    ok = [r for r in requests if not r.failed]
+    lat = [r.latency for r in ok]
+    work = sum(r.nodes * r.steps for r in ok)
+    return {"requests": len(requests), "failed": len(requests) - len(ok), "wall_s": wall_s,
+            "updates": work, "mlups": work / wall_s / 1e6 if wall_s > 0 else None,
             "p50_s": percentile(lat, 50), "p99_s": percentile(lat, 99),
             "max_s": max(lat) if lat else None}

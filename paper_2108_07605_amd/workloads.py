@@ -322,6 +322,35 @@ def mechanism_abc(seed: int = 1, substeps: int = 2):
     return mech
 
 
+def mechanism_abcd(seed: int = 1, substeps: int = 2):
+    """Four species: the three of mechanism_abc and an inert D(28) that takes
+    part in transport and thermo only (one reaction A+B->2C)."""
+    mech = mechanism_abc(seed=seed, substeps=substeps)
+    rng = _rng(3, seed)
+    out = copy.deepcopy(mech)
+    out["name"] = "synthetic A+B->2C with inert D"
+    out["species"] = mech["species"] + ["D"]
+    out["M"] = 4
+    out["molar_mass"] = mech["molar_mass"] + [28.0]
+    out["elements"] = ["H", "O", "N"]
+    out["composition"] = [row + [0] for row in mech["composition"]] + [[0, 0, 2]]
+    out["nasa"] = mech["nasa"] + [_nasa_coeffs(rng, {"N": 2}, 0.0)]
+    out["nu_f"] = [row + [0] for row in mech["nu_f"]]
+    out["nu_r"] = [row + [0] for row in mech["nu_r"]]
+    _transport(out, T_ref=out["transport"]["T_ref"], rho_ref=1.0, P_ref=out["P0"], pair_ref=(0, 1))
+    _screen_rates(out, substeps)
+    return out
+
+
+def with_prandtl(mech, Pr: float):
+    """Copy of a mechanism with another Prandtl number (Pr = 1 makes the
+    energy lattice's two relaxation rates equal, omega_1 = omega)."""
+    out = copy.deepcopy(mech)
+    out["transport"]["Pr"] = float(Pr)
+    out["name"] = "%s, Pr %g" % (mech["name"], Pr)
+    return out
+
+
 def mechanism_h2air9(seed: int = 2, substeps: int = 2, n_reactions: int = 21,
                      dx_phys: float = 1e-3 / 64):
     """Nine species, `n_reactions` reversible element-balanced reactions drawn
@@ -466,7 +495,10 @@ def _case_abc_box(seed=0, nx=32, ny=8, nz=8, steps=200, substeps=2, perturb=True
     ph1, ph2 = rng.uniform(0, 2 * np.pi, 2)
     amp_y, amp_t = (0.05, 0.02) if perturb else (0.0, 0.0)
     YA = 0.1 * (1 + amp_y * np.sin(2 * np.pi * x / nx + ph1))
-    Y = np.stack([YA, 1 - YA, np.zeros_like(YA)])
+    if mech["M"] == 4:          # with the inert D at a uniform 30% by mass
+        Y = np.stack([0.7 * YA, 0.7 * (1 - YA), np.zeros_like(YA), np.full_like(YA, 0.3)])
+    else:
+        Y = np.stack([YA, 1 - YA, np.zeros_like(YA)])
     T = 1000.0 * (1 + amp_t * np.sin(2 * np.pi * x / nx + ph2))
     rho = _rho_from_state(mech, mech["P0"], T, Y)
     u = np.zeros((3, x.size))

@@ -366,6 +366,97 @@ def test_batch_equals_alone(mech9):
         assert np.array_equal(lat.populations(), ref)
 
 
+def test_batch_matches_oracle(mech9):
+    """Three uneven lattices in one batch (a flame tube with inlet and outlet,
+    a walled 2D channel on the linearly implicit update, a periodic reactor),
+    stepped by two batch calls with different counts per lattice (whole
+    16-step chunks replay the captured graph, the rest are direct launches):
+    each against its own oracle, FP64 storage."""
+    rlbm = _gpu()
+    cases = [wl.make_case("tube", seed=31, nx=96, mech=mech9),
+             wl.make_case("channel2d", seed=32, nx=40, ny=10, nz=1, mech=mech9, reaction="implicit"),
+             wl.make_case("reactor", seed=33, nx=4, ny=4, nz=4, mech=mech9, T0=1400.0)]
+    print("case batch tube 96 + channel2d 40x10 implicit + reactor 4^3 vs oracle, f64", flush=True)
+    m = rlbm.Mechanism(mech9)
+    lats = [rlbm.Lattice(c, storage="f64", mech=m).set_state() for c in cases]
+    oras = [Oracle(c) for c in cases]
+    b = rlbm.Batch(lats)
+    for call in ([30, 17, 20], [7, 21, 3]):
+        b.step(call)
+        for o, n in zip(oras, call):
+            o.step(n)
+        assert b.status() == [0, 0, 0]
+        for lat, o, c in zip(lats, oras, cases):
+            _compare_pops(lat.populations(), o.populations(), TOL64)
+            _compare_fields(lat.fields(), o.fields(), TOL64, _u_floor(c))
+
+
+def test_batch_graph_replays_match_direct_launches(mech9):
+    """Four calls of 16 steps each (one replay of the captured chunk per
+    call), with reads and synchronisations between them: after every call
+    the batch equals the same lattices stepped by direct launches, bit for
+    bit."""
+    rlbm = _gpu()
+    print("case batch graph replays vs direct launches, f32dev", flush=True)
+    cases = [wl.make_case("tube", seed=41, nx=70, mech=mech9),
+             wl.make_case("channel2d", seed=42, nx=24, ny=8, nz=1, mech=mech9)]
+    m = rlbm.Mechanism(mech9)
+    lats = [rlbm.Lattice(c, storage="f32dev", mech=m).set_state() for c in cases]
+    alone = [rlbm.Lattice(c, storage="f32dev", mech=m).set_state() for c in cases]
+    b = rlbm.Batch(lats)
+    for _ in range(4):
+        b.step([16, 16])
+        for a in alone:
+            a.step(16)
+        for lat, a in zip(lats, alone):
+            assert np.array_equal(lat.populations(), a.populations())
+
+
+def test_long_walled_channel_vs_oracle(mech9):
+    """A 64x16x1 channel with TMS walls, flux inlet and LODI outlet over 300
+    steps (the outlet state and the wall temperature ramp act all the
+    while), FP64 storage, every node against the oracle."""
+    rlbm = _gpu()
+    print("case channel2d 64x16 300 steps f64", flush=True)
+    case = wl.make_case("channel2d", nx=64, ny=16, nz=1, mech=mech9)
+    lat, ora, out = _run_pair(case, [100, 300])
+    for gp, op, gf, of in out:
+        _compare_pops(gp, op, TOL64)
+        _compare_fields(gf, of, TOL64, _u_floor(case))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+def test_unit_prandtl_number_parity(mech9, storage):
+    """Pr = 1 (omega_1 = omega): the energy update's singularity-free form
+    on the GPU against the oracle on a walled channel."""
+    print(f"case channel2d 48x12 Pr=1 {storage}", flush=True)
+    case = wl.make_case("channel2d", nx=48, ny=12, nz=1, mech=wl.with_prandtl(mech9, 1.0))
+    lat, ora, out = _run_pair(case, [1, 30], storage=storage)
+    for gp, op, gf, of in out:
+        if storage == "f64":
+            _compare_pops(gp, op, TOL64)
+            _compare_fields(gf, of, TOL64, _u_floor(case))
+    gf, of = out[-1][2], out[-1][3]
+    assert _nerr(gf["T"], of["T"]) <= (TOL64 if storage == "f64" else TOL32)
+    assert max(_nerr(gf["Y"][a], of["Y"][a], 1e-6) for a in range(of["Y"].shape[0])) <= TOL32
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+def test_four_species_parity(storage):
+    """The four-species kernels (three reacting species and an inert one) in
+    the perturbed periodic box against the oracle."""
+    print(f"case abc_box 32x8x8 M=4 {storage}", flush=True)
+    case = wl.make_case("abc_box", mech=wl.mechanism_abcd())
+    lat, ora, out = _run_pair(case, [1, 10, 100], storage=storage)
+    for gp, op, gf, of in out:
+        if storage == "f64":
+            _compare_pops(gp, op, TOL64)
+            _compare_fields(gf, of, TOL64, _u_floor(case))
+        else:
+            assert _nerr(gf["T"], of["T"]) <= TOL32
+            assert max(_nerr(gf["Y"][a], of["Y"][a], 1e-6) for a in range(4)) <= TOL32
+
+
 def _window(pops, case, cx, cy, cz, h=2):
     nx, ny, nz = case["nx"], case["ny"], case["nz"]
     xs = [(cx + d) % nx for d in range(-h, h + 1)]

@@ -553,8 +553,14 @@ def test_equilibrium_round_trip(mech9):
     np.testing.assert_allclose(fl["Y"], ini["Y"], rtol=1e-12, atol=1e-16)
 
 
-def test_periodic_conservation_abc_box():
-    case = wl.make_case("abc_box")
+@pytest.mark.parametrize("species", [3, 4])
+def test_periodic_conservation_abc_box(species):
+    """Periodic box, 200 steps: mass, momentum, energy and element totals are
+    conserved (section 2.1) with three species and with a fourth, inert one
+    (which enters the transport and thermo only)."""
+    mech = wl.mechanism_abc() if species == 3 else wl.mechanism_abcd()
+    case = wl.make_case("abc_box", mech=mech)
+    assert case["mech"]["M"] == species
     o = Oracle(case)
     inv0 = o.invariants()
     fl0 = o.fields()
@@ -563,7 +569,7 @@ def test_periodic_conservation_abc_box():
     fl = o.fields()
     scale = np.abs(inv0)
     # mass, energy, elements: relative; momentum: relative to sum rho * sound speed
-    for k in (0, 4, 5, 6):
+    for k in [0, 4] + list(range(5, 5 + len(case["mech"]["elements"]))):
         assert abs(inv1[k] - inv0[k]) <= 1e-13 * scale[k], k
     cs = math.sqrt(float(np.mean(fl0["P"] / fl0["rho"])))
     for k in (1, 2, 3):
@@ -1046,8 +1052,10 @@ def test_binary_diffusion_coefficient():
     assert abs(r32 - 1.0) < 0.03, (r16, r32)
 
 
-def _thermal_rate(nx, steps=600, t0=20):
+def _thermal_rate(nx, steps=600, t0=20, Pr=None):
     case = wl.make_case("binary", nx=nx, amp=0.0)
+    if Pr is not None:
+        case["mech"] = wl.with_prandtl(case["mech"], Pr)
     ini = case["init"]
     x = np.arange(nx)
     ini["T"] = 300.0 * (1 + 1e-4 * np.sin(2 * np.pi * x / nx))
@@ -1082,7 +1090,17 @@ def test_thermal_mode_conductivity():
     assert 3.0 < abs(r16 - 1.0) / abs(r32 - 1.0) < 5.0, (r16, r32)
 
 
-def test_interdiffusion_keeps_temperature_uniform():
+def test_thermal_mode_conductivity_at_unit_prandtl_number():
+    """At Pr = 1 the two relaxation rates of the energy lattice coincide
+    (omega_1 = omega), where eqs. qdiff and corrFourier each divide by
+    omega - omega_1: the evaluated update stays finite, and the entropy mode
+    decays at lambda / (rho C_p) k^2 with lambda = mu C_p."""
+    r32 = _thermal_rate(32, Pr=1.0)
+    assert abs(r32 - 1.0) < 0.01, r32
+
+
+@pytest.mark.parametrize("Pr", [0.7, 1.0])
+def test_interdiffusion_keeps_temperature_uniform(Pr):
     """A composition mode at uniform T and P: with the interdiffusion flux
     (eq. qdiff) and the Fourier correction (eq. corrFourier) in place the
     temperature stays uniform to second order in the amplitude, although the
@@ -1094,6 +1112,7 @@ def test_interdiffusion_keeps_temperature_uniform():
     nasa = case["mech"]["nasa"]
     nasa[0][5] += 1000.0          # formation-enthalpy offsets (kelvin)
     nasa[1][5] -= 1000.0 / 3.0
+    case["mech"] = wl.with_prandtl(case["mech"], Pr)
     o = Oracle(case)
     dev = 0.0
     for _ in range(10):

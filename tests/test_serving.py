@@ -153,6 +153,45 @@ def test_served_results_identical_to_alone(mech9):
         assert np.array_equal(alone.populations(), r.result["populations"]), r.rid
 
 
+class FailingBackend(SimBackend):
+    """A lattice whose case names `fail_after` reports a failure flag in the
+    first round that takes it past that many steps; a case with `bad` cannot
+    be created."""
+
+    def create(self, case):
+        if case.get("bad"):
+            raise RuntimeError("invalid request")
+        return super().create(case)
+
+    def step(self, lats, steps):
+        super().step(lats, steps)
+        return [1 if lat["case"].get("fail_after") is not None and lat["steps"] > lat["case"]["fail_after"]
+                else 0 for lat in lats]
+
+
+def test_failed_request_is_quarantined():
+    """A request whose lattice is flagged is retired at once with an error and
+    its memory released; one that cannot be created fails at admission; every
+    other request is served its full budget."""
+    clock = SimClock()
+    be = FailingBackend(clock)
+    reqs = [_req(k, 0.001 * k, 100 + 10 * k, 40, 10) for k in range(6)]
+    reqs[2].case["fail_after"] = 5
+    reqs[4].case["bad"] = True
+    srv = Server(be, budget_bytes=1e9, max_slots=8, round_s=1e-4, rate_guess=1e6, min_chunk=2,
+                 max_chunk=4, clock=clock, sleep=clock.sleep)
+    out = {r.rid: r for r in srv.run(reqs)}
+    assert out[2].failed and "failure flag" in out[2].error and out[2].result is None
+    assert out[4].failed and out[4].error.startswith("create") and out[4].admitted is None
+    for k in (0, 1, 3, 5):
+        assert not out[k].failed and out[k].result["steps"] == 40
+    # retired early, after the round that flagged it, and nothing left behind
+    assert out[2].done < min(out[k].done for k in (0, 1, 3, 5))
+    assert be.used == 0 and not be.live
+    summ = summarize(list(out.values()), 1.0)
+    assert summ["failed"] == 2 and summ["updates"] == sum(out[k].nodes * 40 for k in (0, 1, 3, 5))
+
+
 def test_equal_work_share_lets_small_requests_finish_first():
     """A small request arriving with a large one finishes after a few rounds,
     not after as many rounds as the large one needs."""
@@ -163,3 +202,115 @@ def test_equal_work_share_lets_small_requests_finish_first():
     out = {r.rid: r for r in srv.run(reqs)}
     assert out[1].done < 0.05 * out[0].done
     assert out[0].result["steps"] == 200 and out[1].result["steps"] == 200
+
+
+def _poison(lat):
+    """An impossible state: every energy population NaN.  The kernels'
+    bounded temperature iteration gives up and flags the lattice; every
+    kernel still finishes."""
+    pops = lat.populations()
+    pops[-1] = np.nan
+    lat.write_populations(pops)
+    return lat
+
+
+@pytest.mark.gpu
+def test_flagged_lattice_is_isolated_in_a_batch(mech9):
+    """One lattice of a batch holds a non-physical state: the batch reports
+    its flag and no other, and the other lattices end bit-identical to
+    stepping them alone."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2108_07605_amd import rlbm, workloads as wl
+    print("case batch with one poisoned lattice, f32dev", flush=True)
+    cases = [wl.make_case("tube", seed=11, nx=100, mech=mech9),
+             wl.make_case("channel2d", seed=12, nx=32, ny=8, nz=1, mech=mech9),
+             wl.make_case("reactor", seed=13, nx=4, ny=4, nz=4, mech=mech9, T0=1300.0)]
+    m = rlbm.Mechanism(mech9)
+    lats = [rlbm.Lattice(c, storage="f32dev", mech=m).set_state() for c in cases]
+    _poison(lats[1])
+    b = rlbm.Batch(lats)
+    b.step([20, 20, 20])
+    assert b.status() == [0, 1, 0]
+    assert b.status() == [0, 0, 0]           # read and cleared
+    for k in (0, 2):
+        alone = rlbm.Lattice(cases[k], storage="f32dev", mech=m).set_state()
+        alone.step(20)
+        assert alone.status() == 0
+        assert np.array_equal(alone.populations(), lats[k].populations()), k
+    with pytest.raises(rlbm.RlbmError):
+        lats[1].fields()                     # read-out reports the state too
+
+
+@pytest.mark.gpu
+def test_server_quarantines_a_failed_request(mech9):
+    """A served request whose state turns non-physical is retired with an
+    error while the requests served beside it finish bit-identical to
+    running alone."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2108_07605_amd import rlbm, workloads as wl
+    from paper_2108_07605_amd.serving import GpuBackend
+
+    class PoisonBackend(GpuBackend):
+        def create(self, case):
+            lat = super().create(case)
+            return _poison(lat) if case.get("poison") else lat
+
+    print("case serving mix with one poisoned request, f32dev", flush=True)
+    cases = [wl.make_case("tube", seed=21, nx=120, mech=mech9),
+             wl.make_case("channel2d", seed=22, nx=32, ny=8, nz=1, mech=mech9),
+             wl.make_case("reactor", seed=23, nx=4, ny=4, nz=4, mech=mech9, T0=1250.0),
+             wl.make_case("tube", seed=24, nx=80, mech=mech9)]
+    cases[1]["poison"] = True
+    steps = [30, 40, 25, 35]
+    reqs = [Request(k, 0.0, c, s) for k, (c, s) in enumerate(zip(cases, steps))]
+    be = PoisonBackend(mech9, storage="f32dev", keep="populations")
+    srv = Server(be, budget_bytes=1e10, max_slots=8, round_s=1e-4, rate_guess=1e8, min_chunk=4,
+                 max_chunk=9)
+    out = {r.rid: r for r in srv.run(reqs)}
+    assert out[1].failed and "failure flag" in out[1].error
+    mech = rlbm.Mechanism(mech9)
+    for k in (0, 2, 3):
+        r = out[k]
+        assert not r.failed, r.error
+        alone = rlbm.Lattice(r.case, storage="f32dev", mech=mech).set_state()
+        alone.step(r.steps)
+        assert np.array_equal(alone.populations(), r.result["populations"]), k
+
+
+@pytest.mark.gpu
+def test_served_requests_match_the_oracle(mech9):
+    """One small request of each served kind (reactor, flame tube, 2D and 3D
+    channels) through the server in FP32 deviation storage: the fields read
+    back match the FP64 oracle to 1e-5 in mass fractions and temperature."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import Oracle
+    from paper_2108_07605_amd import workloads as wl
+    from paper_2108_07605_amd.serving import GpuBackend
+    print("case served reactor/tube/channel2d/channel3d vs oracle, f32dev", flush=True)
+    cases = [wl.make_case("reactor", seed=51, nx=4, ny=4, nz=4, mech=mech9, T0=1350.0),
+             wl.make_case("tube", seed=52, nx=96, mech=mech9),
+             wl.make_case("channel2d", seed=53, nx=48, ny=12, nz=1, mech=mech9),
+             wl.make_case("channel3d", seed=54, nx=20, ny=8, nz=6, mech=mech9)]
+    steps = [40, 45, 30, 20]
+    reqs = [Request(k, 0.001 * k, c, s) for k, (c, s) in enumerate(zip(cases, steps))]
+    be = GpuBackend(mech9, storage="f32dev", keep="fields")
+    srv = Server(be, budget_bytes=1e10, max_slots=8, round_s=1e-4, rate_guess=1e8, min_chunk=5,
+                 max_chunk=12)
+    out = {r.rid: r for r in srv.run(reqs)}
+    for k, (c, n) in enumerate(zip(cases, steps)):
+        r = out[k]
+        assert not r.failed, r.error
+        o = Oracle(c)
+        o.step(n)
+        of, gf = o.fields(), r.result
+        eT = float(np.abs(gf["T"] - of["T"]).max() / np.abs(of["T"]).max())
+        eY = max(float(np.abs(gf["Y"][a] - of["Y"][a]).max() / max(np.abs(of["Y"][a]).max(), 1e-6))
+                 for a in range(of["Y"].shape[0]))
+        print(f"served {c['name']} vs oracle after {n} steps: Y {eY:.2e} T {eT:.2e}", flush=True)
+        assert eY <= 1e-5 and eT <= 1e-5, (k, eY, eT)

@@ -288,6 +288,21 @@ int rlbm_batch_status(rlbm_batch* batch, int32_t* status);
  * lattices, which may already have been destroyed). */
 void rlbm_batch_destroy(rlbm_batch* batch);
 
+/* Group step without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Advances lattice j by steps[j] >= 0 steps, with the same
+ * kernels and results as a batch of these lattices (bit for bit), but keeps
+ * the work list in a file-scope device array of the library instead of
+ * caller memory: no allocation, no batch object, no pinned staging, no graph.
+ * Limits: 1 <= k <= RLBM_GROUP_MAX_LATTICES (RLBM_EINVAL beyond); all
+ * lattices on one device and one stream (RLBM_EINVAL otherwise), with the
+ * batch's other requirements.  Asynchronous on that stream.  Every call on a
+ * GPU shares that GPU's array (about 100 KB, held until the process ends):
+ * calls that overlap on one GPU, from several threads or on several streams,
+ * race and must be ordered by the caller. */
+#define RLBM_GROUP_MAX_LATTICES 256
+int rlbm_step_group(rlbm_lattice* const* lats, int32_t k, const int64_t* steps);
+
 const char* rlbm_last_error(void);
 
 #ifdef __cplusplus

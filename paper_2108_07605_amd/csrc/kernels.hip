@@ -21,6 +21,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "launch.hpp"
@@ -1910,6 +1911,62 @@ hipError_t launch_gather_flags(int* const* flags, int k, int* out, hipStream_t s
     (void)hipGetLastError();   // report this launch's error only
     if (k <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_flags, dim3((k + 255) / 256), dim3(256), 0, st, flags, k, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free group steps: tables in a file-scope device array
+// ---------------------------------------------------------------------------
+// Each GPU holds its own copy until the process ends.  Host code never
+// names it: it uses the device address that group_scratch() returns.
+static __device__ __align__(256) unsigned char scratch[GROUP_SCRATCH_BYTES];
+
+hipError_t group_scratch(int device, char** ptr) {
+    // one address per device, looked up once with that device current
+    static std::mutex mu;
+    static char* addr[64] = {};
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = (char*)p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
+
+// Entries base .. base + n - 1 of the group table: block j copies lattice
+// j's device entry word by word, then sets its buffer parity and step
+// count; block 0 writes the block prefixes of those entries (and of the
+// entry after the last), and resets the step counter on the first chunk.
+__global__ __launch_bounds__(64) void k_group_gather(char* __restrict__ sc, GroupChunk c) {
+    const int j = blockIdx.x;
+    LatDev* table = (LatDev*)(sc + GROUP_OFF_TABLE);
+    int* blk = (int*)(sc + GROUP_OFF_BLK);
+    static_assert(sizeof(LatDev) % 8 == 0, "the entry is copied in 8-byte words");
+    const unsigned long long* src = (const unsigned long long*)c.src[j];
+    unsigned long long* dst = (unsigned long long*)&table[c.base + j];
+    for (int w = threadIdx.x; w < (int)(sizeof(LatDev) / 8); w += 64) dst[w] = src[w];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        table[c.base + j].parity0 = c.parity[j];
+        table[c.base + j].t_end = c.t_end[j];
+    }
+    if (j == 0) {
+        for (int q = threadIdx.x; q < 3 * (c.n + 1); q += 64) {
+            const int a = q / (c.n + 1), e = q % (c.n + 1);
+            blk[a * (c.k + 1) + c.base + e] = c.blk[a][e];
+        }
+        if (c.base == 0 && threadIdx.x == 0) *(long long*)sc = 0;
+    }
+}
+
+hipError_t launch_group_gather(char* sc, const GroupChunk& c, hipStream_t st) {
+    (void)hipGetLastError();   // report this launch's error only
+    if (c.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_group_gather, dim3(c.n), dim3(64), 0, st, sc, c);
     return hipGetLastError();
 }
 

@@ -43,4 +43,26 @@ hipError_t launch_advance_time(long long* tp, long long n, hipStream_t st);
 hipError_t launch_gather_flags(int* const* flags, int k, int* out, hipStream_t st);
 bool species_supported(int M);
 
+// Allocation-free group steps (rlbm_step_group): at most GROUP_MAX lattices,
+// their table in a file-scope device array of the kernel library.
+constexpr int GROUP_MAX = RLBM_GROUP_MAX_LATTICES;
+constexpr int GROUP_CHUNK = 32;   // table entries filled per gather launch (kernel arguments)
+struct GroupChunk {
+    const LatDev* src[GROUP_CHUNK];   // the lattices' device entries
+    long long t_end[GROUP_CHUNK];     // steps of this call
+    int parity[GROUP_CHUNK];          // buffer holding the current populations
+    int blk[3][GROUP_CHUNK + 1];      // node, interface and 64-node block prefixes of entries base..base+n
+    int base, n, k;
+};
+// Layout of the group scratch: the step counter, the lattice table
+// [GROUP_MAX] and the three block prefixes [GROUP_MAX + 1] each.
+constexpr size_t GROUP_OFF_TABLE = 256;
+constexpr size_t GROUP_OFF_BLK = GROUP_OFF_TABLE + (((size_t)GROUP_MAX * sizeof(LatDev) + 255) & ~(size_t)255);
+constexpr size_t GROUP_SCRATCH_BYTES =
+    GROUP_OFF_BLK + (((size_t)3 * (GROUP_MAX + 1) * sizeof(int) + 255) & ~(size_t)255);
+// Device address of the group scratch on `device` (the current device),
+// looked up once per device.
+hipError_t group_scratch(int device, char** ptr);
+hipError_t launch_group_gather(char* sc, const GroupChunk& c, hipStream_t st);
+
 }  // namespace rlbm

@@ -1140,6 +1140,73 @@ int rlbm_batch_status(rlbm_batch* b, int32_t* status) {
     return RLBM_OK;
 }
 
+int rlbm_step_group(rlbm_lattice* const* lats, int32_t k, const int64_t* steps) {
+    if (!lats || !steps) return fail(RLBM_EINVAL, "null argument");
+    if (k < 1 || k > RLBM_GROUP_MAX_LATTICES)
+        return fail(RLBM_EINVAL, "group needs 1 <= k <= RLBM_GROUP_MAX_LATTICES lattices");
+    long long tmax = 0;
+    for (int j = 0; j < k; ++j) {
+        const rlbm_lattice* lat = lats[j];
+        if (!lat) return fail(RLBM_EINVAL, "null lattice in group");
+        if (!lat->state_set) return fail(RLBM_EINVAL, "rlbm_set_state has not been called");
+        if (lat->M != lats[0]->M || lat->storage != lats[0]->storage || lat->device != lats[0]->device ||
+            lat->host.weak != lats[0]->host.weak || lat->stream != lats[0]->stream)
+            return fail(RLBM_EINVAL, "grouped lattices need the same species count, storage, device and stream");
+        for (int i = 0; i < j; ++i)
+            if (lats[i] == lat) return fail(RLBM_EINVAL, "a lattice appears twice in the group");
+        if (steps[j] < 0) return fail(RLBM_EINVAL, "negative step count");
+        tmax = std::max<long long>(tmax, steps[j]);
+    }
+    if (tmax == 0) return RLBM_OK;
+    rlbm_lattice* l0 = lats[0];
+    HIP_TRY(hipSetDevice(l0->device), "hipSetDevice");
+    char* sc = nullptr;
+    HIP_TRY(group_scratch(l0->device, &sc), "hipGetSymbolAddress");
+    // the table, filled on the device from the lattices' own entries in
+    // chunks whose data travel as kernel arguments
+    int pre[3] = {0, 0, 0};
+    unsigned schemes = 0;
+    for (int base = 0; base < k; base += GROUP_CHUNK) {
+        GroupChunk c;
+        std::memset(&c, 0, sizeof(c));
+        c.base = base;
+        c.n = std::min(GROUP_CHUNK, k - base);
+        c.k = k;
+        for (int j = 0; j <= c.n; ++j) {
+            for (int a = 0; a < 3; ++a) c.blk[a][j] = pre[a];
+            if (j == c.n) break;
+            const rlbm_lattice* lat = lats[base + j];
+            c.src[j] = lat->d_lat;
+            c.t_end[j] = steps[base + j];
+            c.parity[j] = (int)((lat->host.parity0 + lat->steps_done) & 1);
+            schemes |= 1u << lat->host.reaction;
+            pre[0] += (int)((lat->geo.N + 255) / 256);
+            pre[1] += (int)((lat->geo.if_node.size() + BC_NODES - 1) / BC_NODES);
+            pre[2] += (int)((lat->geo.N + 63) / 64);
+        }
+        HIP_TRY(launch_group_gather(sc, c, l0->stream), "group table kernel");
+    }
+    const LatDev* table = (const LatDev*)(sc + GROUP_OFF_TABLE);
+    const int* blk = (const int*)(sc + GROUP_OFF_BLK);
+    for (long long t = 0; t < tmax; ++t) {
+        for (int phase = 0; phase < NPHASE; ++phase) {
+            StepLaunch a;
+            a.lats = table;
+            a.blk = phase == 0 ? blk + (k + 1) : (phase == NPHASE - 1 ? blk + 2 * (k + 1) : blk);
+            a.n_lat = k;
+            a.blocks = phase == 0 ? pre[1] : (phase == NPHASE - 1 ? pre[2] : pre[0]);
+            a.tp = (const long long*)sc;
+            a.toff = t;
+            a.stream = l0->stream;
+            a.schemes = schemes;
+            if (a.blocks == 0) continue;
+            HIP_TRY(launch_phase(phase, l0->M, l0->storage, l0->host.weak, a), "group kernel launch");
+        }
+    }
+    for (int j = 0; j < k; ++j) lats[j]->steps_done += steps[j];
+    return RLBM_OK;
+}
+
 void rlbm_batch_destroy(rlbm_batch* b) {
     if (!b) return;
     // the batch's last launches read its tables and the pinned staging its

@@ -34,7 +34,7 @@ EXPORTS = (
     "rlbm_lattice_shape", "rlbm_set_timing", "rlbm_kernel_times", "rlbm_batch_bytes",
     "rlbm_state_bytes", "rlbm_save_state", "rlbm_load_state",
     "rlbm_batch_create", "rlbm_batch_step", "rlbm_batch_destroy", "rlbm_last_error",
-    "rlbm_lattice_status", "rlbm_batch_status",
+    "rlbm_lattice_status", "rlbm_batch_status", "rlbm_step_group",
 )
 
 
@@ -115,6 +115,7 @@ def lib():
         "rlbm_batch_destroy": (None, [vp]),
         "rlbm_lattice_status": (c_int, [vp, POINTER(c_int32)]),
         "rlbm_batch_status": (c_int, [vp, POINTER(c_int32)]),
+        "rlbm_step_group": (c_int, [POINTER(vp), c_int32, POINTER(c_int64)]),
         "rlbm_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -336,6 +337,18 @@ class Lattice:
         _check(lib().rlbm_kernel_times(self.handle, ms, cnt, len(KERNELS)))
         return {name: (ms[k], cnt[k])
                 for k, name in enumerate(KERNELS)}
+
+
+GROUP_MAX_LATTICES = 256
+
+
+def step_group(lattices, steps):
+    """Advance lattices together without any allocation (rlbm_step_group):
+    all on one stream, at most GROUP_MAX_LATTICES of them."""
+    k = len(lattices)
+    arr = (c_void_p * k)(*[lat.handle.value for lat in lattices])
+    st = (c_int64 * k)(*[int(s) for s in steps])
+    _check(lib().rlbm_step_group(arr, k, st))
 
 
 class Batch:

@@ -1200,325 +1200,230 @@ __device__ __forceinline__ double eq_value(MechC mc, const EqState<M, SPV>& e, i
 }
 
 // ---------------------------------------------------------------------------
-// k_boundary: reconstruction at interface nodes (section 4).  Lane-parallel:
-// half a wave (32 lanes) takes one interface node, lane v < 27 the discrete
-// velocity i = v, so the node's 27 * L populations are loaded at once and
-// every equilibrium is evaluated by the lane of its velocity; zeroth and
-// first moments are half-wave sums.  The state construction (temperature
-// iteration, LODI) is evaluated redundantly by the lanes of a node.
+// k_boundary: reconstruction at interface nodes (section 4).  A block takes
+// 64 consecutive entries of the interface list (grouped by boundary type and
+// ordered by node within a type, so mostly a run of a wall row or plane),
+// one lane per node, and one wave per stored lattice: every population load
+// and store of a wave is coalesced and its lattice, with the lattice's
+// constants, is the same for the whole wave.  The node's state goes between
+// the waves through LDS: the lattices' moments, and the imposed and local
+// states that the first wave forms from them (temperature by the bounded
+// Newton iteration, the LODI outlet state).  All barriers are at the top
+// level of the kernel, so every wave meets all of them.
 // ---------------------------------------------------------------------------
-// Sum over the 32 lanes of a half-wave.  Lane pairs are combined within
-// quads, half-rows and rows of 16 by DPP moves, then the two rows of 16 by
-// gfx950's row swap (v_permlane16_swap), all in the vector ALU with no LDS
-// round trip.  Every step adds the same two operands on both lanes of a pair
-// (a + b = b + a exactly), so all 32 lanes end with bit-identical sums and
-// the lanes of a node continue from identical moments.
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double hsum32(double v) {
-    v += dpp_f64<0xb1>(v);    // quad_perm [1, 0, 3, 2]
-    v += dpp_f64<0x4e>(v);    // quad_perm [2, 3, 0, 1]
-    v += dpp_f64<0x141>(v);   // row_half_mirror
-    v += dpp_f64<0x140>(v);   // row_mirror
-    // rows 2k and 2k+1 exchange: with both operands v, element 0 holds row
-    // 2k's value and element 1 row 2k+1's value on every lane of the pair
-    const long long b = __builtin_bit_cast(long long, v);
-    const auto lo = __builtin_amdgcn_permlane16_swap((int)b, (int)b, false, false);
-    const auto hi = __builtin_amdgcn_permlane16_swap((int)(b >> 32), (int)(b >> 32), false, false);
-    const double r0 = __builtin_bit_cast(double, ((long long)hi[0] << 32) | (unsigned)lo[0]);
-    const double r1 = __builtin_bit_cast(double, ((long long)hi[1] << 32) | (unsigned)lo[1]);
-    return r0 + r1;
-}
+static_assert(BC_NODES == 64, "one lane per node in a wave");
 
-// Equilibrium state of section 4.1: density, mass fractions, velocity (with
-// per-species velocities in the wall's local state, eq. locua) and T.
-template <int M, bool SPV>
-struct BcState {
-    double rho, th, U, T;
-    double u[3];
-    double Y[M];
-    double us[SPV ? M : 1][3];
+// An equilibrium of one lattice at velocity i: s (U Wx Wy Wz + kx Wy Wz +
+// Wx (ky Wz + Wy kz)), with W[d][c + 1] the product-form factor of axis d.
+// The species and momentum lattices have U = 1 and k = 0; the energy lattice
+// has the factors of eq. geq_i (section 3.3) and U the internal energy.
+struct LatEq {
+    double s, U;
+    double W[3][3], k[3][3];
 };
 
-template <int M, bool SPV>
-__device__ __forceinline__ void bc_prepare(MechC mc, BcState<M, SPV>& e, double T) {
-    e.T = T;
-    e.th = mc.R_univ * mix_inv_m<M>(mc, e.Y) * T;
-    e.U = mix_U<M>(mc, e.Y, T);
+__device__ __forceinline__ void eq_axis(double w, double th, bool energy, double* Wa, double* ka) {
+    const double w2 = w * w;
+    const double P = th + w2;
+    Wa[0] = 0.5 * (P - w);
+    Wa[1] = 1.0 - P;
+    Wa[2] = 0.5 * (P + w);
+    if (energy) {
+        const double o1 = th * w + 0.5 * w2 * w;
+        const double o2 = th * th + 2.5 * th * w2 + 0.5 * w2 * w2;
+        ka[0] = 0.5 * (o2 - o1);
+        ka[1] = 0.5 * w2 - o2;
+        ka[2] = 0.5 * (o2 + o1);
+    } else {
+        ka[0] = ka[1] = ka[2] = 0.0;
+    }
 }
 
-// Equilibria of every lattice at this lane's velocity (eqs. faEqGeneral,
-// fEqGeneral, gEqGeneral): species a (all M, slaved included) into ea[a],
-// the momentum lattice into ef, the energy lattice into eg.
-template <int M, bool SPV>
-__device__ __forceinline__ void bc_eq(MechC mc, const BcState<M, SPV>& e, int c0, int c1, int c2, double* ea,
-                                      double& ef, double& eg) {
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-        const double tha = mc.Ra[a] * e.T;
-        const double w0 = SPV ? e.us[SPV ? a : 0][0] : e.u[0];
-        const double w1 = SPV ? e.us[SPV ? a : 0][1] : e.u[1];
-        const double w2 = SPV ? e.us[SPV ? a : 0][2] : e.u[2];
-        ea[a] = e.rho * e.Y[a] * psi(c0, w0, w0 * w0 + tha) * psi(c1, w1, w1 * w1 + tha) *
-                psi(c2, w2, w2 * w2 + tha);
-    }
-    ef = e.rho * psi(c0, e.u[0], e.u[0] * e.u[0] + e.th) * psi(c1, e.u[1], e.u[1] * e.u[1] + e.th) *
-         psi(c2, e.u[2], e.u[2] * e.u[2] + e.th);
-    GeqAxis gx, gy, gz;
-    geq_axis(e.u[0], e.th, gx);
-    geq_axis(e.u[1], e.th, gy);
-    geq_axis(e.u[2], e.th, gz);
-    const double Wx = sel3d(c0, gx.W[0], gx.W[1], gx.W[2]), kx = sel3d(c0, gx.k[0], gx.k[1], gx.k[2]);
-    const double Wy = sel3d(c1, gy.W[0], gy.W[1], gy.W[2]), ky = sel3d(c1, gy.k[0], gy.k[1], gy.k[2]);
-    const double Wz = sel3d(c2, gz.W[0], gz.W[1], gz.W[2]), kz = sel3d(c2, gz.k[0], gz.k[1], gz.k[2]);
-    eg = e.rho * (e.U * Wx * Wy * Wz + kx * Wy * Wz + Wx * (ky * Wz + Wy * kz));
+template <int C0, int C1, int C2>
+__device__ __forceinline__ double lat_eq(const LatEq& e) {
+    const double wx = e.W[0][C0 + 1], wy = e.W[1][C1 + 1], wz = e.W[2][C2 + 1];
+    const double wyz = wy * wz;
+    return e.s * (e.U * wx * wyz + e.k[0][C0 + 1] * wyz + wx * (e.k[1][C1 + 1] * wz + wy * e.k[2][C2 + 1]));
 }
 
-// Local state (eqs. locRho .. locT and their inlet/outlet counterparts): the
-// moments of the populations with the incoming links set to the imposed
-// equilibrium A, outgoing links from advection (pa, pf, pg: this lane's
-// streamed values by species / momentum / energy lattice).  A's equilibria
-// at this lane's velocity are returned in ea, ef, eg for the caller's
-// reconstruction.
-template <int M, int W, bool SPV, bool ASPV>
-__device__ __forceinline__ void bc_local(MechC mc, const BcState<M, ASPV>& A, int s, bool act, bool in, int c0,
-                                         int c1, int c2, const double* pa, double pf, double pg,
-                                         BcState<M, SPV>& Lc, int* fail, double* ea, double& ef, double& eg) {
-    bc_eq<M, ASPV>(mc, A, c0, c1, c2, ea, ef, eg);
-    double ra[M], ja[M][3];
-    const double cx = c0, cy = c1, cz = c2;
+// Node state of an equilibrium (sections 4.1-4.4), one LDS column per node:
+// density, temperature, mixture theta, internal energy, velocity, mass
+// fractions.
+constexpr int ST_RHO = 0, ST_T = 1, ST_TH = 2, ST_U = 3, ST_V = 4, ST_Y = 7;
+
+template <int M>
+__device__ __forceinline__ void state_store(MechC mc0, double (*st)[BC_NODES], int lane, double rho, const double* u,
+                                            const double* Y, double T) {
+    reload_barrier();
+    MechC mc = in_loop(mc0);
+    st[ST_RHO][lane] = rho;
+    st[ST_T][lane] = T;
+    st[ST_TH][lane] = mc.R_univ * mix_inv_m<M>(mc, Y) * T;
+    st[ST_U][lane] = mix_U<M>(mc, Y, T);
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-        if (a == s) continue;
-        const double v = act ? (in ? ea[a] : pa[a]) : 0.0;
-        ra[a] = hsum32(v);
-        ja[a][0] = hsum32(v * cx);
-        ja[a][1] = hsum32(v * cy);
-        ja[a][2] = hsum32(v * cz);
-    }
-    const double vf = act ? (in ? ef : pf) : 0.0;
-    const double vg = act ? (in ? eg : pg) : 0.0;
-    const double rl = hsum32(vf);
-    const double jl[3] = {hsum32(vf * cx), hsum32(vf * cy), hsum32(vf * cz)};
-    const double El = hsum32(vg);
-    double rs = rl, j0 = jl[0], j1 = jl[1], j2 = jl[2];
+    for (int d = 0; d < 3; ++d) st[ST_V + d][lane] = u[d];
 #pragma unroll
-    for (int a = 0; a < M; ++a)
-        if (a != s) { rs -= ra[a]; j0 -= ja[a][0]; j1 -= ja[a][1]; j2 -= ja[a][2]; }
-#pragma unroll
-    for (int a = 0; a < M; ++a)
-        if (a == s) { ra[a] = rs; ja[a][0] = j0; ja[a][1] = j1; ja[a][2] = j2; }
-    Lc.rho = rl;
-    const double irl = 1.0 / rl;
-#pragma unroll
-    for (int dd = 0; dd < 3; ++dd) Lc.u[dd] = jl[dd] * irl;
-    double iry = irl;   // the weakly coupled storage normalises Y by sum_a rho_a
-    if constexpr (W) {
-        double ry = 0.0;
-#pragma unroll
-        for (int a = 0; a < M; ++a) ry += ra[a];
-        iry = 1.0 / ry;
-    }
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-        Lc.Y[a] = ra[a] * iry;
-        if constexpr (SPV) {
-            const bool small = ra[a] <= 1e-14 * rl;
-            const double ira = small ? 0.0 : 1.0 / ra[a];
-#pragma unroll
-            for (int dd = 0; dd < 3; ++dd) Lc.us[a][dd] = small ? Lc.u[dd] : ja[a][dd] * ira;
-        }
-    }
-    const double Ul = El * irl - 0.5 * (Lc.u[0] * Lc.u[0] + Lc.u[1] * Lc.u[1] + Lc.u[2] * Lc.u[2]);
-    const double T_l = solve_T<M>(mc, Lc.Y, Ul, A.T, fail);
-    bc_prepare<M, SPV>(mc, Lc, T_l);
+    for (int c = 0; c < M; ++c) st[ST_Y + c][lane] = Y[c];
 }
 
-constexpr int BC_THREADS = 32 * BC_NODES;
+// Equilibrium factors of stored lattice l (the wave's) for the state in
+// column `lane` of st; a species lattice takes the velocity w (its own in
+// the wall's local state, eq. locua), the others the mixture velocity.
+template <int M, int W>
+__device__ __forceinline__ void lat_prepare(MechC mc0, const double (*st)[BC_NODES], int lane, int l, int slaved,
+                                            const double* w, LatEq& q) {
+    constexpr int LF = Lat<M, W>::LF, LG = Lat<M, W>::LG;
+    reload_barrier();
+    MechC mc = in_loop(mc0);
+    const bool lg = l == LG, sp = l < LF;
+    const int a = sp ? (W ? l : l + (l >= slaved ? 1 : 0)) : 0;
+    const double rho = st[ST_RHO][lane];
+    const double th = sp ? mc.Ra[a] * st[ST_T][lane] : st[ST_TH][lane];
+    q.s = sp ? rho * st[ST_Y + a][lane] : rho;
+    q.U = lg ? st[ST_U][lane] : 1.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) eq_axis(sp && w ? w[d] : st[ST_V + d][lane], th, lg, q.W[d], q.k[d]);
+}
+
+// Compile-time loop over the 27 velocities.
+template <int I, typename F>
+__device__ __forceinline__ void for_q(F&& f) {
+    if constexpr (I < Q) {
+        f(std::integral_constant<int, I>{});
+        for_q<I + 1>(f);
+    }
+}
+
+template <int M, int W>
+constexpr int bc_threads() { return BC_NODES * Lat<M, W>::NL; }
 
 template <int M, typename S, int W>
-__global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_boundary(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                                         int n_lat, const long long* __restrict__ tp, long long toff) {
+__global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
+    const LatDev* __restrict__ lats, const int* __restrict__ blk, int n_lat, const long long* __restrict__ tp,
+    long long toff) {
+    constexpr int LF = Lat<M, W>::LF, LG = Lat<M, W>::LG, NL = Lat<M, W>::NL;
+    __shared__ double mom[NL][4][BC_NODES];             // moments per lattice and node
+    __shared__ double stA[ST_Y + M][BC_NODES];          // imposed state
+    __shared__ double stL[ST_Y + M][BC_NODES];          // local state
+    __shared__ double stT[ST_Y + M][BC_NODES];          // the full inlet's target
+    __shared__ int flg[BC_NODES];
     const long long t = step_time(tp, toff);
     const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
-    if (t >= L.t_end) return;
-    const int k = (b - blk[lj]) * BC_NODES + (int)threadIdx.x / 32;
-    if (k >= L.n_if) return;                       // whole half-waves leave together
-    const int v = threadIdx.x % 32;
-    const bool act = v < Q;
-    const int i = act ? v : 0;
-    const int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);
-    MechC mc = *as_const(L.mech);
-    const void* src = L.pop[(L.parity0 + t) & 1];
-    const int node = L.if_node[k];
-    const unsigned Dm = L.if_mask[k];
-    const bool in = act && ((Dm >> i) & 1u);      // incoming link (set D)
-    const int type = L.if_type[k];
-    constexpr int LF = Lat<M, W>::LF, LG = Lat<M, W>::LG, NL = Lat<M, W>::NL;
-    const int s = W ? M : L.slaved;
+    if (t >= L.t_end) return;                       // the whole block
+    const int lane = (int)threadIdx.x % BC_NODES;
+    const int l = __builtin_amdgcn_readfirstlane((int)threadIdx.x / BC_NODES);   // this wave's lattice
+    const int k = (b - blk[lj]) * BC_NODES + lane;
+    const bool live = k < L.n_if;
+    const int kk = live ? k : 0;                    // nodes past the end mirror entry 0 and write nothing
+    MechC mc0 = *as_const(L.mech);
+    const int par = (L.parity0 + t) & 1;
+    const RLBM_GLOBAL S* src = as_global(static_cast<const S*>(L.pop[par]));
+    RLBM_GLOBAL S* bc = as_global(static_cast<S*>(L.bcbuf));
     const size_t N = (size_t)L.N;
+    const int nif = L.n_if;
+    const int node = L.if_node[kk];
+    const unsigned Dm = L.if_mask[kk];
+    const int type = L.if_type[kk];
+    const int s = W ? M : L.slaved;
     const int x = node % L.nx, r = node / L.nx, y = r % L.ny, z = r / L.ny;
     PullOff o;
     pull_offsets(L, x, y, z, o);
-    const int off = node + sel3(c0, o.x[0], 0, o.x[2]) + sel3(c1, o.y[0], 0, o.y[2]) + sel3(c2, o.z[0], 0, o.z[2]);
-    int fail = 0;
-
-    // this lane's populations after advection (outgoing links); on incoming
-    // links at a wall, the bounce-back source f'_{opp(i)}(x) instead (all
-    // lattices at a bounce-back wall, species and momentum at a TMS wall)
     const bool wall = type == RLBM_FACE_WALL;
     const bool bback = type == RLBM_FACE_BOUNCEBACK;
-    const bool bbl = in && (wall || bback);
-    const int ld_off = bbl ? node : off;
-    const int ld_i = bbl ? Q - 1 - i : i;
-    const bool need = act && (!in || wall || bback);   // open-face incoming links take no population
-    const int par = (L.parity0 + t) & 1;
+    const bool outlet = type == RLBM_FACE_OUTLET;
+    const bool inlet_full = type == RLBM_FACE_INLET;
     const RLBM_CONST double* G = as_const(L.ref);
-    // FP32 deviation storage: the advected value's reference belongs to this
-    // node; a bounce-back source f'_{opp(i)}(x) is referred to the node that
-    // would pull it, the pull source x - c_i (wrapped)
-    float s_ld[NL], s_own[NL];
+    if (l == 0) flg[lane] = 0;
+
+    // FP32 deviation storage: references belong to the node that reads a
+    // value, this node for an advected value and for what is written to the
+    // boundary buffer, the pull source x - c_i (wrapped) for a bounce-back
+    // source f'_{opp(i)}(x)
+    float sl = 0.0f, sf = 0.0f;
     if constexpr (sizeof(S) == 4) {
-        const RLBM_GLOBAL float* a0 = scale_at(L, par, bbl ? off : node);
-        const RLBM_GLOBAL float* a1 = scale_at(L, par, node);
-#pragma unroll
-        for (int l = 0; l < NL; ++l) { s_ld[l] = a0[l]; s_own[l] = a1[l]; }
+        const RLBM_GLOBAL float* sc = scale_at(L, par, node);
+        sl = sc[l];
+        sf = sc[LF];
     }
-    auto refv = [&](const float* sc, int l, int li) -> double {
-        if constexpr (sizeof(S) == 4)
-            return l < LG ? ref_of(sc[l], G[li]) : ref_g(sc[LG], sc[LF], G[li], G[REF_K<NL> + li % Q]);
-        else return 0.0;
-    };
-    double pa[M], pf = 0.0, pg = 0.0;
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-        pa[a] = 0.0;
-        if (a == s || !need) continue;
-        const int l = lat_of(a, s);
-        const int li = l * Q + ld_i;
-        pa[a] = Codec<S>::ld(src, (size_t)li * N + ld_off, refv(s_ld, l, li));
-    }
-    if (need) {
-        const int lf = LF * Q + ld_i;
-        pf = Codec<S>::ld(src, (size_t)lf * N + ld_off, refv(s_ld, LF, lf));
-        if (!in) {
-            const int lg = LG * Q + i;
-            pg = Codec<S>::ld(src, (size_t)lg * N + off, refv(s_own, LG, lg));
-        } else if (bback) {
-            const int lg = LG * Q + ld_i;
-            pg = Codec<S>::ld(src, (size_t)lg * N + ld_off, refv(s_ld, LG, lg));
+    // population (l, i) after advection, or with bb on an incoming link the
+    // bounce-back source (every lattice at a bounce-back wall, species and
+    // momentum at a TMS wall)
+    auto pop = [&](auto ic, bool bb) -> double {
+        constexpr int i = decltype(ic)::value;
+        constexpr int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i), io = Q - 1 - i;
+        const int off = node + sel3(c0, o.x[0], 0, o.x[2]) + sel3(c1, o.y[0], 0, o.y[2]) + sel3(c2, o.z[0], 0, o.z[2]);
+        double v;
+        if (bb && ((Dm >> i) & 1u)) {
+            v = (double)ld_at(src + (size_t)(l * Q + io) * N, node);
+            if constexpr (sizeof(S) == 4) {
+                const RLBM_GLOBAL float* sc = scale_at(L, par, off);
+                const float sb = sc[l], sfb = sc[LF];
+                v += l == LG ? ref_g(sb, sfb, G[l * Q + io], G[REF_K<NL> + io]) : ref_of(sb, G[l * Q + io]);
+            }
+        } else {
+            v = (double)ld_at(src + (size_t)(l * Q + i) * N, off);
+            if constexpr (sizeof(S) == 4)
+                v += l == LG ? ref_g(sl, sf, G[l * Q + i], G[REF_K<NL> + i]) : ref_of(sl, G[l * Q + i]);
         }
-    }
-    auto put = [&](int l, double val) {
-        const int li = l * Q + i;
-        if (act) Codec<S>::st(L.bcbuf, (size_t)li * L.n_if + k, val, refv(s_own, l, li));
+        return v;
+    };
+    auto put = [&](auto ic, double v) {
+        constexpr int i = decltype(ic)::value;
+        if (!live) return;
+        RLBM_GLOBAL S* pl = bc + (size_t)(l * Q + i) * nif;
+        if constexpr (sizeof(S) == 4) {
+            const double ref = l == LG ? ref_g(sl, sf, G[l * Q + i], G[REF_K<NL> + i]) : ref_of(sl, G[l * Q + i]);
+            st_at(pl, k, __double2float_rn(v - ref));
+        } else {
+            st_at(pl, k, v);
+        }
     };
 
+    // step 1.  Bounce-back wall (section 4.2.1, eq. bb): incoming links carry
+    // the opposite population of the same node, outgoing links their own.
+    // TMS wall (section 4.2.2): the bounce-back densities (eqs. BBrho, BBY),
+    // zeroth moments with the bounce-back sources on D.
     if (bback) {
-        // bounce-back wall (section 4.2.1, eq. bb): incoming links take the
-        // opposite population of the same node, outgoing links keep theirs
+        for_q<0>([&](auto ic) { put(ic, pop(ic, true)); });
+    } else if (wall && l <= LF) {
+        double m0 = 0.0;
+        for_q<0>([&](auto ic) { m0 += pop(ic, true); });
+        mom[l][0][lane] = m0;
+    }
+    __syncthreads();
+    // step 2: the imposed state, formed by the first wave: the TMS target
+    // (u = 0, T_w(x)), the LODI outlet state (section 4.4, from the previous
+    // outlet state and the previous post-boundary moments of the first
+    // interior node), or the inlet equilibrium (section 4.3, eqs. in_f, in_g,
+    // in_fa)
+    if (l == 0 && !bback) {
+        double Y[M], u[3] = {0.0, 0.0, 0.0}, rho, T;
+        if (wall) {
+            double rs = 0.0;
+            const double rb = mom[LF][0][lane];
 #pragma unroll
-        for (int a = 0; a < M; ++a)
-            if (a != s) put(lat_of(a, s), pa[a]);
-        put(LF, pf);
-        put(LG, pg);
-    } else if (wall) {
-        // Tamm-Mott-Smith wall (section 4.2.2)
-        BcState<M, false> A;   // target: bounce-back rho and Y (eqs. BBrho, BBY), u^tgt = 0, T^tgt
-        {
-            double rY[M];
-            const double rb = hsum32(act ? pf : 0.0);
-            double rs = rb;
-#pragma unroll
-            for (int a = 0; a < M; ++a) {
-                if (a == s) continue;
-                rY[a] = hsum32(pa[a]);
-                rs -= rY[a];
+            for (int c = 0; c < M; ++c) {
+                const bool slv = !W && c == s;
+                const double v = slv ? 0.0 : mom[slv ? 0 : (W ? c : c - (c > s ? 1 : 0))][0][lane];
+                Y[c] = v;
+                rs += v;
             }
-            // the weakly coupled storage normalises Y by sum_a rho_a
-            double ry = rb;
-            if constexpr (W) {
-                ry = 0.0;
+            if constexpr (!W) {
 #pragma unroll
-                for (int a = 0; a < M; ++a) ry += rY[a];
+                for (int c = 0; c < M; ++c)
+                    if (c == s) Y[c] = rb - rs;
             }
-            const double iry = 1.0 / ry;
+            const double iry = 1.0 / (W ? rs : rb);   // the weakly coupled storage normalises Y by sum_a rho_a
 #pragma unroll
-            for (int a = 0; a < M; ++a) A.Y[a] = (a == s ? rs : rY[a]) * iry;
-            A.rho = rb;
-            A.u[0] = A.u[1] = A.u[2] = 0.0;
-            bc_prepare<M, false>(mc, A, L.if_T[k]);
-        }
-        // step 3: local state with species velocities (eqs. locRho .. locT)
-        BcState<M, true> Lc;
-        double eA[M], fA, gA, eL[M], fL, gL;
-        bc_local<M, W, true, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail, eA, fA, gA);
-        // step 4 (eqs. ftms, gtms, fatms)
-        bc_eq<M, true>(mc, Lc, c0, c1, c2, eL, fL, gL);
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-            if (a != s) put(lat_of(a, s), in ? 2.0 * eA[a] - eL[a] : eA[a] + pa[a] - eL[a]);
-        put(LF, in ? 2.0 * fA - fL : fA + pf - fL);
-        put(LG, in ? 2.0 * gA - gL : gA + pg - gL);
-    } else if (type == RLBM_FACE_INLET_LOCAL) {
-        // simplified flux inlet (end of section 4.3): the local state of step 2
-        // with the incoming links at the inlet equilibrium, and every
-        // population of the node at the local equilibria (eqs. in_loc_*)
-        BcState<M, false> A;
-        A.rho = L.rho_in;
-        A.u[0] = L.u_in; A.u[1] = 0.0; A.u[2] = 0.0;
-#pragma unroll
-        for (int a = 0; a < M; ++a) A.Y[a] = L.Y_in[a];
-        bc_prepare<M, false>(mc, A, L.T_in);
-        BcState<M, false> Lc;
-        double eA[M], fA, gA;
-        bc_local<M, W, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail, eA, fA, gA);
-        double eL[M], fL, gL;
-        bc_eq<M, false>(mc, Lc, c0, c1, c2, eL, fL, gL);
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-            if (a != s) put(lat_of(a, s), eL[a]);
-        put(LF, fL);
-        put(LG, gL);
-    } else if (type == RLBM_FACE_INLET) {
-        // flux inlet (section 4.3)
-        BcState<M, false> A;   // inlet equilibrium (eqs. in_f, in_g, in_fa)
-        A.rho = L.rho_in;
-        A.u[0] = L.u_in; A.u[1] = 0.0; A.u[2] = 0.0;
-#pragma unroll
-        for (int a = 0; a < M; ++a) A.Y[a] = L.Y_in[a];
-        bc_prepare<M, false>(mc, A, L.T_in);
-        BcState<M, false> Lc;  // local state (eqs. inletlocRho .. inletlocT)
-        double eA[M], fA, gA, eL[M], fL, gL, eT[M], fT, gT;
-        bc_local<M, W, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail, eA, fA, gA);
-        // target: local density and composition at the imposed u, T (eqs. in_tgt_*)
-        BcState<M, false> Tg;
-        Tg.rho = Lc.rho;
-        Tg.u[0] = L.u_in; Tg.u[1] = 0.0; Tg.u[2] = 0.0;
-#pragma unroll
-        for (int a = 0; a < M; ++a) Tg.Y[a] = Lc.Y[a];
-        bc_prepare<M, false>(mc, Tg, L.T_in);
-        // (eqs. f_inlet, g_inlet, fa_inlet)
-        bc_eq<M, false>(mc, Lc, c0, c1, c2, eL, fL, gL);
-        bc_eq<M, false>(mc, Tg, c0, c1, c2, eT, fT, gT);
-#pragma unroll
-        for (int a = 0; a < M; ++a)
-            if (a != s) put(lat_of(a, s), eT[a] + (in ? eA[a] : pa[a]) - eL[a]);
-        put(LF, fT + (in ? fA : pf) - fL);
-        put(LG, gT + (in ? gA : pg) - gL);
-    } else {
-        // outlet (section 4.4): LODI state from the previous outlet state and
-        // the previous post-boundary moments of the first interior node
-        BcState<M, false> A;
-        {
-            const int ko = L.if_out[k];
+            for (int c = 0; c < M; ++c) Y[c] *= iry;
+            rho = rb;
+            T = L.if_T[kk];
+        } else if (outlet) {
+            reload_barrier();
+            MechC mc = in_loop(mc0);
+            const int ko = L.if_out[kk];
             const size_t No = (size_t)L.n_out;
             double* os = L.out_state;
             const double rho0 = os[0 * No + ko];
@@ -1527,9 +1432,9 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
             double Y0[M], Y1[M];
             const size_t inn = (size_t)node - 1;
 #pragma unroll
-            for (int a = 0; a < M; ++a) {
-                Y0[a] = os[(5 + a) * No + ko];
-                Y1[a] = L.aux[(AUX_Y + a) * N + inn];
+            for (int c = 0; c < M; ++c) {
+                Y0[c] = os[(5 + c) * No + ko];
+                Y1[c] = L.aux[(AUX_Y + c) * N + inn];
             }
             const double rho1 = L.aux[AUX_RHO * N + inn];
             const double u1[3] = {L.aux[(AUX_U + 0) * N + inn], L.aux[(AUX_U + 1) * N + inn],
@@ -1540,48 +1445,152 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(3, 3
             const double P1 = rho1 * mc.R_univ * mix_inv_m<M>(mc, Y1) * T1;
             double Cv = 0.0;
 #pragma unroll
-            for (int a = 0; a < M; ++a) Cv += Y0[a] * species_cv(mc, a, T0);
+            for (int c = 0; c < M; ++c) Cv += Y0[c] * species_cv(mc, c, T0);
             const double gam = (Cv + R0) / Cv;
-            const double c = sqrt(gam * P0 / rho0);
+            const double cs = sqrt(gam * P0 / rho0);
             const double un = u0[0];
-            const double Ma = un / c;
-            const double L1 = L.sigma * (1.0 - Ma * Ma) * c / (double)L.nx * (P0 - L.P_inf);
-            const double L2 = un * (c * c * (rho0 - rho1) - (P0 - P1));
+            const double Ma = un / cs;
+            const double L1 = L.sigma * (1.0 - Ma * Ma) * cs / (double)L.nx * (P0 - L.P_inf);
+            const double L2 = un * (cs * cs * (rho0 - rho1) - (P0 - P1));
             const double L3 = un * (u0[1] - u1[1]);
             const double L4 = un * (u0[2] - u1[2]);
-            const double L5 = (un + c) * ((P0 - P1) + rho0 * c * (u0[0] - u1[0]));
-            const double rho_o = rho0 - (L2 + 0.5 * (L5 + L1)) / (c * c);
+            const double L5 = (un + cs) * ((P0 - P1) + rho0 * cs * (u0[0] - u1[0]));
+            rho = rho0 - (L2 + 0.5 * (L5 + L1)) / (cs * cs);
             const double P_o = P0 - 0.5 * (L5 + L1);
-            A.rho = rho_o;
-            A.u[0] = un - (L5 - L1) / (2.0 * rho0 * c);
-            A.u[1] = u0[1] - L3;
-            A.u[2] = u0[2] - L4;
+            u[0] = un - (L5 - L1) / (2.0 * rho0 * cs);
+            u[1] = u0[1] - L3;
+            u[2] = u0[2] - L4;
 #pragma unroll
-            for (int a = 0; a < M; ++a) A.Y[a] = Y0[a] - un * (Y0[a] - Y1[a]);   // eq. convectiveBC
-            const double T_o = P_o / (rho_o * mc.R_univ * mix_inv_m<M>(mc, A.Y));
-            bc_prepare<M, false>(mc, A, T_o);
-            // all lanes of the node have read the previous state above
-            __builtin_amdgcn_wave_barrier();
-            if (v == 0) {
-                os[0 * No + ko] = A.rho;
-                os[1 * No + ko] = A.u[0]; os[2 * No + ko] = A.u[1]; os[3 * No + ko] = A.u[2];
-                os[4 * No + ko] = T_o;
+            for (int c = 0; c < M; ++c) Y[c] = Y0[c] - un * (Y0[c] - Y1[c]);   // eq. convectiveBC
+            T = P_o / (rho * mc.R_univ * mix_inv_m<M>(mc, Y));
+            if (live) {
+                os[0 * No + ko] = rho;
+                os[1 * No + ko] = u[0]; os[2 * No + ko] = u[1]; os[3 * No + ko] = u[2];
+                os[4 * No + ko] = T;
 #pragma unroll
-                for (int a = 0; a < M; ++a) os[(5 + a) * No + ko] = A.Y[a];
+                for (int c = 0; c < M; ++c) os[(5 + c) * No + ko] = Y[c];
             }
-        }
-        BcState<M, false> Lc;  // local state (eqs. outletlocRho .. outletlocT)
-        double eA[M], fA, gA, eL[M], fL, gL;
-        bc_local<M, W, false, false>(mc, A, s, act, in, c0, c1, c2, pa, pf, pg, Lc, &fail, eA, fA, gA);
-        // (eqs. f_outlet, g_outlet, fa_outlet)
-        bc_eq<M, false>(mc, Lc, c0, c1, c2, eL, fL, gL);
+        } else {
+            rho = L.rho_in;
+            u[0] = L.u_in;
 #pragma unroll
-        for (int a = 0; a < M; ++a)
-            if (a != s) put(lat_of(a, s), in ? 2.0 * eA[a] - eL[a] : eA[a] + pa[a] - eL[a]);
-        put(LF, in ? 2.0 * fA - fL : fA + pf - fL);
-        put(LG, in ? 2.0 * gA - gL : gA + pg - gL);
+            for (int c = 0; c < M; ++c) Y[c] = L.Y_in[c];
+            T = L.T_in;
+        }
+        state_store<M>(mc0, stA, lane, rho, u, Y, T);
     }
-    if (fail && v == 0) atomicOr(L.flag, 1);
+    __syncthreads();
+    // step 3: moments of the mixed set, incoming links at the imposed
+    // equilibria and outgoing ones advected (eqs. locRho .. locT and their
+    // inlet and outlet counterparts)
+    LatEq eA;
+    if (!bback) {
+        lat_prepare<M, W>(mc0, stA, lane, l, s, nullptr, eA);
+        double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+        for_q<0>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);
+            double v;
+            if ((Dm >> i) & 1u) v = lat_eq<c0, c1, c2>(eA);
+            else v = pop(ic, false);
+            m0 += v;
+            if (c0) m1 += c0 > 0 ? v : -v;
+            if (c1) m2 += c1 > 0 ? v : -v;
+            if (c2) m3 += c2 > 0 ? v : -v;
+        });
+        mom[l][0][lane] = m0; mom[l][1][lane] = m1; mom[l][2][lane] = m2; mom[l][3][lane] = m3;
+    }
+    __syncthreads();
+    // the local state (first wave): rho and u from the momentum lattice, the
+    // species densities (the slaved one by difference, eq. strongest), T by
+    // Newton on the energy lattice's internal energy from the imposed T; and
+    // the full inlet's target, the local density and composition at the
+    // imposed u^in and T^in (eqs. in_tgt_*)
+    if (l == 0 && !bback) {
+        double Y[M], u[3];
+        const double rl = mom[LF][0][lane];
+        double rs = rl, ry = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const bool slv = !W && c == s;
+            const double v = slv ? 0.0 : mom[slv ? 0 : (W ? c : c - (c > s ? 1 : 0))][0][lane];
+            Y[c] = v;
+            rs -= v;
+            ry += v;
+        }
+        if constexpr (!W) {
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+                if (c == s) Y[c] = rs;
+        }
+        const double iry = 1.0 / (W ? ry : rl), irl = 1.0 / rl;   // weakly coupled: Y by sum_a rho_a
+#pragma unroll
+        for (int c = 0; c < M; ++c) Y[c] *= iry;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) u[d] = mom[LF][1 + d][lane] * irl;
+        const double Ul = mom[LG][0][lane] * irl - 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        int fail = 0;
+        reload_barrier();
+        const double Tl = solve_T<M>(in_loop(mc0), Y, Ul, stA[ST_T][lane], &fail);
+        flg[lane] = fail;
+        state_store<M>(mc0, stL, lane, rl, u, Y, Tl);
+        if (inlet_full) {
+            const double uin[3] = {L.u_in, 0.0, 0.0};
+            state_store<M>(mc0, stT, lane, rl, uin, Y, L.T_in);
+        }
+    }
+    __syncthreads();
+    // step 4: reconstruction of this wave's lattice
+    if (!bback) {
+        // the wall's local species equilibria take the species' own velocity
+        // u_a = j_a / rho_a (u where rho_a <= 1e-14 rho, eq. locua)
+        double w[3];
+        const double* wp = nullptr;
+        if (wall && l < LF) {
+            const double ra = mom[l][0][lane];
+            const bool small = ra <= 1e-14 * stL[ST_RHO][lane];
+            const double ir = small ? 0.0 : 1.0 / ra;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) w[d] = small ? stL[ST_V + d][lane] : mom[l][1 + d][lane] * ir;
+            wp = w;
+        }
+        LatEq eL;
+        lat_prepare<M, W>(mc0, stL, lane, l, s, wp, eL);
+        if (type == RLBM_FACE_INLET_LOCAL) {
+            // the simplified inlet: every population at the local equilibria
+            // (eqs. in_loc_*)
+            for_q<0>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                put(ic, lat_eq<cx_of(i), cy_of(i), cz_of(i)>(eL));
+            });
+        } else if (inlet_full) {
+            // eqs. f_inlet, g_inlet, fa_inlet
+            LatEq eT;
+            lat_prepare<M, W>(mc0, stT, lane, l, s, nullptr, eT);
+            for_q<0>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);
+                double fi;
+                if ((Dm >> i) & 1u) fi = lat_eq<c0, c1, c2>(eA);
+                else fi = pop(ic, false);
+                put(ic, lat_eq<c0, c1, c2>(eT) + fi - lat_eq<c0, c1, c2>(eL));
+            });
+        } else {
+            // TMS wall (eqs. ftms, gtms, fatms) and outlet (eqs. f_outlet,
+            // g_outlet, fa_outlet): 2 A - loc on incoming links, A + f - loc
+            // on outgoing ones
+            for_q<0>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);
+                const double ea = lat_eq<c0, c1, c2>(eA), el = lat_eq<c0, c1, c2>(eL);
+                double fi;
+                if ((Dm >> i) & 1u) fi = ea;
+                else fi = pop(ic, false);
+                put(ic, ea + fi - el);
+            });
+        }
+    }
+    if (l == 0 && live && flg[lane]) atomicOr(L.flag, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1996,7 +2005,7 @@ static hipError_t launch_step_phase(int phase, int M, int weak, const StepLaunch
     if (a.blocks <= 0) return hipSuccess;
     (void)hipGetLastError();   // report this launch's error only
     if (phase == 0) {
-        RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_boundary<MM, S, WW>), dim3(a.blocks), dim3(BC_THREADS), 0,
+        RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_boundary<MM, S, WW>), dim3(a.blocks), dim3(bc_threads<MM, WW>()), 0,
                                                     a.stream, a.lats, a.blk, a.n_lat, a.tp, a.toff))
     } else if (phase == 1) {
         RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_local<MM, S, WW>), dim3(a.blocks), dim3(256), 0, a.stream,

@@ -19,8 +19,8 @@ struct StepLaunch {
     unsigned schemes;     // bit r set if a lattice uses RLBM_REACTION r (phase 2 launches one kernel per scheme)
 };
 
-// Interface nodes per boundary block (half a wave per node).
-constexpr int BC_NODES = 8;
+// Interface nodes per boundary block (one wave, one lane per node).
+constexpr int BC_NODES = 64;
 
 // phase 0: boundary (BC_NODES interface nodes per block); phases 1 and 2:
 // moments, diffusion and forward-Euler chemistry, then gradients (with the

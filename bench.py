@@ -35,20 +35,38 @@ def _kernel_hash():
     return h.hexdigest()[:16]
 
 
-def _traffic(storage, kernel, dims):
-    """HBM bytes per launch of `kernel` from committed rocprofv3 counter runs
-    (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a copy kernel of
-    known size), or None when absent, taken on another workload, or taken on
-    different kernel sources."""
+def _traffic_all(storage, dims):
+    """HBM bytes per launch of every step kernel from committed rocprofv3
+    counter runs (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a
+    copy kernel of known size): {kernel: bytes}, or {} when absent, taken on
+    another workload, or taken on different kernel sources."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
-        return None
+        return {}
     if t.get("kernel_hash") != _kernel_hash() or t.get("dims") != list(dims):
-        return None
-    rec = t.get(storage, {}).get(kernel)
-    return None if rec is None else rec.get("bytes_per_launch")
+        return {}
+    return {k: v["bytes_per_launch"] for k, v in t.get(storage, {}).items() if "bytes_per_launch" in v}
+
+
+def _traffic(storage, kernel, dims):
+    """Counted HBM bytes per launch of one kernel, or None (see _traffic_all)."""
+    return _traffic_all(storage, dims).get(kernel)
+
+
+def _host():
+    """The host the CPU baseline ran on: logical CPUs and model name."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
 
 
 def _time_storage(case, storage, steps, warmup):
@@ -89,6 +107,20 @@ def _time_storage(case, storage, steps, warmup):
             "finite": bool(ok)}
 
 
+def _step_roofline(storage, case, N, bytes_node, ms_step):
+    """The whole step against the HBM roofline: algorithmic bytes (every
+    stored population read and written once) per step over the step time,
+    and the counted bytes of all of its kernels (rocprofv3, when recorded
+    for these sources) over the algorithmic ones."""
+    alg = bytes_node * N
+    counted = _traffic_all(storage, (case["nx"], case["ny"], case["nz"]))
+    tot = sum(counted.values()) if counted else None
+    achieved = alg / (ms_step * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_step": alg,
+            "counted_bytes_per_step": tot, "counted_over_algorithmic": None if tot is None else tot / alg}
+
+
 def _cpu_baseline(budget_s=20.0):
     """The oracle, as it stands, on a bounded sample of the same workload: a
     64x16x16 channel with the same mechanism and boundaries, stepped until
@@ -109,7 +141,8 @@ def _cpu_baseline(budget_s=20.0):
     N = case["nx"] * case["ny"] * case["nz"]
     return {"value": N * n / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"channel3d 64x16x16 (16384 nodes), same mechanism and boundaries, "
-                      f"{n} steps in {dt:.1f} s, FP64 NumPy, 1 thread"}
+                      f"{n} steps in {dt:.1f} s, FP64 NumPy, 1 thread",
+            "host": _host()}
 
 
 def _bench_tubes(args):
@@ -171,12 +204,20 @@ def _bench_serve(args):
     torch.cuda.synchronize()
     srv = Server(backend, budget_bytes=200e9, max_slots=256, round_s=0.05)
     t0 = time.perf_counter()
-    out = srv.run(reqs)
+    done = [0]
+
+    def progress(r):
+        done[0] += 1
+        print(f"request {r.rid} done ({done[0]}/{len(reqs)}) at {time.perf_counter() - t0:.1f} s, "
+              f"latency {r.latency:.2f} s{' FAILED' if r.failed else ''}", file=sys.stderr, flush=True)
+
+    out = srv.run(reqs, on_done=progress)
     wall = time.perf_counter() - t0
     summ = summarize(out, wall)
     kinds = {}
     for q, r in zip(trace, out):
         kinds.setdefault(q["kind"], []).append(r.latency)
+    offered = sum(r.nodes * r.steps for r in out) / max(q["arrival_s"] for q in trace)
     return {"metric": "p50/p99 solve latency + MLUPS, continuous batching", "value": summ["mlups"],
             "unit": "MLUPS", "n_gpus": 1, "steps": None, "warmup": 1, "ms_per_step": None,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -186,6 +227,8 @@ def _bench_serve(args):
                                    f"{args.step_scale}, 200 GB admission budget, f32dev storage",
                        "requests": len(out), "step_scale": args.step_scale},
             "latency_s": {"p50": summ["p50_s"], "p99": summ["p99_s"], "max": summ["max_s"]},
+            "failed": summ["failed"],
+            "offered_load_mlups": offered / 1e6,
             "latency_p50_by_kind_s": {k: sorted(v)[len(v) // 2] for k, v in kinds.items()},
             "rounds": srv.rounds, "wall_s": wall}
 
@@ -328,6 +371,68 @@ def _bench_precision(args):
     return out
 
 
+def _bench_configs(args):
+    """The two smaller configurations at their full sizes and step counts:
+    the 32x8x8 three-species box (200 steps) and the 1024x64x1 nine-species
+    channel (5000 steps).  For each: GPU MLUPS in FP64 and FP32-deviation
+    storage with the step's fraction of the HBM roofline (algorithmic bytes
+    2 L 27 s per node), the FP32 against FP64 field errors at the end, and
+    the oracle's MLUPS on the host (the box in full; the channel on a prefix
+    bounded by --cpu-budget seconds)."""
+    import numpy as np
+    import torch
+    from threadpoolctl import threadpool_limits
+    from oracle import Oracle
+    from paper_2108_07605_amd import rlbm, workloads as wl
+    rows = {}
+    for name, case, steps in (("cfg1 abc_box 32x8x8 M=3", wl.make_case("abc_box"), 200),
+                              ("cfg2 channel2d 1024x64x1 M=9", wl.make_case("channel2d"), 5000)):
+        N = case["nx"] * case["ny"] * case["nz"]
+        M = case["mech"]["M"]
+        L = M + 1
+        row = {"nodes": N, "steps": steps, "species": M}
+        fields = {}
+        for st, sb in (("f64", 8), ("f32dev", 4)):
+            lat = rlbm.Lattice(case, storage=st).set_state()
+            lat.step(min(steps, 20))                  # warm-up, then the full run from a fresh state
+            lat.set_state()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(lat.stream)
+            lat.step(steps)
+            e1.record(lat.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            mlups = N / (ms * 1e-3) / 1e6
+            row[st] = {"mlups": mlups, "ms_per_step": ms,
+                       "frac_of_hbm_roofline": mlups * 1e6 * 2 * L * 27 * sb / (HBM_PEAK_GBS * 1e9),
+                       "status": lat.status()}
+            fields[st] = lat.fields()
+            lat.close()
+        th = float(np.mean(case["init"]["T"])) * case["mech"]["R_univ"] / 20.0
+        err = _field_errors(fields["f32dev"], fields["f64"], 1e-3 * th ** 0.5, (case["nx"], case["ny"], case["nz"]))
+        row["f32dev_vs_f64"] = {"Y_max": err["Y_max"], "T": err["T"], "u": err["u"]}
+        with threadpool_limits(limits=1):
+            o = Oracle(case)
+            t0 = time.perf_counter()
+            n = 0
+            while n < steps and (n == 0 or time.perf_counter() - t0 < args.cpu_budget):
+                o.step(1)
+                n += 1
+            dt = time.perf_counter() - t0
+        row["oracle"] = {"mlups": N * n / dt / 1e6, "steps": n, "cores": 1}
+        if n == steps:
+            of = o.fields()
+            e64 = _field_errors(fields["f64"], of, 1e-3 * th ** 0.5, (case["nx"], case["ny"], case["nz"]))
+            row["f64_vs_oracle"] = {"Y_max": e64["Y_max"], "T": e64["T"], "u": e64["u"]}
+        rows[name] = row
+    return {"metric": "MLUPS (all M+2 LBEs) + % HBM roofline, FP32-store vs FP64", "unit": "MLUPS",
+            "value": rows["cfg2 channel2d 1024x64x1 M=9"]["f32dev"]["mlups"], "n_gpus": 1,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": "configurations 1 and 2 at full size"},
+            "rows": rows, "host": _host()}
+
+
 def _copy_probe(mib):
     """A copy kernel of known size: 5 launches of an out-of-place elementwise
     copy reading and writing mib MiB each."""
@@ -353,18 +458,20 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--storage", default="both", choices=["both", "f32dev", "f64"])
     ap.add_argument("--workload", default="channel3d",
-                    choices=["channel3d", "tubes", "serve", "precision", "substeps", "coupling"],
+                    choices=["channel3d", "tubes", "serve", "precision", "substeps", "coupling", "configs"],
                     help="channel3d: the 512x64x64 channel (default); tubes: 256 uneven flame "
                          "tubes in batched launches vs one lattice at a time; serve: the "
                          "continuous-batching server on a Poisson request trace; precision: "
                          "FP32-deviation vs FP64 storage field errors after --steps steps; "
                          "substeps: step time with l = 1, 2, 4 reaction sub-steps; coupling: the "
-                         "weakly coupled storage (all M species lattices) vs the slaved one")
+                         "weakly coupled storage (all M species lattices) vs the slaved one; "
+                         "configs: the 32x8x8 box and the 1024x64x1 channel at full size in both "
+                         "storages, with the oracle's rate")
     ap.add_argument("--tubes", type=int, default=256)
     ap.add_argument("--seq-steps", type=int, default=20,
                     help="steps of the one-lattice-at-a-time comparison (tubes)")
     ap.add_argument("--requests", type=int, default=200)
-    ap.add_argument("--step-scale", type=float, default=0.05,
+    ap.add_argument("--step-scale", type=float, default=1.0,
                     help="scale of the trace's step budgets (serve)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates the "
@@ -395,6 +502,9 @@ def main():
     if args.workload == "coupling":
         print(json.dumps(_bench_coupling(args)))
         return
+    if args.workload == "configs":
+        print(json.dumps(_bench_configs(args)))
+        return
     case = wl.make_case("channel3d", nx=args.nx, ny=args.ny, nz=args.nz)
     N = case["nx"] * case["ny"] * case["nz"]
     M = case["mech"]["M"]
@@ -424,6 +534,7 @@ def main():
                          "traffic": traffic,
                          "kernel": "k_" + coll_name, "alg_bytes_per_node": bytes_node},
             "step_frac_of_hbm_roofline": mlups * 1e6 * bytes_node / (HBM_PEAK_GBS * 1e9),
+            "step_roofline": _step_roofline(st, case, N, bytes_node, ms_step),
         }
     main_st = storages[0]
     m = res[main_st]
@@ -445,6 +556,7 @@ def main():
                                f"flux inlet, LODI outlet, {main_st} storage",
                    "nodes": N, "storage": main_st, "species": M, "substeps": case["substeps"]},
         "roofline": m["roofline"],
+        "step_roofline": m["step_roofline"],
         "storages": res,
     }
     if not args.no_cpu_baseline:

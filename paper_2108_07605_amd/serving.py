@@ -133,9 +133,10 @@ class Server:
         return [min(a[2], max(self.min_chunk, min(self.max_chunk, int(share / a[0].nodes))))
                 for a in active]
 
-    def run(self, requests):
+    def run(self, requests, on_done=None):
         """Serve `requests` (arrival times relative to the start); returns them
-        with admitted/done times and results filled in."""
+        with admitted/done times and results filled in.  on_done(request), if
+        given, is called as each request completes or fails."""
         queue = sorted(requests, key=lambda r: (r.arrival, r.rid))
         for r in queue:
             r.nodes = int(r.case["nx"]) * int(r.case["ny"]) * int(r.case["nz"])
@@ -158,6 +159,8 @@ class Server:
                 except Exception as e:          # the request fails, the server goes on
                     r.error = f"create: {e}"
                     r.done = self.clock() - t0
+                    if on_done:
+                        on_done(r)
                     continue
                 r.admitted = self.clock() - t0
                 used += r.nbytes
@@ -196,6 +199,8 @@ class Server:
                 r.done = self.clock() - t0
                 self.backend.release(lat)
                 used -= r.nbytes
+                if on_done:
+                    on_done(r)
             active = keep
         return queue
 

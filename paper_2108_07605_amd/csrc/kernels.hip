@@ -1205,11 +1205,15 @@ __device__ __forceinline__ double eq_value(MechC mc, const EqState<M, SPV>& e, i
 // ordered by node within a type, so mostly a run of a wall row or plane),
 // one lane per node, and one wave per stored lattice: every population load
 // and store of a wave is coalesced and its lattice, with the lattice's
-// constants, is the same for the whole wave.  The node's state goes between
-// the waves through LDS: the lattices' moments, and the imposed and local
-// states that the first wave forms from them (temperature by the bounded
-// Newton iteration, the LODI outlet state).  All barriers are at the top
-// level of the kernel, so every wave meets all of them.
+// constants, is the same for the whole wave.  Each wave loads its lattice's
+// populations once, in one pass with all 27 loads in flight, and keeps them
+// in LDS for the moments and the reconstruction (the pull reads of the
+// interface list are scattered over the lattice, so a second pass over them
+// costs as much as the first).  The node's state goes between the waves
+// through LDS: the lattices' moments, and the imposed and local states that
+// the first wave forms from them (temperature by the bounded Newton
+// iteration, the LODI outlet state).  All barriers are at the top level of
+// the kernel, so every wave meets all of them.
 // ---------------------------------------------------------------------------
 static_assert(BC_NODES == 64, "one lane per node in a wave");
 
@@ -1297,6 +1301,17 @@ __device__ __forceinline__ void for_q(F&& f) {
 template <int M, int W>
 constexpr int bc_threads() { return BC_NODES * Lat<M, W>::NL; }
 
+// How many of a block's lattices keep their advected populations (27 * 64
+// stored values each) in LDS beside the node states and moments, within the
+// 160 KB of LDS per CU on gfx950.
+template <int M, typename S, int W>
+constexpr int bc_stash() {
+    constexpr int NL = Lat<M, W>::NL;
+    constexpr long state = (long)(NL * 4 + 3 * (ST_Y + M)) * BC_NODES * (long)sizeof(double) + BC_NODES * 4L;
+    constexpr long n = (160L * 1024 - state) / ((long)Q * BC_NODES * (long)sizeof(S));
+    return n < 0 ? 0 : (n < NL ? (int)n : NL);
+}
+
 template <int M, typename S, int W>
 __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
     const LatDev* __restrict__ lats, const int* __restrict__ blk, int n_lat, const long long* __restrict__ tp,
@@ -1307,6 +1322,12 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
     __shared__ double stL[ST_Y + M][BC_NODES];          // local state
     __shared__ double stT[ST_Y + M][BC_NODES];          // the full inlet's target
     __shared__ int flg[BC_NODES];
+    // the advected populations of the first NS lattices as stored, loaded
+    // once and read by all three passes (NS = NL where they fit beside the
+    // state; one block per CU runs anyway, as the kernel's registers allow no
+    // second one)
+    constexpr int NS = bc_stash<M, S, W>();
+    __shared__ S stash[NS > 0 ? NS : 1][Q][BC_NODES];
     const long long t = step_time(tp, toff);
     const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
@@ -1369,6 +1390,19 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
         }
         return v;
     };
+    const bool stashed = NS == NL || l < NS;   // wave-uniform
+    // the advected population (l, i), from the stash where there is one
+    auto adv = [&](auto ic) -> double {
+        if (NS > 0 && stashed) {
+            constexpr int i = decltype(ic)::value;
+            double v = (double)stash[l][i][lane];
+            if constexpr (sizeof(S) == 4)
+                v += l == LG ? ref_g(sl, sf, G[l * Q + i], G[REF_K<NL> + i]) : ref_of(sl, G[l * Q + i]);
+            return v;
+        } else {
+            return pop(ic, false);
+        }
+    };
     auto put = [&](auto ic, double v) {
         constexpr int i = decltype(ic)::value;
         if (!live) return;
@@ -1387,6 +1421,47 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
     // zeroth moments with the bounce-back sources on D.
     if (bback) {
         for_q<0>([&](auto ic) { put(ic, pop(ic, true)); });
+    } else if (NS > 0 && stashed) {
+        // one pass of loads, every one issued before the first store to LDS:
+        // the advected populations of outgoing links and, at a TMS wall, the
+        // bounce-back sources of incoming ones (species and momentum); any
+        // other incoming link loads this node's own slot, an in-range
+        // stand-in that no pass reads
+        const bool tms = wall && l <= LF;
+        S raw[Q];
+        float sbv[Q];
+        for_q<0>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i), io = Q - 1 - i;
+            const int off = node + sel3(c0, o.x[0], 0, o.x[2]) + sel3(c1, o.y[0], 0, o.y[2]) +
+                            sel3(c2, o.z[0], 0, o.z[2]);
+            const bool in = (Dm >> i) & 1u;
+            const RLBM_GLOBAL S* pi = src + (size_t)(l * Q + i) * N;
+            const RLBM_GLOBAL S* pio = src + (size_t)(l * Q + io) * N;
+            raw[i] = ld_at(tms && in ? pio : pi, in ? node : off);
+            if constexpr (sizeof(S) == 4) {
+                sbv[i] = 0.0f;
+                if (tms && in) sbv[i] = scale_at(L, par, off)[l];   // the reader's scale
+            }
+        });
+        for_q<0>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            stash[l][i][lane] = raw[i];
+        });
+        if (tms) {
+            // TMS wall (section 4.2.2): the bounce-back densities (eqs.
+            // BBrho, BBY), zeroth moments with the bounce-back sources on D
+            double m0 = 0.0;
+            for_q<0>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int io = Q - 1 - i;
+                double v = (double)raw[i];
+                if constexpr (sizeof(S) == 4)
+                    v += ((Dm >> i) & 1u) ? ref_of(sbv[i], G[l * Q + io]) : ref_of(sl, G[l * Q + i]);
+                m0 += v;
+            });
+            mom[l][0][lane] = m0;
+        }
     } else if (wall && l <= LF) {
         double m0 = 0.0;
         for_q<0>([&](auto ic) { m0 += pop(ic, true); });
@@ -1492,7 +1567,7 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
             constexpr int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);
             double v;
             if ((Dm >> i) & 1u) v = lat_eq<c0, c1, c2>(eA);
-            else v = pop(ic, false);
+            else v = adv(ic);
             m0 += v;
             if (c0) m1 += c0 > 0 ? v : -v;
             if (c1) m2 += c1 > 0 ? v : -v;
@@ -1572,7 +1647,7 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
                 constexpr int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);
                 double fi;
                 if ((Dm >> i) & 1u) fi = lat_eq<c0, c1, c2>(eA);
-                else fi = pop(ic, false);
+                else fi = adv(ic);
                 put(ic, lat_eq<c0, c1, c2>(eT) + fi - lat_eq<c0, c1, c2>(eL));
             });
         } else {
@@ -1585,7 +1660,7 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
                 const double ea = lat_eq<c0, c1, c2>(eA), el = lat_eq<c0, c1, c2>(eL);
                 double fi;
                 if ((Dm >> i) & 1u) fi = ea;
-                else fi = pop(ic, false);
+                else fi = adv(ic);
                 put(ic, ea + fi - el);
             });
         }

@@ -1275,7 +1275,7 @@ __device__ __forceinline__ void state_store(MechC mc0, double (*st)[BC_NODES], i
 // the wall's local state, eq. locua), the others the mixture velocity.
 template <int M, int W>
 __device__ __forceinline__ void lat_prepare(MechC mc0, const double (*st)[BC_NODES], int lane, int l, int slaved,
-                                            const double* w, LatEq& q) {
+                                            bool spv, const double (&w)[3], LatEq& q) {
     constexpr int LF = Lat<M, W>::LF, LG = Lat<M, W>::LG;
     reload_barrier();
     MechC mc = in_loop(mc0);
@@ -1286,7 +1286,7 @@ __device__ __forceinline__ void lat_prepare(MechC mc0, const double (*st)[BC_NOD
     q.s = sp ? rho * st[ST_Y + a][lane] : rho;
     q.U = lg ? st[ST_U][lane] : 1.0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) eq_axis(sp && w ? w[d] : st[ST_V + d][lane], th, lg, q.W[d], q.k[d]);
+    for (int d = 0; d < 3; ++d) eq_axis(sp && spv ? w[d] : st[ST_V + d][lane], th, lg, q.W[d], q.k[d]);
 }
 
 // Compile-time loop over the 27 velocities.
@@ -1329,7 +1329,13 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
     constexpr int NS = bc_stash<M, S, W>();
     __shared__ S stash[NS > 0 ? NS : 1][Q][BC_NODES];
     const long long t = step_time(tp, toff);
-    const int b = xcd_block();
+    // tiles in reverse list order, without the XCD remap: the list is sorted
+    // by boundary type and starts with the TMS walls (the cheapest entries),
+    // so the costlier inlet, outlet and bounce-back tiles start first and
+    // wall tiles fill the tail; and consecutive tiles go to different XCDs,
+    // so every XCD gets a share of each kind (L2 sharing between neighbouring
+    // tiles matters little here)
+    const int b = (int)(gridDim.x - 1 - blockIdx.x);
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
     if (t >= L.t_end) return;                       // the whole block
@@ -1356,6 +1362,7 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
     const bool outlet = type == RLBM_FACE_OUTLET;
     const bool inlet_full = type == RLBM_FACE_INLET;
     const RLBM_CONST double* G = as_const(L.ref);
+    const double zero3[3] = {0.0, 0.0, 0.0};
     if (l == 0) flg[lane] = 0;
 
     // FP32 deviation storage: references belong to the node that reads a
@@ -1560,7 +1567,7 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
     // inlet and outlet counterparts)
     LatEq eA;
     if (!bback) {
-        lat_prepare<M, W>(mc0, stA, lane, l, s, nullptr, eA);
+        lat_prepare<M, W>(mc0, stA, lane, l, s, false, zero3, eA);
         double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
         for_q<0>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
@@ -1619,18 +1626,17 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
     if (!bback) {
         // the wall's local species equilibria take the species' own velocity
         // u_a = j_a / rho_a (u where rho_a <= 1e-14 rho, eq. locua)
-        double w[3];
-        const double* wp = nullptr;
-        if (wall && l < LF) {
+        double w[3] = {0.0, 0.0, 0.0};
+        const bool spv = wall && l < LF;
+        if (spv) {
             const double ra = mom[l][0][lane];
             const bool small = ra <= 1e-14 * stL[ST_RHO][lane];
             const double ir = small ? 0.0 : 1.0 / ra;
 #pragma unroll
             for (int d = 0; d < 3; ++d) w[d] = small ? stL[ST_V + d][lane] : mom[l][1 + d][lane] * ir;
-            wp = w;
         }
         LatEq eL;
-        lat_prepare<M, W>(mc0, stL, lane, l, s, wp, eL);
+        lat_prepare<M, W>(mc0, stL, lane, l, s, spv, w, eL);
         if (type == RLBM_FACE_INLET_LOCAL) {
             // the simplified inlet: every population at the local equilibria
             // (eqs. in_loc_*)
@@ -1641,7 +1647,7 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
         } else if (inlet_full) {
             // eqs. f_inlet, g_inlet, fa_inlet
             LatEq eT;
-            lat_prepare<M, W>(mc0, stT, lane, l, s, nullptr, eT);
+            lat_prepare<M, W>(mc0, stT, lane, l, s, false, zero3, eT);
             for_q<0>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 constexpr int c0 = cx_of(i), c1 = cy_of(i), c2 = cz_of(i);

@@ -1047,6 +1047,11 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
             const RLBM_CONST double* Ra = slotc;
             const RLBM_CONST double* Ks = slotc + M;
             const RLBM_CONST double* ref = as_const(L.ref) + opaque_zero();
+            // scales of the node that reads what this velocity writes (L2 hits,
+            // consumed after the species work below), issued before the
+            // prefetch so that waiting for them leaves the prefetch in flight
+            float srd[NS];
+            if constexpr (sizeof(S) == 4) load_scales(par ^ 1, reader(c0, c1, c2), srd);
             // prefetch the next velocity of this thread
             S fnx[NL];
             if constexpr (c0 < 1) {
@@ -1054,10 +1059,6 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
             } else {
                 if (c1 < 1) load(i + 1, offyz + sel3(c1 + 1, o.y[0], 0, o.y[2]) - sel3(c1, o.y[0], 0, o.y[2]) + o.x[0], fnx);
             }
-            // scales of the node that reads what this velocity writes (L2 hits,
-            // consumed after the species work below)
-            float srd[NS];
-            if constexpr (sizeof(S) == 4) load_scales(par ^ 1, reader(c0, c1, c2), srd);
             const double T = sp[PRM_T][lane], ux = sp[PRM_U][lane];
             double D[M];
 #pragma unroll

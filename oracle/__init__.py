@@ -22,9 +22,11 @@ Modules
     boundary   TMS wall, flux inlet and LODI outlet (section 4)
     solver     the time step and read-out
 
-Parity unpinned: the corner rule (a node on several non-periodic faces takes
-the union of their incoming links, walls first) has no independent check;
-the synthetic thermo, transport and mechanism laws are inputs, not method.
-Every other part is pinned in tests/test_oracle_pins.py.
+Parity unpinned: which boundary a node on faces of different kinds follows
+(a wall face before an inlet or outlet face, a TMS face before a
+bounce-back one) has no independent check; the synthetic thermo, transport
+and mechanism laws are inputs, not method.  Every other part is pinned in
+tests/test_oracle_pins.py, the union of incoming links at edges and corners
+by causality in a box closed by walls.
 """
 from .solver import Oracle  # noqa: F401

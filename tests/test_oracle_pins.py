@@ -653,6 +653,58 @@ def test_closed_tms_box_conserves_mass():
         assert abs(inv1[k] - inv0[k]) <= 1e-13 * abs(inv0[k])
 
 
+def _closed_box(nx, ny, nz, wall_type):
+    mech = wl.mechanism_abc()
+    case = wl.make_case("abc_box", nx=nx, ny=ny, nz=nz, mech=mech, perturb=False)
+    if wall_type == "wall":
+        face = {"type": "wall", "T_lo": 1000.0, "T_hi": 1000.0, "x0": 0.0, "width": 1.0}
+    else:
+        face = {"type": "bounceback"}
+    case["faces"] = [dict(face) for _ in range(6)]
+    return case
+
+
+@pytest.mark.parametrize("wall_type", ["wall", "bounceback"])
+def test_box_corners_keep_information_local(wall_type):
+    """Corner rule (a node on several walls takes the union of their
+    incoming links), pinned by causality: a population moves one node per
+    step and the same-time gradients reach one node further, so after k
+    steps a disturbance at one corner of a box closed by walls can only
+    have reached nodes within 2k + 1 of it.  Were an edge or corner node to
+    pull one of its outside links periodically instead (the links of one of
+    its faces only, or only the links common to all of them), the far side
+    of the box would see the disturbance at once."""
+    nx, ny, nz = 12, 10, 8
+    case = _closed_box(nx, ny, nz, wall_type)
+    pert = _closed_box(nx, ny, nz, wall_type)
+    init = {k: np.array(v, dtype=float) for k, v in pert["init"].items()}
+    init["T"][0] *= 1.02                      # node (0, 0, 0)
+    init["Y"][0, 0] *= 1.2
+    init["Y"][1, 0] = 1.0 - init["Y"][0, 0] - init["Y"][2, 0]
+    init["u"][:, 0] = [0.01, 0.02, -0.01]
+    pert["init"] = init
+    a, b = Oracle(case), Oracle(pert)
+    k = 3
+    a.step(k)
+    b.step(k)
+    fa, fb = a.fields(), b.fields()
+    x = np.arange(nx * ny * nz) % nx
+    y = (np.arange(nx * ny * nz) // nx) % ny
+    z = np.arange(nx * ny * nz) // (nx * ny)
+    far = np.maximum(np.maximum(x, y), z) > 2 * k + 1
+    near = np.maximum(np.maximum(x, y), z) <= 1
+    # far away only the last bits may differ: the temperature iteration runs
+    # over a set of nodes until all of them have converged, so one slow node
+    # adds an iteration (a change at round-off) everywhere in the set; a
+    # population pulled across the box would carry the disturbance itself
+    for key in ("rho", "T"):
+        scale = np.abs(fa[key]).max()
+        assert np.abs(fb[key][near] - fa[key][near]).max() > 1e-6 * scale   # it moved
+        assert np.abs(fb[key][far] - fa[key][far]).max() <= 1e-14 * scale, key
+    assert np.abs(fb["Y"][:, far] - fa["Y"][:, far]).max() <= 1e-14
+    assert np.abs(fb["u"][:, far] - fa["u"][:, far]).max() <= 1e-15   # lattice units; the kick is 1e-2
+
+
 def test_bounce_back_box_conserves_mass_energy_and_elements(mech9):
     """Bounce-back (section 4.2.1, eq. bb) hands every post-collision
     population that would leave the domain back to its own node: a duct

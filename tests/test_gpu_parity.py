@@ -79,6 +79,29 @@ def test_abc_box_parity(storage):
         _compare_fields(gf, of, TOL64, _u_floor(case))
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+@pytest.mark.parametrize("wall_type", ["wall", "bounceback"])
+def test_closed_box_corners_parity(wall_type, storage):
+    """A box closed by walls on all six faces (edges on two walls, corners
+    on three, with 15 and 19 incoming links), TMS or bounce-back, against
+    the oracle."""
+    print(f"case closed box 10x8x6 M=3 {wall_type} {storage}", flush=True)
+    case = wl.make_case("abc_box", nx=10, ny=8, nz=6, mech=wl.mechanism_abc())
+    if wall_type == "wall":
+        face = {"type": "wall", "T_lo": 1000.0, "T_hi": 1000.0, "x0": 0.0, "width": 1.0}
+    else:
+        face = {"type": "bounceback"}
+    case["faces"] = [dict(face) for _ in range(6)]
+    lat, ora, out = _run_pair(case, [1, 20], storage=storage)
+    for gp, op, gf, of in out:
+        if storage == "f64":
+            _compare_pops(gp, op, TOL64)
+            _compare_fields(gf, of, TOL64, _u_floor(case))
+        else:
+            assert _nerr(gf["T"], of["T"]) <= TOL32
+            assert max(_nerr(gf["Y"][a], of["Y"][a], 1e-6) for a in range(3)) <= TOL32
+
+
 def test_abc_box_initial_state_exact():
     rlbm = _gpu()
     case = wl.make_case("abc_box")

@@ -181,14 +181,14 @@ __device__ __forceinline__ double sel3d(int c, double m, double z, double p) { r
 // storage) stores every species at its own index.
 __device__ __forceinline__ int lat_of(int a, int slaved) { return a - (a > slaved ? 1 : 0); }
 
-// Per-thread LDS columns of k_local (stride 256 doubles between rows): the
+// Per-thread LDS columns of k_local (stride LOC_T doubles between rows): the
 // species densities rho_a [M] and velocity differences u_a - u [3 M], handed
 // from the streaming part to the Stefan-Maxwell step without a trip to memory.
 struct LocalLds {
     double* ra;   // &rho_a[0][tid]
     double* dv;   // &(u_a - u)[0][tid], row 3 a + d
 };
-constexpr int LOC_T = 256;   // k_local threads per block
+constexpr int LOC_T = NODE_TILE;   // k_local threads per block
 
 // ---------------------------------------------------------------------------
 // Stefan-Maxwell diffusion velocities (section 2.3, eq. transform1)
@@ -488,14 +488,14 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
 }
 
 template <int M, typename S, int W>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_local(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+__global__ __launch_bounds__(NODE_TILE) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_local(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                                int n_lat, const long long* __restrict__ tp, long long toff) {
     const long long t = step_time(tp, toff);
     const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
     if (t >= L.t_end) return;
-    const int node = (b - blk[lj]) * 256 + threadIdx.x;
+    const int node = (b - blk[lj]) * NODE_TILE + threadIdx.x;
     if (node >= L.N) return;
     MechC mc = *as_const(L.mech);
     const int par = (L.parity0 + t) & 1;
@@ -695,14 +695,14 @@ __device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const
     const LatDev& L = lats[lj];
     if (t >= L.t_end) return;
     if ((L.reaction == RLBM_REACTION_LINEARLY_IMPLICIT) != IMPL) return;
-    const int node = (b - blk[lj]) * 256 + threadIdx.x;
+    const int node = (b - blk[lj]) * NODE_TILE + threadIdx.x;
     if (node >= L.N) return;
     if constexpr (IMPL) {
         MechC mc = *as_const(L.mech);
         double* prm = L.prm;
         const size_t N = (size_t)L.N;
-        __shared__ double s_c[M][256], s_g[M][256], s_q[M][256];
-        const ChemLds<256> ls{&s_c[0][threadIdx.x], &s_g[0][threadIdx.x], &s_q[0][threadIdx.x]};
+        __shared__ double s_c[M][NODE_TILE], s_g[M][NODE_TILE], s_q[M][NODE_TILE];
+        const ChemLds<NODE_TILE> ls{&s_c[0][threadIdx.x], &s_g[0][threadIdx.x], &s_q[0][threadIdx.x]};
         double rho_a[M], fin[M];
 #pragma unroll
         for (int a = 0; a < M; ++a) rho_a[a] = prm[(PRM_SP + 6 * a) * N + node];
@@ -717,7 +717,7 @@ __device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const
         const double U = prm[PRM_UINT * N + node];
         const double T = prm[PRM_T * N + node];
         int fail = 0;
-        reaction_increment<M, 256, true>(mc, rho_a, rho, U, T, L.substeps, ls, fin, &fail);
+        reaction_increment<M, NODE_TILE, true>(mc, rho_a, rho, U, T, L.substeps, ls, fin, &fail);
         if (fail) atomicOr(L.flag, 1);
         // Delta rho_a against the densities read again, so that they need not
         // stay in registers through the sub-steps
@@ -736,14 +736,14 @@ __device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const
 }
 
 template <int M>
-__global__ __launch_bounds__(256) void k_gradients(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+__global__ __launch_bounds__(NODE_TILE) void k_gradients(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                                    int n_lat, const long long* __restrict__ tp, long long toff) {
     chem_body<M, false>(lats, blk, n_lat, tp, toff);
 }
 
 // The linearly implicit variant holds an (M-1)^2 matrix in registers.
 template <int M>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_chem_implicit(
+__global__ __launch_bounds__(NODE_TILE) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_chem_implicit(
     const LatDev* __restrict__ lats, const int* __restrict__ blk, int n_lat, const long long* __restrict__ tp, long long toff) {
     chem_body<M, true>(lats, blk, n_lat, tp, toff);
 }
@@ -2090,14 +2090,14 @@ static hipError_t launch_step_phase(int phase, int M, int weak, const StepLaunch
         RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_boundary<MM, S, WW>), dim3(a.blocks), dim3(bc_threads<MM, WW>()), 0,
                                                     a.stream, a.lats, a.blk, a.n_lat, a.tp, a.toff))
     } else if (phase == 1) {
-        RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_local<MM, S, WW>), dim3(a.blocks), dim3(256), 0, a.stream,
+        RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_local<MM, S, WW>), dim3(a.blocks), dim3(NODE_TILE), 0, a.stream,
                                                     a.lats, a.blk, a.n_lat, a.tp, a.toff))
     } else if (phase == 2) {
         if (a.schemes & (1u << RLBM_REACTION_EXPLICIT))
-            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_gradients<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
+            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_gradients<MM>), dim3(a.blocks), dim3(NODE_TILE), 0, a.stream, a.lats,
                                                     a.blk, a.n_lat, a.tp, a.toff))
         if (a.schemes & (1u << RLBM_REACTION_LINEARLY_IMPLICIT))
-            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem_implicit<MM>), dim3(a.blocks), dim3(256), 0, a.stream, a.lats,
+            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem_implicit<MM>), dim3(a.blocks), dim3(NODE_TILE), 0, a.stream, a.lats,
                                                     a.blk, a.n_lat, a.tp, a.toff))
     } else {
         RLBM_DISPATCH_W(M, weak, hipLaunchKernelGGL((k_update<MM, S, WW>), dim3(a.blocks), dim3(UPD_THREADS), 0,

@@ -22,10 +22,16 @@ struct StepLaunch {
 // Interface nodes per boundary block (one wave, one lane per node).
 constexpr int BC_NODES = 64;
 
+// Nodes per block of the moments and gradient phases, one thread per node.
+#ifndef RLBM_NODE_TILE
+#define RLBM_NODE_TILE 64
+#endif
+constexpr int NODE_TILE = RLBM_NODE_TILE;
+
 // phase 0: boundary (BC_NODES interface nodes per block); phases 1 and 2:
 // moments, diffusion and forward-Euler chemistry, then gradients (with the
-// linearly implicit chemistry first where selected) (256-thread blocks over
-// nodes); phase 3: update (one block per 64 nodes).
+// linearly implicit chemistry first where selected) (NODE_TILE-thread blocks
+// over nodes); phase 3: update (one block per 64 nodes).
 hipError_t launch_phase(int phase, int M, int storage, int weak, const StepLaunch& a);
 // weak: the weakly coupled storage (all M species lattices, no slaved species)
 hipError_t launch_init(int M, int storage, int weak, const LatDev* lat, long long N, const double* rho,

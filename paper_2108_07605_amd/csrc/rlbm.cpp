@@ -455,7 +455,7 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     lat->d_ref = (double*)(base + p.off_ref);
     lat->d_partial = (double*)(base + p.off_partial);
     lat->d_invout = (double*)(base + p.off_invout);
-    const int nb_nodes = (int)((g.N + 255) / 256);
+    const int nb_nodes = (int)((g.N + NODE_TILE - 1) / NODE_TILE);
     const int nb_if = (int)((nif + BC_NODES - 1) / BC_NODES);
     const int nb64 = (int)((g.N + 63) / 64);
     const int blk[6] = {0, nb_nodes, 0, nb_if, 0, nb64};
@@ -598,7 +598,7 @@ int rlbm_set_state(rlbm_lattice* lat, const double* rho, const double* u, const 
 }
 
 static int step_one(rlbm_lattice* lat, long long t) {
-    const int nb_nodes = (int)((lat->geo.N + 255) / 256);
+    const int nb_nodes = (int)((lat->geo.N + NODE_TILE - 1) / NODE_TILE);
     const int nb_if = (int)((lat->geo.if_node.size() + BC_NODES - 1) / BC_NODES);
     const int nb64 = (int)((lat->geo.N + 63) / 64);
     for (int phase = 0; phase < NPHASE; ++phase) {
@@ -1056,7 +1056,7 @@ int rlbm_batch_create(rlbm_lattice* const* lats, int32_t k, void* dev_mem, size_
     for (int j = 0; j < k; ++j) {
         const rlbm_lattice* lat = lats[j];
         b->schemes |= 1u << lat->host.reaction;
-        b->host_blk[j + 1] = b->host_blk[j] + (int)((lat->geo.N + 255) / 256);
+        b->host_blk[j + 1] = b->host_blk[j] + (int)((lat->geo.N + NODE_TILE - 1) / NODE_TILE);
         b->host_blk[(k + 1) + j + 1] =
             b->host_blk[(k + 1) + j] + (int)((lat->geo.if_node.size() + BC_NODES - 1) / BC_NODES);
         b->host_blk[2 * (k + 1) + j + 1] = b->host_blk[2 * (k + 1) + j] + (int)((lat->geo.N + 63) / 64);
@@ -1180,7 +1180,7 @@ int rlbm_step_group(rlbm_lattice* const* lats, int32_t k, const int64_t* steps) 
             c.t_end[j] = steps[base + j];
             c.parity[j] = (int)((lat->host.parity0 + lat->steps_done) & 1);
             schemes |= 1u << lat->host.reaction;
-            pre[0] += (int)((lat->geo.N + 255) / 256);
+            pre[0] += (int)((lat->geo.N + NODE_TILE - 1) / NODE_TILE);
             pre[1] += (int)((lat->geo.if_node.size() + BC_NODES - 1) / BC_NODES);
             pre[2] += (int)((lat->geo.N + 63) / 64);
         }

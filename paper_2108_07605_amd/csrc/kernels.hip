@@ -688,14 +688,13 @@ __device__ __forceinline__ void node_gradients(const LatDev& L, int node) {
 // ---------------------------------------------------------------------------
 template <int M, bool IMPL>
 __device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const int* __restrict__ blk, int n_lat,
-                                          const long long* __restrict__ tp, long long toff) {
+                                          const long long* __restrict__ tp, long long toff, int b, int tid) {
     const long long t = step_time(tp, toff);
-    const int b = xcd_block();
     const int lj = find_lattice(blk, n_lat, b);
     const LatDev& L = lats[lj];
     if (t >= L.t_end) return;
     if ((L.reaction == RLBM_REACTION_LINEARLY_IMPLICIT) != IMPL) return;
-    const int node = (b - blk[lj]) * NODE_TILE + threadIdx.x;
+    const int node = (b - blk[lj]) * NODE_TILE + tid;
     if (node >= L.N) return;
     if constexpr (IMPL) {
         MechC mc = *as_const(L.mech);
@@ -735,17 +734,25 @@ __device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const
     node_gradients<M>(L, node);
 }
 
+// GRAD_TILES tiles per block, one wave each (the stencil shares nothing
+// between waves): the lattice of each tile is looked up per wave, and tiles
+// past the end of the list return.
+constexpr int GRAD_TILES = 4;
+static_assert(NODE_TILE == 64, "one wave per tile");
 template <int M>
-__global__ __launch_bounds__(NODE_TILE) void k_gradients(const LatDev* __restrict__ lats, const int* __restrict__ blk,
-                                                   int n_lat, const long long* __restrict__ tp, long long toff) {
-    chem_body<M, false>(lats, blk, n_lat, tp, toff);
+__global__ __launch_bounds__(GRAD_TILES * NODE_TILE) void k_gradients(const LatDev* __restrict__ lats,
+                                                                      const int* __restrict__ blk, int n_lat,
+                                                                      const long long* __restrict__ tp, long long toff) {
+    const int tile = xcd_block() * GRAD_TILES + __builtin_amdgcn_readfirstlane((int)threadIdx.x / NODE_TILE);
+    if (tile >= blk[n_lat]) return;
+    chem_body<M, false>(lats, blk, n_lat, tp, toff, tile, (int)threadIdx.x % NODE_TILE);
 }
 
 // The linearly implicit variant holds an (M-1)^2 matrix in registers.
 template <int M>
 __global__ __launch_bounds__(NODE_TILE) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_chem_implicit(
     const LatDev* __restrict__ lats, const int* __restrict__ blk, int n_lat, const long long* __restrict__ tp, long long toff) {
-    chem_body<M, true>(lats, blk, n_lat, tp, toff);
+    chem_body<M, true>(lats, blk, n_lat, tp, toff, xcd_block(), (int)threadIdx.x);
 }
 
 
@@ -2094,7 +2101,7 @@ static hipError_t launch_step_phase(int phase, int M, int weak, const StepLaunch
                                                     a.lats, a.blk, a.n_lat, a.tp, a.toff))
     } else if (phase == 2) {
         if (a.schemes & (1u << RLBM_REACTION_EXPLICIT))
-            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_gradients<MM>), dim3(a.blocks), dim3(NODE_TILE), 0, a.stream, a.lats,
+            RLBM_DISPATCH(M, hipLaunchKernelGGL((k_gradients<MM>), dim3((a.blocks + GRAD_TILES - 1) / GRAD_TILES), dim3(GRAD_TILES * NODE_TILE), 0, a.stream, a.lats,
                                                     a.blk, a.n_lat, a.tp, a.toff))
         if (a.schemes & (1u << RLBM_REACTION_LINEARLY_IMPLICIT))
             RLBM_DISPATCH(M, hipLaunchKernelGGL((k_chem_implicit<MM>), dim3(a.blocks), dim3(NODE_TILE), 0, a.stream, a.lats,

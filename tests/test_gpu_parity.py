@@ -102,6 +102,26 @@ def test_closed_box_corners_parity(wall_type, storage):
             assert max(_nerr(gf["Y"][a], of["Y"][a], 1e-6) for a in range(3)) <= TOL32
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
+def test_bounce_back_channel_with_inlet_and_outlet_parity(mech9, storage):
+    """A 2D channel whose y walls are bounce-back walls, with the flux inlet
+    and the LODI outlet: the bounce-back kernel path beside inlet and outlet
+    tiles, and the edge nodes where a bounce-back face meets the inlet and
+    outlet faces (the wall is taken there)."""
+    print(f"case channel2d 40x10 bounce-back walls {storage}", flush=True)
+    case = wl.make_case("channel2d", nx=40, ny=10, nz=1, mech=mech9)
+    for f in (2, 3):
+        case["faces"][f] = {"type": "bounceback"}
+    lat, ora, out = _run_pair(case, [1, 40], storage=storage)
+    for gp, op, gf, of in out:
+        if storage == "f64":
+            _compare_pops(gp, op, TOL64)
+            _compare_fields(gf, of, TOL64, _u_floor(case))
+        else:
+            assert _nerr(gf["T"], of["T"]) <= TOL32
+            assert max(_nerr(gf["Y"][a], of["Y"][a], 1e-6) for a in range(of["Y"].shape[0])) <= TOL32
+
+
 def test_abc_box_initial_state_exact():
     rlbm = _gpu()
     case = wl.make_case("abc_box")

@@ -152,7 +152,8 @@ typedef struct rlbm_face {
 
 typedef struct rlbm_lattice_desc {
     int32_t nx, ny, nz;           /* >= 1 each, >= 2 along an axis with an inlet/outlet; N = nx ny nz
-                                     with 9 N s < 2^32 for s = 4 (FP32) or 8 (FP64) bytes */
+                                     with 9 (N + n_if) s < 2^32 for s = 4 (FP32) or 8 (FP64) bytes,
+                                     n_if the number of interface nodes (RLBM_EUNSUP otherwise) */
     rlbm_face faces[6];
     int32_t storage;              /* RLBM_STORAGE_* */
     int32_t substeps;             /* reaction sub-steps l >= 1 (eq. R3) */

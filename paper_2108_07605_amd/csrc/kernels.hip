@@ -358,27 +358,24 @@ __device__ __forceinline__ S ld_win(const RLBM_GLOBAL S* win, unsigned plane, in
 // The moment sums of k_local.  IF = false: no lane of the wave is an
 // interface node and every population is pulled from the source buffer;
 // IF = true: interface lanes read their reconstructed populations from the
-// boundary buffer instead.
+// planes' interface slots instead.
 template <int M, typename S, int W, bool IF>
 __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, int node, const PullOff& o,
                                               const LocalLds& ls, LocalMoments<M>& m) {
     constexpr int NSP = Lat<M, W>::NSP, LF = Lat<M, W>::LF, LG = Lat<M, W>::LG, NL = Lat<M, W>::NL;
     const size_t N = (size_t)L.N;
-    const int nif = L.n_if;
     const int s = W ? M : L.slaved;
     const RLBM_GLOBAL S* src = as_global(static_cast<const S*>(L.pop[par]));
-    const RLBM_GLOBAL S* bc = as_global(static_cast<const S*>(L.bcbuf));
     RLBM_GLOBAL double* prm = as_global(L.prm);
     auto off_of = [&](int i) { return node + o.x[cx_of(i) + 1] + o.y[cy_of(i) + 1] + o.z[cz_of(i) + 1]; };
-    const unsigned nb = plane_bytes(L.N, sizeof(S));
+    const size_t P = (size_t)L.P;
+    const unsigned nb = plane_bytes(L.P, sizeof(S));
+    // an interface lane reads its post-boundary population from the plane's
+    // interface slot N + k instead of its pull source: the same load with
+    // another index
     auto ld = [&](int l, int i) -> S {
-        const int li = l * Q + i;
-        if constexpr (!IF) {
-            return ld_win(src + (size_t)(l * Q + 9 * (i / 9)) * N, nb, i % 9, off_of(i));
-        } else {
-            if (k >= 0) return ld_at(bc + (size_t)li * nif, k);
-            return ld_at(src + (size_t)li * N, off_of(i));
-        }
+        const int idx = IF ? (k >= 0 ? (int)N + k : off_of(i)) : off_of(i);
+        return ld_win(src + (size_t)(l * Q + 9 * (i / 9)) * P, nb, i % 9, idx);
     };
     const RLBM_GLOBAL float* sc = nullptr;
     RLBM_GLOBAL float* so = nullptr;
@@ -842,9 +839,8 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
     const int par = (L.parity0 + t) & 1;
     const RLBM_GLOBAL S* src = as_global(static_cast<const S*>(L.pop[par]));
     RLBM_GLOBAL S* dst = as_global(static_cast<S*>(L.pop[par ^ 1]));
-    const RLBM_GLOBAL S* bc = as_global(static_cast<const S*>(L.bcbuf));
+    const size_t P = (size_t)L.P;
     const RLBM_GLOBAL double* prm = as_global(L.prm);
-    const int nif = L.n_if;
 
     // stage the record's stored rows (species rows in slot order) and (FP32
     // storage) this node's reference scales: wave w takes stored rows w,
@@ -911,23 +907,19 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
 
     int x = 0, y = 0, z = 0;
     if (valid) { x = node % L.nx; const int r = node / L.nx; y = r % L.ny; z = r / L.ny; }
-    const int k = (nif && valid) ? as_global(L.if_index)[node] : -1;
+    const int k = (L.n_if && valid) ? as_global(L.if_index)[node] : -1;
     const bool wave_if = __builtin_amdgcn_ballot_w64(k >= 0) != 0;   // uniform
     PullOff o;
     pull_offsets(L, x, y, z, o);
     const int offz = node + sel3(c2, o.z[0], 0, o.z[2]);
 
     // populations of velocity i at node offset off (after advection and
-    // boundary reconstruction)
+    // boundary reconstruction: an interface lane reads the plane's interface
+    // slot N + k)
     auto load = [&](int i, int off, S* out) {
-        if (!wave_if) {
+        const int idx = wave_if && k >= 0 ? N + k : off;
 #pragma unroll
-            for (int l = 0; l < NL; ++l) out[l] = ld_at(src + (size_t)(l * Q + i) * L.N, off);
-        } else {
-#pragma unroll
-            for (int l = 0; l < NL; ++l)
-                out[l] = k >= 0 ? bc[(size_t)(l * Q + i) * nif + k] : src[(size_t)(l * Q + i) * L.N + off];
-        }
+        for (int l = 0; l < NL; ++l) out[l] = ld_at(src + (size_t)(l * Q + i) * P, idx);
     };
     // FP32 deviation storage: reference scales of this node (decode) and of
     // the node that reads what is written for velocity (c0, c1, c2) (encode)
@@ -1093,8 +1085,8 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
                 if constexpr (sizeof(S) == 4) f += ref_of(ssc[j][lane], ref[li]);
                 const double out = f + 2.0 * be * (ra * Wj - f) + (be - 1.0) * (fcm * ra * F) + Wj * dr;
                 if constexpr (sizeof(S) == 4)
-                    st_at(dst + (size_t)li * L.N, node, __double2float_rn(out - ref_of(srd[j], ref[li])));
-                else st_at(dst + (size_t)li * L.N, node, out);
+                    st_at(dst + (size_t)li * P, node, __double2float_rn(out - ref_of(srd[j], ref[li])));
+                else st_at(dst + (size_t)li * P, node, out);
             }
             const double rho = sp[PRM_RHO][lane], th = sp[PRM_TH][lane], omega = sp[PRM_OMEGA][lane];
             // momentum lattice, extended equilibrium (eqs. f, feqmix, Pex)
@@ -1105,8 +1097,8 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
                 const double fe = rho * psi_c<c0>(ux, th + ux * ux + exf * sp[GR][lane]) * Fyz;
                 const double out = f + omega * (fe - f);
                 if constexpr (sizeof(S) == 4)
-                    st_at(dst + (size_t)li * L.N, node, __double2float_rn(out - ref_of(srd[LF], ref[li])));
-                else st_at(dst + (size_t)li * L.N, node, out);
+                    st_at(dst + (size_t)li * P, node, __double2float_rn(out - ref_of(srd[LF], ref[li])));
+                else st_at(dst + (size_t)li * P, node, out);
             }
             // energy lattice (eqs. g, geq_i, gstar)
             {
@@ -1142,9 +1134,9 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict
                     }
                 }
                 if constexpr (sizeof(S) == 4)
-                    st_at(dst + (size_t)li * L.N, node,
+                    st_at(dst + (size_t)li * P, node,
                           __double2float_rn(out - ref_g(srd[LG], srd[LF], ref[li], ref[REF_K<NL> + i])));
-                else st_at(dst + (size_t)li * L.N, node, out);
+                else st_at(dst + (size_t)li * P, node, out);
             }
 #pragma unroll
             for (int l = 0; l < NL; ++l) fin[l] = fnx[l];
@@ -1355,9 +1347,11 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
     MechC mc0 = *as_const(L.mech);
     const int par = (L.parity0 + t) & 1;
     const RLBM_GLOBAL S* src = as_global(static_cast<const S*>(L.pop[par]));
-    RLBM_GLOBAL S* bc = as_global(static_cast<S*>(L.bcbuf));
+    // the output: interface slot N + k of every plane of the same buffer,
+    // disjoint from the node slots the pull reads
+    RLBM_GLOBAL S* bc = as_global(static_cast<S*>(L.pop[par])) + L.N;
     const size_t N = (size_t)L.N;
-    const int nif = L.n_if;
+    const size_t P = (size_t)L.P;
     const int node = L.if_node[kk];
     const unsigned Dm = L.if_mask[kk];
     const int type = L.if_type[kk];
@@ -1392,14 +1386,14 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
         const int off = node + sel3(c0, o.x[0], 0, o.x[2]) + sel3(c1, o.y[0], 0, o.y[2]) + sel3(c2, o.z[0], 0, o.z[2]);
         double v;
         if (bb && ((Dm >> i) & 1u)) {
-            v = (double)ld_at(src + (size_t)(l * Q + io) * N, node);
+            v = (double)ld_at(src + (size_t)(l * Q + io) * P, node);
             if constexpr (sizeof(S) == 4) {
                 const RLBM_GLOBAL float* sc = scale_at(L, par, off);
                 const float sb = sc[l], sfb = sc[LF];
                 v += l == LG ? ref_g(sb, sfb, G[l * Q + io], G[REF_K<NL> + io]) : ref_of(sb, G[l * Q + io]);
             }
         } else {
-            v = (double)ld_at(src + (size_t)(l * Q + i) * N, off);
+            v = (double)ld_at(src + (size_t)(l * Q + i) * P, off);
             if constexpr (sizeof(S) == 4)
                 v += l == LG ? ref_g(sl, sf, G[l * Q + i], G[REF_K<NL> + i]) : ref_of(sl, G[l * Q + i]);
         }
@@ -1421,7 +1415,7 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
     auto put = [&](auto ic, double v) {
         constexpr int i = decltype(ic)::value;
         if (!live) return;
-        RLBM_GLOBAL S* pl = bc + (size_t)(l * Q + i) * nif;
+        RLBM_GLOBAL S* pl = bc + (size_t)(l * Q + i) * P;
         if constexpr (sizeof(S) == 4) {
             const double ref = l == LG ? ref_g(sl, sf, G[l * Q + i], G[REF_K<NL> + i]) : ref_of(sl, G[l * Q + i]);
             st_at(pl, k, __double2float_rn(v - ref));
@@ -1451,8 +1445,8 @@ __global__ __launch_bounds__((bc_threads<M, W>())) void k_boundary(
             const int off = node + sel3(c0, o.x[0], 0, o.x[2]) + sel3(c1, o.y[0], 0, o.y[2]) +
                             sel3(c2, o.z[0], 0, o.z[2]);
             const bool in = (Dm >> i) & 1u;
-            const RLBM_GLOBAL S* pi = src + (size_t)(l * Q + i) * N;
-            const RLBM_GLOBAL S* pio = src + (size_t)(l * Q + io) * N;
+            const RLBM_GLOBAL S* pi = src + (size_t)(l * Q + i) * P;
+            const RLBM_GLOBAL S* pio = src + (size_t)(l * Q + io) * P;
             raw[i] = ld_at(tms && in ? pio : pi, in ? node : off);
             if constexpr (sizeof(S) == 4) {
                 sbv[i] = 0.0f;
@@ -1760,7 +1754,7 @@ __global__ __launch_bounds__(256) void k_init(const LatDev* __restrict__ lat, co
     for (int l = 0; l < Lat<M, W>::NL; ++l)
         for (int i = 0; i < Q; ++i) {
             const int li = l * Q + i;
-            Codec<S>::st(dst, (size_t)li * N + node, eq_value<M, W, false>(mc, e, l, L.slaved, i),
+            Codec<S>::st(dst, (size_t)li * L.P + node, eq_value<M, W, false>(mc, e, l, L.slaved, i),
                          slot_ref<M, S, W>(L, L.parity0, node, l, i));
         }
     double* aux = L.aux;
@@ -1848,9 +1842,9 @@ __global__ __launch_bounds__(256) void k_fields(const LatDev* __restrict__ lat, 
     const int s = W ? M : L.slaved;
     double rho = 0.0, j[3] = {0.0, 0.0, 0.0}, rE = 0.0, ra[M];
     for (int i = 0; i < Q; ++i) {
-        const double f = Codec<S>::ld(src, (size_t)(LF * Q + i) * N + node, slot_ref<M, S, W>(L, q, node, LF, i));
+        const double f = Codec<S>::ld(src, (size_t)(LF * Q + i) * L.P + node, slot_ref<M, S, W>(L, q, node, LF, i));
         rho += f; j[0] += f * cx_of(i); j[1] += f * cy_of(i); j[2] += f * cz_of(i);
-        rE += Codec<S>::ld(src, (size_t)(LG * Q + i) * N + node, slot_ref<M, S, W>(L, q, node, LG, i));
+        rE += Codec<S>::ld(src, (size_t)(LG * Q + i) * L.P + node, slot_ref<M, S, W>(L, q, node, LG, i));
     }
     double rs = rho;
 #pragma unroll
@@ -1859,7 +1853,7 @@ __global__ __launch_bounds__(256) void k_fields(const LatDev* __restrict__ lat, 
         if (a == s) continue;
         const int l = lat_of(a, s);
         for (int i = 0; i < Q; ++i)
-            ra[a] += Codec<S>::ld(src, (size_t)(l * Q + i) * N + node, slot_ref<M, S, W>(L, q, node, l, i));
+            ra[a] += Codec<S>::ld(src, (size_t)(l * Q + i) * L.P + node, slot_ref<M, S, W>(L, q, node, l, i));
         rs -= ra[a];
     }
 #pragma unroll
@@ -1898,14 +1892,15 @@ __global__ __launch_bounds__(256) void k_pops(const LatDev* __restrict__ lat, lo
     const size_t total = (size_t)nl * Q * L.N;
     const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;
-    const size_t gidx = (size_t)l0 * Q * L.N + idx;
+    const size_t gidx = (size_t)l0 * Q * L.N + idx;   // in the packed [L][27][N] order
     const int li = (int)(gidx / L.N);
     const long long node = (long long)(gidx % L.N);
+    const size_t pidx = (size_t)li * L.P + node;      // in the buffer's planes
     const int q = (L.parity0 + t) & 1;
     void* p = L.pop[q];
     const double ref = slot_ref<M, S, W>(L, q, node, li / Q, li % Q);
-    if (write) Codec<S>::st(p, gidx, buf[idx], ref);
-    else buf[idx] = Codec<S>::ld(p, gidx, ref);
+    if (write) Codec<S>::st(p, pidx, buf[idx], ref);
+    else buf[idx] = Codec<S>::ld(p, pidx, ref);
 }
 
 // Per-block partial sums of the invariants; nv = 6 + E values per block.
@@ -1927,8 +1922,8 @@ __global__ __launch_bounds__(256) void k_invariants(const LatDev* __restrict__ l
         double rho = 0.0;
         for (int i = 0; i < Q; ++i) {
             const double f =
-                Codec<S>::ld(src, (size_t)(LF * Q + i) * N + node, slot_ref<M, S, W>(L, q, node, LF, i));
-            const double g = Codec<S>::ld(src, (size_t)(LG * Q + i) * N + node, slot_ref<M, S, W>(L, q, node, LG, i));
+                Codec<S>::ld(src, (size_t)(LF * Q + i) * L.P + node, slot_ref<M, S, W>(L, q, node, LF, i));
+            const double g = Codec<S>::ld(src, (size_t)(LG * Q + i) * L.P + node, slot_ref<M, S, W>(L, q, node, LG, i));
             if (!isfinite(f) || !isfinite(g)) bad = 1.0;
             rho += f;
             v[1] += f * cx_of(i); v[2] += f * cy_of(i); v[3] += f * cz_of(i);
@@ -1943,7 +1938,7 @@ __global__ __launch_bounds__(256) void k_invariants(const LatDev* __restrict__ l
             if (a == s) continue;
             const int l = lat_of(a, s);
             for (int i = 0; i < Q; ++i) {
-                const double f = Codec<S>::ld(src, (size_t)(l * Q + i) * N + node, slot_ref<M, S, W>(L, q, node, l, i));
+                const double f = Codec<S>::ld(src, (size_t)(l * Q + i) * L.P + node, slot_ref<M, S, W>(L, q, node, l, i));
                 if (!isfinite(f)) bad = 1.0;
                 ra[a] += f;
             }

@@ -62,7 +62,10 @@ struct LatDev {
     long long N;
     int n_if, n_out;
     const MechDev* mech;
-    void* pop[2];               // ping-pong population buffers [L][27][N]
+    long long P;                // population plane stride: N nodes, then the n_if interface slots, rounded up to 64
+    void* pop[2];               // ping-pong population buffers [L][27][P]; slot N + k of a plane in the buffer a
+                                // step reads holds interface node k's post-boundary population (written by the
+                                // boundary kernel of that step)
     double* aux;                // [14 + M][N]: rho, ux, uy, uz, T, Phi_x,y,z, Y_0..Y_{M-1}, P_0..P_5
     double* prm;                // [14 + 6 M + 6][N] per-node record for k_update
     const int* if_index;        // [N]: interface slot or -1 (NULL if n_if == 0)
@@ -71,7 +74,6 @@ struct LatDev {
     const int* if_type;         // [n_if] RLBM_FACE_WALL / INLET / OUTLET
     const double* if_T;         // [n_if] wall target temperature
     const int* if_out;          // [n_if] outlet slot or -1
-    void* bcbuf;                // [L * 27][n_if] post-boundary populations (storage format)
     double* out_state;          // [5 + M][n_out]: rho, ux, uy, uz, T, Y
     const double* ref;          // [L * 27] reference shapes G_li, then [L] sum_i G_li, then sum_i G_fi c_ix^2 (FP32 storage)
     float* rscale[2];           // [N][rss] reference scales s_l of the populations in pop[q] (FP32 storage)

@@ -42,7 +42,7 @@ constexpr int NPHASE = 4;   // boundary, moments + diffusion, chemistry + gradie
 
 struct Plan {
     size_t off_lat, off_mech, off_blk, off_flag, off_ref, off_pop0, off_pop1, off_aux, off_prm, off_ifindex, off_ifnode,
-        off_ifmask, off_iftype, off_ifT, off_ifout, off_bcbuf, off_out, off_partial, off_invout, off_slot,
+        off_ifmask, off_iftype, off_ifT, off_ifout, off_out, off_partial, off_invout, off_slot,
         off_rscale0, off_rscale1, total;
 };
 
@@ -190,6 +190,21 @@ void build_geometry(const rlbm_lattice_desc* d, Geometry& g) {
 // storage, plus f and g.
 int stored_lattices(const rlbm_lattice_desc* d, int M) { return d->slaved == RLBM_SLAVED_NONE ? M + 2 : M + 1; }
 
+// Population plane stride: the nodes, then one slot per interface node for its
+// post-boundary population, rounded up to 64 entries.
+size_t plane_stride(const Geometry& g) {
+    const size_t nif = g.if_node.size();
+    return nif ? ((size_t)g.N + nif + 63) / 64 * 64 : (size_t)g.N;
+}
+
+// Kernels address nine population planes with 32-bit byte offsets.
+int check_planes(const rlbm_lattice_desc* d, const Geometry& g) {
+    const size_t s_bytes = d->storage == RLBM_STORAGE_F32_DEV ? 4 : 8;
+    if (9 * s_bytes * plane_stride(g) >= (1ull << 32))
+        return fail(RLBM_EUNSUP, "too many nodes: 9 (N + interface nodes) sizeof(storage) must stay below 2^32");
+    return RLBM_OK;
+}
+
 Plan make_plan(const rlbm_lattice_desc* d, int M, int E, const Geometry& g) {
     Plan p{};
     const int L = stored_lattices(d, M);
@@ -205,8 +220,9 @@ Plan make_plan(const rlbm_lattice_desc* d, int M, int E, const Geometry& g) {
     p.off_flag = take(sizeof(int));
     p.off_ref = take(((size_t)L * Q + L + Q + 2) * sizeof(double));
     p.off_slot = take((size_t)(M + M * M) * sizeof(double));
-    p.off_pop0 = take((size_t)L * Q * N * s);
-    p.off_pop1 = take((size_t)L * Q * N * s);
+    const size_t P = plane_stride(g);
+    p.off_pop0 = take((size_t)L * Q * P * s);
+    p.off_pop1 = take((size_t)L * Q * P * s);
     p.off_aux = take((size_t)(AUX_Y + M + 6) * N * sizeof(double));
     p.off_prm = take((size_t)prm_rows(M) * N * sizeof(double));
     p.off_ifindex = take(nif ? N * sizeof(int) : 0);
@@ -215,7 +231,6 @@ Plan make_plan(const rlbm_lattice_desc* d, int M, int E, const Geometry& g) {
     p.off_iftype = take(nif * sizeof(int));
     p.off_ifT = take(nif * sizeof(double));
     p.off_ifout = take(nif * sizeof(int));
-    p.off_bcbuf = take((size_t)L * Q * nif * sizeof(double));
     p.off_out = take((size_t)(5 + M) * g.n_out * sizeof(double));
     p.off_partial = take(nblocks * (6 + E) * sizeof(double));
     p.off_invout = take((6 + E) * sizeof(double));
@@ -372,6 +387,8 @@ int rlbm_lattice_bytes(const rlbm_lattice_desc* d, const rlbm_mech* mech, size_t
     if (rc) return rc;
     Geometry g;
     build_geometry(d, g);
+    const int rp = check_planes(d, g);
+    if (rp) return rp;
     *bytes = make_plan(d, mech->dev.M, mech->dev.E, g).total;
     return RLBM_OK;
 }
@@ -394,6 +411,11 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     lat->storage = d->storage;
     lat->stream = (hipStream_t)stream;
     build_geometry(d, lat->geo);
+    rc = check_planes(d, lat->geo);
+    if (rc) {
+        delete lat;
+        return rc;
+    }
     lat->plan = make_plan(d, M, lat->E, lat->geo);
     if (bytes < lat->plan.total) {
         delete lat;
@@ -419,6 +441,7 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     h.storage = d->storage;
     h.reaction = d->reaction;
     h.N = g.N;
+    h.P = (long long)plane_stride(g);
     h.n_if = (int)nif;
     h.n_out = g.n_out;
     h.mech = (const MechDev*)(base + p.off_mech);
@@ -433,7 +456,6 @@ int rlbm_lattice_create(const rlbm_lattice_desc* d, const rlbm_mech* mech, void*
     h.if_type = (const int*)(base + p.off_iftype);
     h.if_T = (const double*)(base + p.off_ifT);
     h.if_out = (const int*)(base + p.off_ifout);
-    h.bcbuf = base + p.off_bcbuf;
     h.out_state = (double*)(base + p.off_out);
     h.ref = d->storage == RLBM_STORAGE_F32_DEV ? (const double*)(base + p.off_ref) : nullptr;
     h.rss = d->storage == RLBM_STORAGE_F32_DEV ? (lat->L + 3) / 4 * 4 : 0;
@@ -749,7 +771,7 @@ StateLayout state_layout(const rlbm_lattice* lat) {
     const size_t N = (size_t)lat->geo.N, L = (size_t)lat->L, M = (size_t)lat->M;
     const bool f32 = lat->storage == RLBM_STORAGE_F32_DEV;
     s.n_ref = f32 ? (L * Q + L + Q + 2) * sizeof(double) : 0;
-    s.n_pops = L * Q * N * (f32 ? 4 : 8);
+    s.n_pops = L * Q * (size_t)lat->host.P * (f32 ? 4 : 8);
     s.n_scale = f32 ? (size_t)lat->host.rss * N * sizeof(float) : 0;
     s.n_aux = ((size_t)AUX_Y + M + 6) * N * sizeof(double);
     s.n_out = (5 + M) * (size_t)lat->geo.n_out * sizeof(double);

@@ -814,8 +814,10 @@ __device__ __forceinline__ void geq_wk(int c, double u, double th, double& W, do
 }
 
 
+// The weakly coupled storage's extra lattice would otherwise take the
+// kernel just past three waves per SIMD (the LDS allows three).
 template <int M, typename S, int W>
-__global__ __launch_bounds__(UPD_THREADS) void k_update(const LatDev* __restrict__ lats, const int* __restrict__ blk,
+__global__ __launch_bounds__(UPD_THREADS) __attribute__((amdgpu_waves_per_eu(W ? 3 : 1))) void k_update(const LatDev* __restrict__ lats, const int* __restrict__ blk,
                                                         int n_lat, const long long* __restrict__ tp, long long toff) {
     const long long t = step_time(tp, toff);
     constexpr int NR = prm_rows(M);

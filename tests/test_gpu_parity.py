@@ -103,6 +103,35 @@ def test_closed_box_corners_parity(wall_type, storage):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32dev"])
+@pytest.mark.parametrize("wall_type", ["wall", "bounceback"])
+@pytest.mark.parametrize("species", [2, 4])
+def test_closed_box_other_species_counts(species, wall_type, storage):
+    """The boundary kernels compiled for two and four species (their LDS
+    holds every lattice in both storages) in boxes closed on all six faces,
+    against the oracle."""
+    print(f"case closed box 10x8x6 M={species} {wall_type} {storage}", flush=True)
+    if species == 2:
+        case = wl.make_case("binary", nx=10, ny=8, nz=6, amp=1e-2)
+        T_w = 300.0
+    else:
+        case = wl.make_case("abc_box", nx=10, ny=8, nz=6, mech=wl.mechanism_abcd())
+        T_w = 1000.0
+    if wall_type == "wall":
+        face = {"type": "wall", "T_lo": T_w, "T_hi": T_w, "x0": 0.0, "width": 1.0}
+    else:
+        face = {"type": "bounceback"}
+    case["faces"] = [dict(face) for _ in range(6)]
+    lat, ora, out = _run_pair(case, [1, 20], storage=storage)
+    for gp, op, gf, of in out:
+        if storage == "f64":
+            _compare_pops(gp, op, TOL64)
+            _compare_fields(gf, of, TOL64, _u_floor(case))
+        else:
+            assert _nerr(gf["T"], of["T"]) <= TOL32
+            assert max(_nerr(gf["Y"][a], of["Y"][a], 1e-6) for a in range(species)) <= TOL32
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32dev"])
 def test_bounce_back_channel_with_inlet_and_outlet_parity(mech9, storage):
     """A 2D channel whose y walls are bounce-back walls, with the flux inlet
     and the LODI outlet: the bounce-back kernel path beside inlet and outlet

@@ -81,12 +81,13 @@ def test_abc_box_parity(storage):
 
 @pytest.mark.parametrize("storage", ["f64", "f32dev"])
 @pytest.mark.parametrize("wall_type", ["wall", "bounceback"])
-def test_closed_box_corners_parity(wall_type, storage):
+@pytest.mark.parametrize("coupling", ["strong", "weak"])
+def test_closed_box_corners_parity(coupling, wall_type, storage):
     """A box closed by walls on all six faces (edges on two walls, corners
-    on three, with 15 and 19 incoming links), TMS or bounce-back, against
-    the oracle."""
-    print(f"case closed box 10x8x6 M=3 {wall_type} {storage}", flush=True)
-    case = wl.make_case("abc_box", nx=10, ny=8, nz=6, mech=wl.mechanism_abc())
+    on three, with 15 and 19 incoming links), TMS or bounce-back, with a
+    slaved species or the weakly coupled storage, against the oracle."""
+    print(f"case closed box 10x8x6 M=3 {coupling} {wall_type} {storage}", flush=True)
+    case = wl.make_case("abc_box", nx=10, ny=8, nz=6, mech=wl.mechanism_abc(), coupling=coupling)
     if wall_type == "wall":
         face = {"type": "wall", "T_lo": 1000.0, "T_hi": 1000.0, "x0": 0.0, "width": 1.0}
     else:

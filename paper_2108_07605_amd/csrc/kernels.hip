@@ -1211,7 +1211,9 @@ __device__ __forceinline__ double eq_value(MechC mc, const EqState<M, SPV>& e, i
 // populations once, in one pass with all 27 loads in flight, and keeps them
 // in LDS for the moments and the reconstruction (the pull reads of the
 // interface list are scattered over the lattice, so a second pass over them
-// costs as much as the first).  The node's state goes between the waves
+// costs as much as the first); lattices beyond what the LDS holds beside the
+// node states read them again per pass.  The output goes to the interface
+// slots N + k of the planes of the buffer the step reads.  The node's state goes between the waves
 // through LDS: the lattices' moments, and the imposed and local states that
 // the first wave forms from them (temperature by the bounded Newton
 // iteration, the LODI outlet state).  All barriers are at the top level of

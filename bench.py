@@ -25,10 +25,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_update_channel3d_512x64x64_traf
 
 
 def _kernel_hash():
-    """Hash of the kernel sources' code: // comments and blank lines are
-    dropped, so commentary edits keep the recorded counters valid."""
+    """Hash of the kernel sources' code (the kernels, the physics and the
+    launch shapes): // comments and blank lines are dropped, so commentary
+    edits keep the recorded counters valid."""
     h = hashlib.sha256()
-    for f in ("physics.hpp", "kernels.hip"):
+    for f in ("physics.hpp", "launch.hpp", "kernels.hip"):
         with open(os.path.join(ROOT, "paper_2108_07605_amd", "csrc", f)) as fh:
             lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in fh.read().splitlines())
             h.update("\n".join(ln for ln in lines if ln).encode())

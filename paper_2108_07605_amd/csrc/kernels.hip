@@ -384,6 +384,15 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
         so = as_global(L.rscale[par ^ 1]) + (size_t)node * L.rss;
     }
 
+    // the first species lattice's loads go out with the momentum and energy
+    // lattices' (FP32 storage), so its sum does not wait for a round trip of
+    // its own
+    constexpr bool PF = sizeof(S) == 4;
+    S cur[Q];
+    if constexpr (PF) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) cur[i] = ld(0, i);
+    }
     // momentum and energy lattices
     double rho = 0.0, rhoE = 0.0, j[3] = {0.0, 0.0, 0.0}, q[3] = {0.0, 0.0, 0.0};
     double Pd[3] = {0.0, 0.0, 0.0}, Po[3] = {0.0, 0.0, 0.0};
@@ -427,14 +436,8 @@ __device__ __forceinline__ void local_moments(const LatDev& L, int par, int k, i
         ls.dv[(3 * a + 1) * LOC_T] = small ? 0.0 : jy * inv - u[1];
         ls.dv[(3 * a + 2) * LOC_T] = small ? 0.0 : jz * inv - u[2];
     };
-    // FP32 storage double-buffers the species loads; FP64 has no registers
-    // to spare for it
-    constexpr bool PF = sizeof(S) == 4;
-    S cur[Q];
-    if constexpr (PF) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) cur[i] = ld(0, i);
-    }
+    // FP32 storage double-buffers the species loads (the first lattice's
+    // were issued above); FP64 has no registers to spare for it
 #pragma unroll 1
     for (int l = 0; l < NSP; ++l) {
         reload_barrier();

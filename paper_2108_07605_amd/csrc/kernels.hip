@@ -635,13 +635,25 @@ __global__ __launch_bounds__(NODE_TILE) __attribute__((amdgpu_waves_per_eu(2, 2)
 // nearest node.  Writes rows PRM_GRAD..PRM_GRAD+5 of the per-node record.
 // ---------------------------------------------------------------------------
 template <int M>
+__device__ __forceinline__ void store_gradients(const LatDev& L, int node, const double (&acc)[6]) {
+    const size_t N = (size_t)L.N;
+    if (L.storage == RLBM_STORAGE_F32_DEV) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) st_corr<true>(as_global(L.prm), prm_grad(M) + q, N, node, acc[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) st_corr<false>(as_global(L.prm), prm_grad(M) + q, N, node, acc[q]);
+    }
+}
+
+// Any node: the 26 neighbours' fields, each at its own offset.
+template <int M>
 __device__ __forceinline__ void node_gradients(const LatDev& L, int node) {
     const int nx = L.nx, ny = L.ny, nz = L.nz;
     const int x = node % nx, r = node / nx, y = r % ny, z = r / ny;
     const size_t N = (size_t)L.N;
     const double* aux = L.aux;
-    double* prm = L.prm;
-    const double T = prm[PRM_T * N + node];
+    const double T = L.prm[PRM_T * N + node];
     const double T2 = T * T, T3 = T2 * T, T4 = T3 * T, T5 = T4 * T;
     const bool px = L.per[0], py = L.per[1], pz = L.per[2];
     const int gx[3] = {x == 0 ? (px ? nx - 1 : 0) : x - 1, x, x == nx - 1 ? (px ? 0 : x) : x + 1};
@@ -667,13 +679,115 @@ __device__ __forceinline__ void node_gradients(const LatDev& L, int node) {
             if (cz) { acc[2] += (cz * w) * aux[(AUX_PHI + 2) * N + nb]; acc[5] += (cz * w) * hy; }
         }
     }
-    if (L.storage == RLBM_STORAGE_F32_DEV) {
+    store_gradients<M>(L, node, acc);
+}
+
+// The weights factor per direction, w_i = w(c_ix) w(c_iy) w(c_iz) with
+// w(0) = 2/3 and w(+-1) = 1/6.  With the sums over the 3x3 (y, z)
+// neighbourhood of one column x
+//   A(x) = sum w(cy) w(cz) phi,  B(x) = sum cy w(cz) phi,  C(x) = sum cz w(cy) phi
+// the stencil is
+//   d_x phi = (A(x+1) - A(x-1)) / 2,  d_y phi = sum_cx w(cx) B(x+cx) / 2,
+//   d_z phi = sum_cx w(cx) C(x+cx) / 2.
+// Column sums of one x: the six enthalpy coefficients (A, B, C each) and
+// A of Phi_x, B of Phi_y, C of Phi_z.
+struct ColSums {
+    double a[6], b[6], c[6];
+    double ax, by, cz;
+};
+template <int M>
+__device__ __forceinline__ void column_sums(const LatDev& L, int xc, const int (&gy)[3], const int (&gz)[3],
+                                            ColSums& o) {
+    const size_t N = (size_t)L.N;
+    const int nx = L.nx, ny = L.ny;
+    const double* aux = L.aux;
+    const double* Pk = aux + (size_t)(AUX_Y + M) * N;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) st_corr<true>(as_global(prm), prm_grad(M) + q, N, node, acc[q]);
-    } else {
+    for (int k = 0; k < 6; ++k) o.a[k] = o.b[k] = o.c[k] = 0.0;
+    o.ax = o.by = o.cz = 0.0;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) st_corr<false>(as_global(prm), prm_grad(M) + q, N, node, acc[q]);
+    for (int j = 0; j < 9; ++j) {
+        const int cy = j % 3 - 1, cz = j / 3 - 1;
+        const double wy = cy ? 1.0 / 6.0 : 2.0 / 3.0, wz = cz ? 1.0 / 6.0 : 2.0 / 3.0;
+        const size_t nb = ((size_t)gz[cz + 1] * ny + gy[cy + 1]) * nx + xc;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double f = Pk[k * N + nb];
+            o.a[k] += (wy * wz) * f;
+            if (cy) o.b[k] += (cy * wz) * f;
+            if (cz) o.c[k] += (cz * wy) * f;
+        }
+        o.ax += (wy * wz) * aux[(AUX_PHI + 0) * N + nb];
+        if (cy) o.by += (cy * wz) * aux[(AUX_PHI + 1) * N + nb];
+        if (cz) o.cz += (cz * wy) * aux[(AUX_PHI + 2) * N + nb];
     }
+}
+
+__device__ __forceinline__ double poly5(double t, const double (&v)[6]) {
+    return v[0] + t * (v[1] + t * (v[2] + t * (v[3] + t * (v[4] + t * v[5]))));
+}
+
+// A wave whose 64 lanes are the consecutive nodes x0..x0+63 of one x-row
+// (lane = x - x0): each lane loads its own column's 9 (y, z) neighbours and
+// takes the column sums of x-1 and x+1 from the adjacent lanes; lane 0 and
+// lane 63 load the ghost-aware column beyond the tile themselves.  The sum
+// of H_b Y_b at this node's temperature is formed from the neighbour's
+// coefficient sums, so a lane evaluates its sums at the temperature of the
+// lane that receives them (the adjacent lane's T).  Every lane of the wave
+// must reach this function.
+template <int M>
+__device__ __forceinline__ void row_tile_gradients(const LatDev& L, int node, int lane) {
+    const int nx = L.nx, ny = L.ny, nz = L.nz;
+    const int x = node % nx, r = node / nx, y = r % ny, z = r / ny;
+    const size_t N = (size_t)L.N;
+    const double T = L.prm[PRM_T * N + node];
+    const bool px = L.per[0], py = L.per[1], pz = L.per[2];
+    const int gy[3] = {y == 0 ? (py ? ny - 1 : 0) : y - 1, y, y == ny - 1 ? (py ? 0 : y) : y + 1};
+    const int gz[3] = {z == 0 ? (pz ? nz - 1 : 0) : z - 1, z, z == nz - 1 ? (pz ? 0 : z) : z + 1};
+    // the adjacent lanes' temperatures (lane 0 and lane 63 keep their own;
+    // what they would send across the tile edge is not used)
+    const double Tl = __shfl_up(T, 1u), Tr = __shfl_down(T, 1u);
+    // from x+1 (sums at this lane's T), from x-1, and this column's own
+    double hp_a, hp_b, hp_c, hm_a, hm_b, hm_c, h0_b, h0_c, fp_ax, fp_by, fp_cz, fm_ax, fm_by, fm_cz, f0_by, f0_cz;
+    {
+        ColSums s;
+        column_sums<M>(L, x, gy, gz, s);
+        h0_b = poly5(T, s.b);
+        h0_c = poly5(T, s.c);
+        f0_by = s.by;
+        f0_cz = s.cz;
+        hp_a = __shfl_down(poly5(Tl, s.a), 1u);
+        hp_b = __shfl_down(poly5(Tl, s.b), 1u);
+        hp_c = __shfl_down(poly5(Tl, s.c), 1u);
+        hm_a = __shfl_up(poly5(Tr, s.a), 1u);
+        hm_b = __shfl_up(poly5(Tr, s.b), 1u);
+        hm_c = __shfl_up(poly5(Tr, s.c), 1u);
+        fp_ax = __shfl_down(s.ax, 1u);
+        fp_by = __shfl_down(s.by, 1u);
+        fp_cz = __shfl_down(s.cz, 1u);
+        fm_ax = __shfl_up(s.ax, 1u);
+        fm_by = __shfl_up(s.by, 1u);
+        fm_cz = __shfl_up(s.cz, 1u);
+    }
+    if (lane == 0 || lane == NODE_TILE - 1) {
+        const int xg = lane == 0 ? (x == 0 ? (px ? nx - 1 : 0) : x - 1) : (x == nx - 1 ? (px ? 0 : x) : x + 1);
+        ColSums s;
+        column_sums<M>(L, xg, gy, gz, s);
+        const double ga = poly5(T, s.a), gb = poly5(T, s.b), gc = poly5(T, s.c);
+        if (lane == 0) {
+            hm_a = ga; hm_b = gb; hm_c = gc; fm_ax = s.ax; fm_by = s.by; fm_cz = s.cz;
+        } else {
+            hp_a = ga; hp_b = gb; hp_c = gc; fp_ax = s.ax; fp_by = s.by; fp_cz = s.cz;
+        }
+    }
+    constexpr double w0 = 2.0 / 3.0, w1 = 1.0 / 6.0;
+    const double acc[6] = {0.5 * (fp_ax - fm_ax),
+                           0.5 * (w1 * fm_by + w0 * f0_by + w1 * fp_by),
+                           0.5 * (w1 * fm_cz + w0 * f0_cz + w1 * fp_cz),
+                           0.5 * (hp_a - hm_a),
+                           0.5 * (w1 * hm_b + w0 * h0_b + w1 * hp_b),
+                           0.5 * (w1 * hm_c + w0 * h0_c + w1 * hp_c)};
+    store_gradients<M>(L, node, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -731,7 +845,12 @@ __device__ __forceinline__ void chem_body(const LatDev* __restrict__ lats, const
                 st_corr<false>(as_global(prm), PRM_SP + 6 * a + 5, N, node, fin[a] - prm[(PRM_SP + 6 * a) * N + node]);
         }
     }
-    node_gradients<M>(L, node);
+    // wave-uniform: the tile's 64 nodes lie in one x-row
+    const int x0 = __builtin_amdgcn_readfirstlane((node - tid) % L.nx);
+    if (x0 + NODE_TILE <= L.nx)
+        row_tile_gradients<M>(L, node, tid);
+    else
+        node_gradients<M>(L, node);
 }
 
 // GRAD_TILES tiles per block, one wave each (the stencil shares nothing

@@ -179,6 +179,9 @@ def test_abc_box_initial_state_exact():
     ("reactor", dict(nx=3, ny=3, nz=2, T0=1500.0, X_radical=0.01, reaction="implicit", coupling="weak"), [1, 30]),
     ("channel2d", dict(nx=40, ny=10, nz=1, inlet="inlet_local", coupling="weak", substeps=3), [1, 20]),
     ("channel3d", dict(nx=256, ny=4, nz=3, perturb=0.5), [1, 6]),    # full 256-node blocks
+    # rows of 80 nodes: some 64-node tiles lie in one row, others span two
+    ("channel3d", dict(nx=80, ny=5, nz=4, perturb=0.5), [1, 10]),
+    ("channel3d", dict(nx=80, ny=5, nz=4, perturb=0.5, coupling="weak"), [1, 10]),
 ])
 def test_nine_species_parity(mech9, name, kw, steps):
     print(f"case {name} {kw} M=9 f64", flush=True)

@@ -309,14 +309,19 @@ def test_f32_deviation_storage_vs_oracle():
     assert max(ey) <= TOL32 and et <= TOL32
 
 
-def test_f32_deviation_channel_vs_oracle(mech9):
-    print("case channel2d 48x12 f32dev", flush=True)
-    case = wl.make_case("channel2d", nx=48, ny=12, nz=1, mech=mech9)
-    lat, ora, out = _run_pair(case, [30], storage="f32dev")
+@pytest.mark.parametrize("name,kw,steps", [
+    ("channel2d", dict(nx=48, ny=12, nz=1), 30),
+    # rows of 80 nodes: 64-node tiles inside one row and tiles across two
+    ("channel3d", dict(nx=80, ny=5, nz=4, perturb=0.5), 10),
+])
+def test_f32_deviation_channel_vs_oracle(mech9, name, kw, steps):
+    print(f"case {name} {kw} f32dev", flush=True)
+    case = wl.make_case(name, mech=mech9, **kw)
+    lat, ora, out = _run_pair(case, [steps], storage="f32dev")
     gp, op, gf, of = out[-1]
     ey = [_nerr(gf["Y"][a], of["Y"][a], 1e-6) for a in range(of["Y"].shape[0])]
     et = _nerr(gf["T"], of["T"])
-    print(f"f32dev vs oracle, channel2d 48x12 30 steps: Y {max(ey):.3e} T {et:.3e}", flush=True)
+    print(f"f32dev vs oracle, {name} {steps} steps: Y {max(ey):.3e} T {et:.3e}", flush=True)
     assert max(ey) <= TOL32 and et <= TOL32
 
 
